@@ -1,0 +1,200 @@
+/*
+ * fgfrft.h -- C ABI of the MI355X (gfx950) FGFRFT library.
+ *
+ * FGFRFT (arXiv 2602.20870) approximates the graph fractional Fourier
+ * transform F^alpha of a unitary GFT matrix F by the L-order operator of
+ * Definition 1,
+ *
+ *     Q_L^alpha = e^{j pi alpha} P + sum_{n=-L}^{L} c_n(alpha) F^n P_c,
+ *     c_n(alpha) = sin(pi (alpha - n)) / (pi (alpha - n)),
+ *
+ * where P projects onto the eigenvalue -1 eigenspace of F and P_c = I - P
+ * (Sec. III-B).  Algorithm 1 splits the work into an offline stage (the
+ * projector and the powers M_n = F^n P_c) and an online stage (the linear
+ * combination for each new order alpha); negative powers are conjugate
+ * transposes, F^{-n} P_c = M_n^H (Proposition 2).
+ *
+ * Conventions for every call
+ *   - Matrices are dense, row-major and contiguous.  Complex values are
+ *     interleaved {re, im} pairs (the layout of complex64 / complex128).
+ *   - Pointers named *_dev are HIP device memory owned by the caller; the
+ *     library never allocates or frees device memory.  Pointers without the
+ *     suffix are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every call only enqueues work on it, except fgfrft_plan and
+ *     fgfrft_grad, which synchronise it (they read results back to the host).
+ *   - Argument errors are detected on the host before anything is enqueued
+ *     and returned synchronously; nothing is written in that case.  A HIP
+ *     launch failure returns FGFRFT_EHIP.  fgfrft_last_error() gives a
+ *     thread-local description of the most recent failure.
+ *   - A plan is read-only after fgfrft_plan returns: update, apply and grad
+ *     may run concurrently on different streams provided each call has its
+ *     own workspace.
+ */
+#ifndef FGFRFT_H
+#define FGFRFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGFRFT_API __attribute__((visibility("default")))
+
+typedef enum {
+  FGFRFT_OK = 0,
+  FGFRFT_EINVAL = -1,        /* bad size, pointer, type or workspace too small            */
+  FGFRFT_ENOTUNITARY = -2,   /* max |F^H F - I| above 1e-10                                */
+  FGFRFT_EALPHA = -3,        /* |alpha| >= L, or alpha not finite                          */
+  FGFRFT_ENOMEM = -4,        /* caller-provided buffer smaller than the stated size        */
+  FGFRFT_EHIP = -5,          /* a HIP runtime call or kernel launch failed                 */
+  FGFRFT_EDRIFT = -6,        /* FP64 power recurrence lost orthogonality (||M_n^H M_n - P_c||_F / sqrt(N) > 1e-9) */
+  FGFRFT_EUNSUPPORTED = -7   /* combination of sizes this build does not implement         */
+} fgfrft_status;
+
+/* Element type of F as handed to fgfrft_plan. */
+typedef enum {
+  FGFRFT_IN_C128 = 0,        /* complex128 F: complex power stack                          */
+  FGFRFT_IN_F64 = 1          /* float64 F (real orthogonal): real power stack, Im Q = sin(pi alpha) P */
+} fgfrft_intype;
+
+/* Storage of the resident power stack M_1..M_L. */
+typedef enum {
+  FGFRFT_STACK_FP32 = 0,     /* float32 (real F) or complex64 (complex F)                  */
+  FGFRFT_STACK_BF16X2 = 1    /* per real value a bf16 pair (hi, lo = bf16(x - hi)), 4 bytes */
+} fgfrft_stacktype;
+
+typedef struct fgfrft_plan_s* fgfrft_plan_t;
+
+/* ---------------------------------------------------------------------------
+ * Offline stage (Algorithm 1, offline part; Sec. III-G complexity)
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device memory a plan needs.  `persistent` must stay allocated for
+ * the plan's lifetime (power stack, projector, tables); `scratch` is FP64
+ * working memory used only during fgfrft_plan and free again when it returns.
+ * Limits: 1 <= N <= 32768, 1 <= L <= 64 (L <= 32 for complex F). */
+FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype,
+                                           size_t* persistent, size_t* scratch);
+
+/* Build a plan for the unitary F (N x N, row-major, device, float64 or
+ * complex128 per `intype`).  On the GPU, in FP64:
+ *   1. unitarity check max|F^H F - I| <= 1e-10, else FGFRFT_ENOTUNITARY;
+ *   2. the eigenvalue -1 eigenspace as the null space of F + I, found by
+ *      Householder QR with column pivoting of F + I; the pivoted QR stops
+ *      when every remaining column norm is <= tau (tau <= 0 selects 1e-6),
+ *      and the trailing columns of the orthogonal factor give an orthonormal
+ *      W with P = W W^H (F is normal, so null(F + I) is the complement of
+ *      the range of F + I);
+ *   3. M_0 = P_c = I - P, M_n = F M_{n-1} for n = 1..L, with the drift
+ *      ||M_n^H M_n - P_c||_F / sqrt(N) checked at n = ceil(L/2) and n = L;
+ *   4. M_1..M_L and P stored in `stacktype` format in `persistent_dev`.
+ * Synchronises `stream`.  F_dev is only read during the call.
+ * On success *out receives a host-side handle (free with fgfrft_destroy);
+ * persistent_dev must outlive it. */
+FGFRFT_API fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stacktype,
+                                     double tau, void* persistent_dev, size_t persistent_bytes,
+                                     void* scratch_dev, size_t scratch_bytes, void* stream,
+                                     fgfrft_plan_t* out);
+
+/* Facts measured while planning: rank of the -1 eigenspace, max|F^H F - I|,
+ * the larger of the two drift values, the largest remaining column norm of
+ * F + I when the pivoted QR stopped (0 if r_minus1 = 0) and the smallest
+ * column norm it pivoted on (how close the nearest non-(-1) eigenvalue is).
+ * Any pointer may be NULL. */
+FGFRFT_API fgfrft_status fgfrft_plan_info(fgfrft_plan_t plan, int* r_minus1, double* unitarity_defect,
+                                          double* drift, double* stop_norm, double* last_pivot_norm);
+
+/* Device pointers to the resident data: stack (M_1..M_L, L*N*N elements of
+ * the stack format) and P (N*N, float32 for real F, complex64 for complex F).
+ * For inspection and tests. */
+FGFRFT_API fgfrft_status fgfrft_plan_buffers(fgfrft_plan_t plan, void** stack_dev, void** P_dev);
+
+FGFRFT_API void fgfrft_destroy(fgfrft_plan_t plan);  /* frees the host handle only */
+
+/* ---------------------------------------------------------------------------
+ * Online stage: operator update (Definition 1, Proposition 2, Algorithm 1
+ * online part)
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for fgfrft_update with n_alpha orders. */
+FGFRFT_API size_t fgfrft_update_workspace_bytes(fgfrft_plan_t plan, int n_alpha);
+
+/* Q[a] = Q_L^{alphas[a]} for a = 0..n_alpha-1, written as complex64
+ * [n_alpha][N][N] to Q_dev.  `alphas` is a host array (copied before the call
+ * returns); each |alpha| < L, else FGFRFT_EALPHA.  Integer alpha goes through
+ * the same formula, which then reduces to F^alpha (Remark on integer order).
+ * The coefficients c_n(alpha), c_0, cos(pi alpha) and sin(pi alpha) are
+ * evaluated on the GPU in FP64 (a-1), then every power-stack tile is read once
+ * from HBM for all n_alpha orders and combined on the matrix cores with FP32
+ * accumulation. */
+FGFRFT_API fgfrft_status fgfrft_update(fgfrft_plan_t plan, const double* alphas, int n_alpha,
+                                       void* Q_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Apply to graph signals (Definition 2)
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for fgfrft_apply_operator (per-signal scale table). */
+FGFRFT_API size_t fgfrft_apply_operator_workspace_bytes(int N, int n_alpha, int B, int x_shared);
+
+/* Y[a] = op(Q[a]) X[a] for a = 0..n_alpha-1 with op = identity (adjoint = 0)
+ * or the conjugate transpose (adjoint = 1; by Proposition 3 this is the
+ * operator of order -alpha).  Q_dev: complex64 [n_alpha][N][N].
+ * X_dev: [n_alpha][N][B] (x_shared = 0) or one [N][B] block for every order
+ * (x_shared = 1), float32 (x_complex = 0) or complex64 (x_complex = 1).
+ * Y_dev: complex64 [n_alpha][N][B], or float32 holding only the real part
+ * when y_real = 1.  1 <= B <= 4096. */
+FGFRFT_API fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_alpha, int adjoint,
+                                               const void* X_dev, int x_complex, int x_shared, int B,
+                                               void* Y_dev, int y_real, void* ws_dev, size_t ws_bytes,
+                                               void* stream);
+
+/* Workspace bytes for fgfrft_apply: operators for `chunk` orders at a time
+ * plus the update and apply workspaces.  chunk <= 0 selects min(n_alpha, 16). */
+FGFRFT_API size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared,
+                                               int chunk);
+
+/* Y[a] = Q_L^{alphas[a]} X[a]: fgfrft_update into the workspace, `chunk`
+ * orders at a time, followed by fgfrft_apply_operator.  Same layouts as
+ * fgfrft_apply_operator with y_real = 0. */
+FGFRFT_API fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha,
+                                      const void* X_dev, int x_complex, int x_shared, int B,
+                                      void* Y_dev, int chunk, void* ws_dev, size_t ws_bytes,
+                                      void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Gradients (Proposition 4)
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for fgfrft_grad. */
+FGFRFT_API size_t fgfrft_grad_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared);
+
+/* Gradients of a real loss l through Y[a] = Q_L^{alphas[a]} X[a].
+ * GY_dev: complex64 [n_alpha][N][B] holding dl/dRe Y + j dl/dIm Y.
+ *   dalpha[a] = Re sum_{n=-L}^{L} c_n'(alpha_a) <G_a, F^n P_c>
+ *             + Re( j pi e^{j pi alpha_a} <G_a, P> ),
+ *   with G_a = GY[a] X[a]^H and <A, B> = sum_ij conj(A_ij) B_ij;
+ * dalpha is a host array of n_alpha doubles, written after the stream has
+ * been synchronised.  The inner products are formed on the GPU in FP32 with
+ * a fixed-order two-pass reduction (deterministic); the final combination
+ * with c_n'(alpha) is FP64.
+ * dX_dev (may be NULL): Q(alpha_a)^H GY[a], float32 (real part) when
+ * x_complex = 0, complex64 otherwise, shaped like X (summed over orders when
+ * x_shared = 1). */
+FGFRFT_API fgfrft_status fgfrft_grad(fgfrft_plan_t plan, const double* alphas, int n_alpha,
+                                     const void* X_dev, int x_complex, int x_shared, int B,
+                                     const void* GY_dev, double* dalpha, void* dX_dev,
+                                     void* ws_dev, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Errors
+ * ------------------------------------------------------------------------- */
+FGFRFT_API const char* fgfrft_strerror(int status);
+FGFRFT_API const char* fgfrft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGFRFT_H */

@@ -1,0 +1,237 @@
+// C ABI of the FGFRFT library: argument validation, buffer carving and dispatch.
+#include "internal.h"
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <new>
+
+namespace fgfrft {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+fgfrft_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return FGFRFT_EHIP;
+}
+
+static bool valid_sizes(int N, int L, int intype, int stacktype) {
+  if (N < 1 || N > 32768) { set_error("N=%d outside [1, 32768]", N); return false; }
+  if (L < 1 || L > 64) { set_error("L=%d outside [1, 64]", L); return false; }
+  if (intype != FGFRFT_IN_C128 && intype != FGFRFT_IN_F64) { set_error("bad intype %d", intype); return false; }
+  if (stacktype != FGFRFT_STACK_FP32 && stacktype != FGFRFT_STACK_BF16X2) { set_error("bad stacktype %d", stacktype); return false; }
+  return true;
+}
+
+static size_t stack_elem_bytes(bool cplx) { return cplx ? 8 : 4; }
+
+static fgfrft_status check_alphas(const Plan* p, const double* alphas, int n_alpha) {
+  if (!alphas || n_alpha < 1) { set_error("alphas is NULL or n_alpha=%d < 1", n_alpha); return FGFRFT_EINVAL; }
+  for (int a = 0; a < n_alpha; ++a) {
+    if (!isfinite(alphas[a]) || fabs(alphas[a]) >= (double)p->L) {
+      set_error("alphas[%d]=%g: need |alpha| < L=%d", a, alphas[a], p->L);
+      return FGFRFT_EALPHA;
+    }
+  }
+  return FGFRFT_OK;
+}
+
+}  // namespace fgfrft
+
+using namespace fgfrft;
+
+extern "C" {
+
+fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype, size_t* persistent, size_t* scratch) {
+  if (!valid_sizes(N, L, intype, stacktype)) return FGFRFT_EINVAL;
+  const bool cplx = intype == FGFRFT_IN_C128;
+  if (cplx && L > 32) { set_error("complex F supports L <= 32"); return FGFRFT_EUNSUPPORTED; }
+  const size_t NN = (size_t)N * N;
+  if (persistent) *persistent = align_up((size_t)L * NN * stack_elem_bytes(cplx), 256) + align_up(NN * (cplx ? 8 : 4), 256);
+  if (scratch) *scratch = plan_scratch_bytes(N, L, cplx);
+  return FGFRFT_OK;
+}
+
+fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stacktype, double tau, void* persistent_dev,
+                          size_t persistent_bytes, void* scratch_dev, size_t scratch_bytes, void* stream,
+                          fgfrft_plan_t* out) {
+  if (!out) { set_error("out is NULL"); return FGFRFT_EINVAL; }
+  *out = nullptr;
+  size_t need_p = 0, need_s = 0;
+  fgfrft_status rc = fgfrft_plan_bytes(N, L, intype, stacktype, &need_p, &need_s);
+  if (rc) return rc;
+  if (!F_dev || !persistent_dev || !scratch_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if (persistent_bytes < need_p) { set_error("persistent buffer %zu < %zu bytes", persistent_bytes, need_p); return FGFRFT_ENOMEM; }
+  if (scratch_bytes < need_s) { set_error("scratch buffer %zu < %zu bytes", scratch_bytes, need_s); return FGFRFT_ENOMEM; }
+  if (!(tau > 0.0)) tau = 1e-6;
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) { set_error("host allocation failed"); return FGFRFT_ENOMEM; }
+  p->N = N;
+  p->L = L;
+  p->LP = L <= 32 ? 32 : 64;
+  p->cplx = intype == FGFRFT_IN_C128;
+  p->stacktype = stacktype;
+  p->tau = tau;
+  p->stack_elem_bytes = stack_elem_bytes(p->cplx);
+  p->stack = persistent_dev;
+  p->P = (char*)persistent_dev + align_up((size_t)L * N * N * p->stack_elem_bytes, 256);
+  rc = plan_build(p, F_dev, tau, scratch_dev, scratch_bytes, (hipStream_t)stream);
+  if (rc) { delete p; return rc; }
+  *out = (fgfrft_plan_t)p;
+  return FGFRFT_OK;
+}
+
+fgfrft_status fgfrft_plan_info(fgfrft_plan_t plan, int* r_minus1, double* unitarity_defect, double* drift,
+                               double* stop_norm, double* last_pivot_norm) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  if (r_minus1) *r_minus1 = p->r_minus1;
+  if (unitarity_defect) *unitarity_defect = p->unitarity_defect;
+  if (drift) *drift = p->drift;
+  if (stop_norm) *stop_norm = p->stop_norm;
+  if (last_pivot_norm) *last_pivot_norm = p->last_pivot_norm;
+  return FGFRFT_OK;
+}
+
+fgfrft_status fgfrft_plan_buffers(fgfrft_plan_t plan, void** stack_dev, void** P_dev) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  if (stack_dev) *stack_dev = p->stack;
+  if (P_dev) *P_dev = p->P;
+  return FGFRFT_OK;
+}
+
+void fgfrft_destroy(fgfrft_plan_t plan) { delete (Plan*)plan; }
+
+size_t fgfrft_update_workspace_bytes(fgfrft_plan_t plan, int n_alpha) {
+  if (!plan || n_alpha < 1) return 0;
+  return update_ws_bytes((const Plan*)plan, n_alpha);
+}
+
+fgfrft_status fgfrft_update(fgfrft_plan_t plan, const double* alphas, int n_alpha, void* Q_dev, void* ws_dev,
+                            size_t ws_bytes, void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  fgfrft_status rc = check_alphas(p, alphas, n_alpha);
+  if (rc) return rc;
+  if (!Q_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if ((uintptr_t)Q_dev % 8) { set_error("Q_dev must be 8-byte aligned"); return FGFRFT_EINVAL; }
+  const size_t need = update_ws_bytes(p, n_alpha);
+  if (ws_bytes < need) { set_error("update workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  hipStream_t s = (hipStream_t)stream;
+  FG_HIP(hipMemcpyAsync(ws_dev, alphas, (size_t)n_alpha * sizeof(double), hipMemcpyHostToDevice, s));
+  return update_launch(p, (const double*)ws_dev, n_alpha, Q_dev, ws_dev, s);
+}
+
+size_t fgfrft_apply_operator_workspace_bytes(int N, int n_alpha, int B, int x_shared) {
+  if (N < 1 || n_alpha < 1 || B < 1) return 0;
+  return apply_ws_bytes(N, n_alpha, B, x_shared);
+}
+
+fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_alpha, int adjoint, const void* X_dev, int x_complex,
+                                    int x_shared, int B, void* Y_dev, int y_real, void* ws_dev, size_t ws_bytes,
+                                    void* stream) {
+  if (N < 1 || N > 32768 || n_alpha < 1 || B < 1 || B > 4096) {
+    set_error("bad sizes N=%d n_alpha=%d B=%d", N, n_alpha, B);
+    return FGFRFT_EINVAL;
+  }
+  if (!Q_dev || !X_dev || !Y_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if ((uintptr_t)Q_dev % 16 || (uintptr_t)X_dev % 8 || (uintptr_t)Y_dev % 8) {
+    set_error("Q_dev must be 16-byte and X_dev, Y_dev 8-byte aligned");
+    return FGFRFT_EINVAL;
+  }
+  const size_t need = apply_ws_bytes(N, n_alpha, B, x_shared);
+  if (ws_bytes < need) { set_error("apply workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  return apply_launch(Q_dev, N, n_alpha, adjoint ? 1 : 0, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, Y_dev,
+                      y_real ? 1 : 0, ws_dev, (hipStream_t)stream);
+}
+
+static int apply_chunk(int n_alpha, int chunk) {
+  if (chunk <= 0) chunk = 16;
+  return chunk < n_alpha ? chunk : n_alpha;
+}
+
+size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared, int chunk) {
+  if (!plan || n_alpha < 1 || B < 1) return 0;
+  const Plan* p = (const Plan*)plan;
+  const int ch = apply_chunk(n_alpha, chunk);
+  return align_up((size_t)n_alpha * 8, 256) + align_up((size_t)ch * p->N * p->N * 8, 256) + update_ws_bytes(p, ch) +
+         apply_ws_bytes(p->N, ch, B, x_shared);
+}
+
+fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha, const void* X_dev, int x_complex,
+                           int x_shared, int B, void* Y_dev, int chunk, void* ws_dev, size_t ws_bytes, void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  fgfrft_status rc = check_alphas(p, alphas, n_alpha);
+  if (rc) return rc;
+  if (B < 1 || B > 4096) { set_error("B=%d outside [1, 4096]", B); return FGFRFT_EINVAL; }
+  if (!X_dev || !Y_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if ((uintptr_t)X_dev % 8 || (uintptr_t)Y_dev % 8 || (uintptr_t)ws_dev % 256) {
+    set_error("X_dev, Y_dev must be 8-byte and ws_dev 256-byte aligned");
+    return FGFRFT_EINVAL;
+  }
+  const int ch = apply_chunk(n_alpha, chunk);
+  const size_t need = fgfrft_apply_workspace_bytes(plan, n_alpha, B, x_shared, chunk);
+  if (ws_bytes < need) { set_error("apply workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws_dev;
+  double* al = (double*)base; base += align_up((size_t)n_alpha * 8, 256);
+  void* Qc = base; base += align_up((size_t)ch * p->N * p->N * 8, 256);
+  void* uws = base; base += update_ws_bytes(p, ch);
+  void* aws = base;
+  FG_HIP(hipMemcpyAsync(al, alphas, (size_t)n_alpha * 8, hipMemcpyHostToDevice, s));
+  const size_t NB = (size_t)p->N * B;
+  for (int a0 = 0; a0 < n_alpha; a0 += ch) {
+    const int nc = n_alpha - a0 < ch ? n_alpha - a0 : ch;
+    if ((rc = update_launch(p, al + a0, nc, Qc, uws, s))) return rc;
+    const void* xa = x_shared ? X_dev : (const void*)((const char*)X_dev + a0 * NB * (x_complex ? 8 : 4));
+    void* ya = (char*)Y_dev + a0 * NB * 8;
+    if ((rc = apply_launch(Qc, p->N, nc, 0, xa, x_complex ? 1 : 0, x_shared ? 1 : 0, B, ya, 0, aws, s))) return rc;
+  }
+  return FGFRFT_OK;
+}
+
+size_t fgfrft_grad_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared) {
+  if (!plan || n_alpha < 1 || B < 1) return 0;
+  return grad_ws_bytes((const Plan*)plan, n_alpha, B, x_shared);
+}
+
+fgfrft_status fgfrft_grad(fgfrft_plan_t plan, const double* alphas, int n_alpha, const void* X_dev, int x_complex,
+                          int x_shared, int B, const void* GY_dev, double* dalpha, void* dX_dev, void* ws_dev,
+                          size_t ws_bytes, void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  fgfrft_status rc = check_alphas(p, alphas, n_alpha);
+  if (rc) return rc;
+  if (B < 1 || B > 4096) { set_error("B=%d outside [1, 4096]", B); return FGFRFT_EINVAL; }
+  if (!X_dev || !GY_dev || !dalpha || !ws_dev) { set_error("NULL pointer"); return FGFRFT_EINVAL; }
+  if ((uintptr_t)ws_dev % 256) { set_error("ws_dev must be 256-byte aligned"); return FGFRFT_EINVAL; }
+  if (p->stacktype != FGFRFT_STACK_FP32) { set_error("grad needs an FP32 power stack"); return FGFRFT_EUNSUPPORTED; }
+  return grad_run(p, alphas, n_alpha, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, GY_dev, dalpha, dX_dev, ws_dev,
+                  ws_bytes, (hipStream_t)stream);
+}
+
+const char* fgfrft_strerror(int status) {
+  switch (status) {
+    case FGFRFT_OK: return "ok";
+    case FGFRFT_EINVAL: return "invalid argument";
+    case FGFRFT_ENOTUNITARY: return "F is not unitary";
+    case FGFRFT_EALPHA: return "order out of range (need |alpha| < L)";
+    case FGFRFT_ENOMEM: return "buffer too small";
+    case FGFRFT_EHIP: return "HIP runtime error";
+    case FGFRFT_EDRIFT: return "power recurrence drift";
+    case FGFRFT_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* fgfrft_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the FGFRFT HIP sources (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "../../include/fgfrft.h"
+
+namespace fgfrft {
+
+// ---------------------------------------------------------------- vector types
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+
+struct cplx64 { float re, im; };
+struct cplx128 { double re, im; };
+
+// Fixed power-of-two scales for the split 16-bit operands.  Power-stack and
+// projector entries, coefficients and operator entries are bounded by ~1.1 in
+// magnitude (entries of contractions of unitary matrices, |c_n| <= 1), so a
+// factor 2^12 keeps every fp16 value normal and far from overflow.
+constexpr float kStackScale = 4096.0f;
+constexpr float kCoefScale = 4096.0f;
+constexpr float kUnscale = 1.0f / (4096.0f * 4096.0f);
+
+// ---------------------------------------------------------------- plan object
+struct Plan {
+  int N = 0, L = 0, LP = 0;        // LP: L padded to a multiple of 32 (MFMA k extent)
+  int cplx = 0;                    // 1: complex F, complex power stack
+  int stacktype = 0;               // fgfrft_stacktype
+  int r_minus1 = 0;
+  double unitarity_defect = 0, drift = 0, stop_norm = 0, last_pivot_norm = 0, tau = 1e-6;
+  void* stack = nullptr;           // [L][N][N] elements (4 B real / 8 B complex)
+  void* P = nullptr;               // [N][N] float (real) or cplx64 (complex)
+  size_t stack_elem_bytes = 0;
+};
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+fgfrft_status hip_fail(hipError_t e, const char* what);
+#define FG_HIP(call)                                              \
+  do {                                                            \
+    hipError_t e_ = (call);                                       \
+    if (e_ != hipSuccess) return ::fgfrft::hip_fail(e_, #call);   \
+  } while (0)
+#define FG_LAUNCHED(what)                                         \
+  do {                                                            \
+    hipError_t e_ = hipGetLastError();                            \
+    if (e_ != hipSuccess) return ::fgfrft::hip_fail(e_, what);    \
+  } while (0)
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- kernel entry points
+// FP64 plan side (plan_f64.hip)
+fgfrft_status gemm_f64(bool cplx, bool conj_a, int M, int Ncols, int K, const void* A, int lda,
+                       const void* B, int ldb, void* C, int ldc, hipStream_t s);
+fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size_t scratch_bytes,
+                         hipStream_t s);
+size_t plan_scratch_bytes(int N, int L, bool cplx);
+
+// Online side (update.hip)
+size_t update_ws_bytes(const Plan* p, int n_alpha);
+fgfrft_status update_launch(const Plan* p, const double* alphas_dev, int n_alpha, void* Q,
+                            void* ws, hipStream_t s);
+fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, int n_alpha_pad,
+                          void* table, float4* epi, int deriv, hipStream_t s);
+
+// Apply (apply.hip)
+size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared);
+fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex,
+                           int x_shared, int B, void* Y, int y_real, void* ws, hipStream_t s);
+
+// Gradient (grad.hip)
+size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared);
+fgfrft_status grad_run(const Plan* p, const double* alphas_host, int n_alpha, const void* X, int x_complex,
+                       int x_shared, int B, const void* GY, double* dalpha, void* dX, void* ws,
+                       size_t ws_bytes, hipStream_t s);
+
+}  // namespace fgfrft

@@ -1,0 +1,190 @@
+"""Torch-facing wrapper of the FGFRFT C ABI: device memory and streams from
+PyTorch, every computation in the HIP library (argument marshalling only).
+
+    plan = Plan(F_cuda, L)                 # offline stage, Algorithm 1
+    Q = plan.update(alphas)                # Q_L^alpha for many orders (Definition 1)
+    Y = plan.apply(alphas, X)              # Q_L^alpha X (Definition 2)
+    da, dX = plan.grad(alphas, X, GY)      # Proposition 4
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import P_double, check, lib
+
+STACK_TYPES = {"fp32": 0, "bf16x2": 1}
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _alphas(alphas) -> np.ndarray:
+    if isinstance(alphas, torch.Tensor):
+        alphas = alphas.detach().cpu().numpy()
+    return np.ascontiguousarray(np.atleast_1d(np.asarray(alphas, dtype=np.float64)))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Plan:
+    """Offline stage of Algorithm 1 on the GPU for a unitary F.
+
+    F: cuda tensor, float64 (real orthogonal F) or complex128, shape [N, N].
+    The persistent buffer (power stack M_1..M_L and P) is a torch tensor owned
+    by this object; the FP64 planning scratch is released when planning ends.
+    """
+
+    def __init__(self, F: torch.Tensor, L: int, stacktype: str = "fp32", tau: float = 0.0, stream=None):
+        if not F.is_cuda:
+            raise ValueError("F must be a cuda tensor")
+        if F.dtype == torch.float64:
+            intype = 1
+        elif F.dtype == torch.complex128:
+            intype = 0
+        else:
+            raise TypeError("F must be float64 or complex128")
+        F = F.contiguous()
+        N = F.shape[0]
+        if F.shape != (N, N):
+            raise ValueError("F must be square")
+        L_ = lib()
+        pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(L_.fgfrft_plan_bytes(N, L, intype, STACK_TYPES[stacktype], ctypes.byref(pb), ctypes.byref(sb)),
+              "fgfrft_plan_bytes")
+        self.device = F.device
+        self.persistent = _workspace(pb.value, F.device)
+        scratch = _workspace(sb.value, F.device)
+        h = ctypes.c_void_p()
+        check(L_.fgfrft_plan(_ptr(F), N, L, intype, STACK_TYPES[stacktype], float(tau), _ptr(self.persistent),
+                             pb.value, _ptr(scratch), sb.value, _stream(stream), ctypes.byref(h)), "fgfrft_plan")
+        del scratch
+        self._h = h
+        self.N, self.L = N, L
+        self.complex = intype == 0
+        self.stacktype = stacktype
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fgfrft_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------ info
+    def info(self) -> dict:
+        r = ctypes.c_int()
+        u, d, sn, lp = (ctypes.c_double() for _ in range(4))
+        check(lib().fgfrft_plan_info(self._h, ctypes.byref(r), ctypes.byref(u), ctypes.byref(d), ctypes.byref(sn),
+                                     ctypes.byref(lp)), "fgfrft_plan_info")
+        return dict(r_minus1=r.value, unitarity_defect=u.value, drift=d.value, stop_norm=sn.value,
+                    last_pivot_norm=lp.value)
+
+    @property
+    def r_minus1(self) -> int:
+        return self.info()["r_minus1"]
+
+    def buffers(self):
+        """(stack, P) as torch views of the resident data (FP32 stack only)."""
+        N, L = self.N, self.L
+        s, p = ctypes.c_void_p(), ctypes.c_void_p()
+        check(lib().fgfrft_plan_buffers(self._h, ctypes.byref(s), ctypes.byref(p)), "fgfrft_plan_buffers")
+        base = self.persistent.data_ptr()
+        es = 8 if self.complex else 4
+        stack = self.persistent[: L * N * N * es]
+        poff = p.value - base
+        P = self.persistent[poff: poff + N * N * es]
+        if self.stacktype == "fp32":
+            dt = torch.complex64 if self.complex else torch.float32
+            stack = stack.view(dt).view(L, N, N)
+        P = P.view(torch.complex64 if self.complex else torch.float32).view(N, N)
+        return stack, P
+
+    # ------------------------------------------------------------------ online stage
+    def update(self, alphas, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        a = _alphas(alphas)
+        n = a.size
+        if out is None:
+            out = torch.empty((n, self.N, self.N), dtype=torch.complex64, device=self.device)
+        if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() < n * self.N * self.N:
+            raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*N elements")
+        L_ = lib()
+        ws = _workspace(L_.fgfrft_update_workspace_bytes(self._h, n), self.device)
+        check(L_.fgfrft_update(self._h, a.ctypes.data_as(P_double), n, _ptr(out), _ptr(ws), ws.numel(),
+                               _stream(stream)), "fgfrft_update")
+        return out
+
+    def apply(self, alphas, X: torch.Tensor, chunk: int = 0, stream=None) -> torch.Tensor:
+        """Y[a] = Q(alphas[a]) X[a] with X [n_alpha, N, B] or a shared [N, B] block."""
+        a = _alphas(alphas)
+        n = a.size
+        x_shared = X.dim() == 2
+        B = X.shape[-1]
+        xc = _check_signal(X, n, self.N, x_shared)
+        Y = torch.empty((n, self.N, B), dtype=torch.complex64, device=self.device)
+        L_ = lib()
+        ws = _workspace(L_.fgfrft_apply_workspace_bytes(self._h, n, B, int(x_shared), chunk), self.device)
+        check(L_.fgfrft_apply(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(Y), chunk,
+                              _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply")
+        return Y
+
+    def grad(self, alphas, X: torch.Tensor, GY: torch.Tensor, want_dX: bool = True, stream=None):
+        """(dl/dalpha as float64 numpy array, dl/dX or None) for GY = dl/dRe Y + j dl/dIm Y."""
+        a = _alphas(alphas)
+        n = a.size
+        x_shared = X.dim() == 2
+        B = X.shape[-1]
+        xc = _check_signal(X, n, self.N, x_shared)
+        if GY.dtype != torch.complex64 or not GY.is_contiguous() or tuple(GY.shape) != (n, self.N, B):
+            raise ValueError("GY must be contiguous complex64 [n_alpha, N, B]")
+        dX = torch.empty_like(X) if want_dX else None
+        dal = np.zeros(n, dtype=np.float64)
+        L_ = lib()
+        ws = _workspace(L_.fgfrft_grad_workspace_bytes(self._h, n, B, int(x_shared)), self.device)
+        check(L_.fgfrft_grad(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(GY),
+                             dal.ctypes.data_as(P_double), _ptr(dX) if dX is not None else None, _ptr(ws),
+                             ws.numel(), _stream(stream)), "fgfrft_grad")
+        return dal, dX
+
+
+def _check_signal(X: torch.Tensor, n: int, N: int, x_shared: bool) -> int:
+    if not X.is_cuda or not X.is_contiguous():
+        raise ValueError("X must be a contiguous cuda tensor")
+    if X.dtype == torch.float32:
+        xc = 0
+    elif X.dtype == torch.complex64:
+        xc = 1
+    else:
+        raise TypeError("X must be float32 or complex64")
+    if x_shared:
+        if X.shape[0] != N:
+            raise ValueError("shared X must be [N, B]")
+    elif X.dim() != 3 or X.shape[0] != n or X.shape[1] != N:
+        raise ValueError("X must be [n_alpha, N, B] or [N, B]")
+    return xc
+
+
+def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_real: bool = False,
+                   stream=None) -> torch.Tensor:
+    """Y[a] = op(Q[a]) X[a] for a complex64 operator batch Q [n, N, N]."""
+    if Q.dtype != torch.complex64 or not Q.is_contiguous() or Q.dim() != 3:
+        raise ValueError("Q must be contiguous complex64 [n, N, N]")
+    n, N, _ = Q.shape
+    x_shared = X.dim() == 2
+    B = X.shape[-1]
+    xc = _check_signal(X, n, N, x_shared)
+    Y = torch.empty((n, N, B), dtype=torch.float32 if y_real else torch.complex64, device=Q.device)
+    L_ = lib()
+    ws = _workspace(L_.fgfrft_apply_operator_workspace_bytes(N, n, B, int(x_shared)), Q.device)
+    check(L_.fgfrft_apply_operator(_ptr(Q), N, n, int(adjoint), _ptr(X), xc, int(x_shared), B, _ptr(Y), int(y_real),
+                                   _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply_operator")
+    return Y

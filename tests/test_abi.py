@@ -1,0 +1,81 @@
+"""The C-ABI library loads, exports every symbol include/fgfrft.h declares, and
+rejects bad arguments on the host (no GPU needed for any of these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2602_20870_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fgfrft.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"FGFRFT_API\s+[\w\s\*]+?\b(fgfrft_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libfgfrft.so not built")
+    return _lib.lib()
+
+
+def test_header_declares_expected_entry_points():
+    syms = declared_symbols()
+    for name in ("fgfrft_plan", "fgfrft_update", "fgfrft_apply", "fgfrft_apply_operator", "fgfrft_grad",
+                 "fgfrft_destroy", "fgfrft_strerror", "fgfrft_last_error"):
+        assert name in syms
+
+
+def test_every_declared_symbol_is_exported(L):
+    syms = declared_symbols()
+    assert set(syms) == set(_lib.SIGNATURES), "binding and header disagree"
+    for name in syms:
+        assert hasattr(L, name), name
+
+
+def test_only_abi_symbols_are_exported(L):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    fg = {s for s in exported if s.startswith("fgfrft_")}
+    assert fg == set(declared_symbols())
+
+
+def test_plan_bytes_validation(L):
+    p, s = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.fgfrft_plan_bytes(0, 10, 1, 0, ctypes.byref(p), ctypes.byref(s)) == -1
+    assert L.fgfrft_plan_bytes(64, 0, 1, 0, ctypes.byref(p), ctypes.byref(s)) == -1
+    assert L.fgfrft_plan_bytes(64, 65, 1, 0, ctypes.byref(p), ctypes.byref(s)) == -1
+    assert L.fgfrft_plan_bytes(64, 33, 0, 0, ctypes.byref(p), ctypes.byref(s)) == -7  # complex F, L > 32
+    assert L.fgfrft_plan_bytes(64, 10, 5, 0, ctypes.byref(p), ctypes.byref(s)) == -1
+    assert L.fgfrft_plan_bytes(64, 10, 1, 0, ctypes.byref(p), ctypes.byref(s)) == 0
+    N, Lt = 64, 10
+    assert p.value >= Lt * N * N * 4 + N * N * 4
+    assert s.value >= 4 * N * N * 8
+    assert L.fgfrft_plan_bytes(64, 10, 0, 0, ctypes.byref(p), ctypes.byref(s)) == 0
+    assert p.value >= Lt * N * N * 8 + N * N * 8
+
+
+def test_null_and_small_arguments_are_rejected_on_host(L):
+    h = ctypes.c_void_p()
+    # NULL device pointers: rejected before any HIP call
+    rc = L.fgfrft_plan(None, 16, 4, 1, 0, 0.0, None, 0, None, 0, None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert b"NULL" in L.fgfrft_last_error()
+    a = (ctypes.c_double * 2)(0.5, 0.25)
+    assert L.fgfrft_update(None, a, 2, None, None, 0, None) == -1
+    assert L.fgfrft_grad(None, a, 2, None, 0, 0, 4, None, None, None, None, 0, None) == -1
+    assert L.fgfrft_apply_operator(None, 16, 1, 0, None, 0, 0, 4, None, 0, None, 0, None) == -1
+    assert L.fgfrft_apply_operator(None, 0, 1, 0, None, 0, 0, 4, None, 0, None, 0, None) == -1
+    assert L.fgfrft_update_workspace_bytes(None, 4) == 0
+
+
+def test_strerror_names(L):
+    for code in range(0, -8, -1):
+        assert L.fgfrft_strerror(code)
+    assert L.fgfrft_strerror(-3).startswith(b"order out of range")

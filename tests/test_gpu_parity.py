@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs.  Bar: relative Frobenius error per order <= 1e-5 (FP32 path)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_common import TOL_BF16X2, TOL_FP32, announce, rel_fro, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _real_orthogonal_with_minus1(n, r, seed, margin=0.3):
+    rng = np.random.default_rng(seed)
+    rest = n - r
+    pairs = rest // 2
+    ph = rng.uniform(0.05, np.pi - margin, size=pairs)
+    d = np.zeros((n, n))
+    d[: 2 * pairs, : 2 * pairs] = synth.rotation_blocks(ph)
+    k = 2 * pairs
+    if rest % 2:
+        d[k, k] = 1.0
+        k += 1
+    for i in range(k, n):
+        d[i, i] = -1.0
+    v, rr = np.linalg.qr(rng.standard_normal((n, n)))
+    v = v * np.sign(np.diag(rr))[None, :]
+    return v @ d @ v.T
+
+
+def _gpu_plan(torch, F, L, stacktype="fp32"):
+    from paper_2602_20870_amd import Plan
+    return Plan(torch.from_numpy(np.ascontiguousarray(F)).cuda(), L, stacktype=stacktype)
+
+
+def _check_update(torch, F, L, alphas, tol=TOL_FP32, stacktype="fp32", sample=None, r_expect=None):
+    plan = _gpu_plan(torch, F, L, stacktype)
+    ref = O.Plan(F, L)
+    if r_expect is not None:
+        assert plan.r_minus1 == r_expect == ref.r_minus1
+    else:
+        assert plan.r_minus1 == ref.r_minus1
+    Q = plan.update(alphas).cpu().numpy()
+    idx = range(len(alphas)) if sample is None else sample
+    worst = 0.0
+    for a in idx:
+        e = rel_fro(Q[a], ref.combine(float(alphas[a])))
+        worst = max(worst, e)
+        assert e <= tol, (a, alphas[a], e)
+    return worst, plan, ref, Q
+
+
+# ----------------------------------------------------------------------------
+# plan (offline stage)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["er64", "orth_r3", "dft64", "orth_r1_odd"])
+def test_plan_projector_and_stack(case):
+    torch = torch_cuda()
+    announce(f"plan {case}")
+    if case == "er64":
+        F, L = synth.make_config("er64", with_signals=False)["F"], 10
+    elif case == "orth_r3":
+        F, L = _real_orthogonal_with_minus1(48, 3, 5), 12
+    elif case == "orth_r1_odd":
+        F, L = _real_orthogonal_with_minus1(37, 1, 6), 7
+    else:
+        F, L = synth.dft_matrix(64), 9
+    plan = _gpu_plan(torch, F, L)
+    ref = O.Plan(F, L)
+    info = plan.info()
+    assert info["r_minus1"] == ref.r_minus1
+    assert info["unitarity_defect"] < 1e-12
+    assert info["drift"] < 1e-12
+    stack, P = plan.buffers()
+    assert np.max(np.abs(P.cpu().numpy() - ref.P)) < 1e-6
+    S = stack.cpu().numpy()
+    for n in range(1, L + 1):
+        assert np.max(np.abs(S[n - 1] - ref.M[n])) < 1e-6, n
+
+
+def test_plan_rejects_non_unitary():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import FGFRFTError
+    F = synth.make_config("er64", with_signals=False)["F"].copy()
+    F[3, 5] += 1e-6
+    with pytest.raises(FGFRFTError) as ei:
+        _gpu_plan(torch, F, 10)
+    assert ei.value.name == "FGFRFT_ENOTUNITARY"
+
+
+# ----------------------------------------------------------------------------
+# update (a-1, a-2)
+# ----------------------------------------------------------------------------
+def test_update_er64_config():
+    torch = torch_cuda()
+    announce("update er64 N=64 L=10 16 orders")
+    c = synth.make_config("er64", with_signals=False)
+    worst, *_ = _check_update(torch, c["F"], c["L"], c["alphas"])
+    print("worst rel err", worst)
+
+
+def test_update_dft256_complex_minus1():
+    torch = torch_cuda()
+    announce("update dft256 L=32 256 orders")
+    c = synth.make_config("dft256", with_signals=False)
+    _check_update(torch, c["F"], c["L"], c["alphas"], sample=range(0, 256, 9), r_expect=64)
+
+
+def test_update_grid1024_launch_config():
+    torch = torch_cuda()
+    announce("update grid1024 L=32 256 orders (sampled)")
+    c = synth.make_config("grid1024", with_signals=False)
+    _check_update(torch, c["F"], c["L"], c["alphas"], sample=[0, 1, 77, 128, 255])
+
+
+@pytest.mark.parametrize("N,L,n_alpha", [(1, 3, 5), (2, 4, 1), (17, 5, 33), (50, 40, 3), (100, 64, 40)])
+def test_update_ragged_and_edge_sizes(N, L, n_alpha):
+    torch = torch_cuda()
+    announce(f"update ragged N={N} L={L} n_alpha={n_alpha}")
+    rng = np.random.default_rng(N * 100 + L)
+    F = _real_orthogonal_with_minus1(N, min(N, 1 + N // 10), N) if N > 1 else np.array([[-1.0]])
+    alphas = rng.uniform(-min(L, 3) + 0.01, min(L, 3) - 0.01, n_alpha)
+    _check_update(torch, F, L, alphas)
+
+
+def test_update_complex_haar_L10():
+    torch = torch_cuda()
+    announce("update haar N=96 L=10")
+    F = synth.haar_unitary(96, np.random.default_rng(4))
+    alphas = np.array([0.5, -1.7, 0.15, 0.999, -0.001])
+    _check_update(torch, F, 10, alphas)
+
+
+def test_update_integer_orders_and_adjoint_symmetry():
+    torch = torch_cuda()
+    announce("update integer orders / adjoint symmetry")
+    F = _real_orthogonal_with_minus1(40, 3, 8)
+    plan = _gpu_plan(torch, F, 8)
+    alphas = np.array([0.0, 1.0, -1.0, 2.0, -3.0, 0.37, -0.37])
+    Q = plan.update(alphas).cpu().numpy().astype(np.complex128)
+    ref = [np.eye(40), F, F.T, F @ F, (F @ F @ F).T]
+    for a, R in enumerate(ref):
+        assert np.max(np.abs(Q[a] - R)) < 2e-6, alphas[a]
+    assert rel_fro(Q[6], Q[5].conj().T) < 2e-6
+
+
+def test_update_bf16x2_precision_form():
+    torch = torch_cuda()
+    announce("update bf16x2 grid1024 (sampled)")
+    c = synth.make_config("grid1024", with_signals=False, n_alpha=64)
+    worst, *_ = _check_update(torch, c["F"], c["L"], c["alphas"], tol=TOL_BF16X2, stacktype="bf16x2",
+                              sample=[0, 5, 31, 63])
+    print("bf16x2 worst rel err", worst)
+
+
+def test_update_rejects_out_of_range_orders():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import FGFRFTError
+    plan = _gpu_plan(torch, synth.rotation_blocks([0.3, 1.2]), 3)
+    for bad in ([3.0], [-3.5], [np.nan]):
+        with pytest.raises(FGFRFTError) as ei:
+            plan.update(bad)
+        assert ei.value.name == "FGFRFT_EALPHA"
+
+
+# ----------------------------------------------------------------------------
+# apply (a-3)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("xc,shared,N,B", [(False, False, 64, 32), (True, False, 80, 37), (False, True, 50, 5),
+                                           (True, True, 130, 70)])
+def test_apply_against_oracle(xc, shared, N, B):
+    torch = torch_cuda()
+    announce(f"apply xc={xc} shared={shared} N={N} B={B}")
+    F = _real_orthogonal_with_minus1(N, 2, N)
+    L = 10
+    rng = np.random.default_rng(N + B)
+    alphas = rng.uniform(-2, 2, 6)
+    shape = (N, B) if shared else (6, N, B)
+    X = synth.complex_signals(shape, rng) if xc else synth.real_signals(shape, rng)
+    X = X * 1e3  # exercise the per-signal scaling
+    plan = _gpu_plan(torch, F, L)
+    ref = O.Plan(F, L)
+    Xt = torch.from_numpy(X.astype(np.complex64 if xc else np.float32)).cuda()
+    Y = plan.apply(alphas, Xt, chunk=4).cpu().numpy()
+    for a, al in enumerate(alphas):
+        Xa = X if shared else X[a]
+        Xa32 = Xa.astype(np.complex64 if xc else np.float32).astype(np.complex128)
+        assert rel_fro(Y[a], ref.combine(al) @ Xa32) <= TOL_FP32, a
+
+
+def test_apply_operator_adjoint_and_real_output():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import apply_operator
+    announce("apply_operator adjoint / y_real")
+    rng = np.random.default_rng(3)
+    n, N, B = 3, 72, 24
+    Q = (rng.standard_normal((n, N, N)) + 1j * rng.standard_normal((n, N, N))) / np.sqrt(N)
+    X = rng.standard_normal((n, N, B)) + 1j * rng.standard_normal((n, N, B))
+    Qt = torch.from_numpy(Q.astype(np.complex64)).cuda()
+    Xt = torch.from_numpy(X.astype(np.complex64)).cuda()
+    Q32 = Q.astype(np.complex64).astype(np.complex128)
+    X32 = X.astype(np.complex64).astype(np.complex128)
+    Y = apply_operator(Qt, Xt, adjoint=True).cpu().numpy()
+    Yr = apply_operator(Qt, Xt, adjoint=False, y_real=True).cpu().numpy()
+    for a in range(n):
+        assert rel_fro(Y[a], Q32[a].conj().T @ X32[a]) <= TOL_FP32
+        assert rel_fro(Yr[a], (Q32[a] @ X32[a]).real) <= TOL_FP32
+
+
+# ----------------------------------------------------------------------------
+# gradients (a-4)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("xc,shared,cplxF", [(False, False, False), (True, False, False), (False, True, False),
+                                             (True, False, True)])
+def test_grad_against_oracle(xc, shared, cplxF):
+    torch = torch_cuda()
+    announce(f"grad xc={xc} shared={shared} complexF={cplxF}")
+    rng = np.random.default_rng(11)
+    N, L, B, n = 48, 9, 6, 5
+    F = synth.haar_unitary(N, rng) if cplxF else _real_orthogonal_with_minus1(N, 2, 12)
+    alphas = np.array([0.55, -1.3, 1.0, 0.02, -2.2])
+    shape = (N, B) if shared else (n, N, B)
+    X = synth.complex_signals(shape, rng) if xc else synth.real_signals(shape, rng)
+    X = X.astype(np.complex64 if xc else np.float32)
+    GY = (rng.standard_normal((n, N, B)) + 1j * rng.standard_normal((n, N, B))).astype(np.complex64)
+    plan = _gpu_plan(torch, F, L)
+    ref = O.Plan(F, L)
+    Xd = X.astype(np.complex128) if xc else X.astype(np.float64)
+    Xs = np.broadcast_to(Xd, (n, N, B)) if shared else Xd
+    dal_ref, dX_ref = O.grad(ref.P, ref.M, alphas, Xs, GY.astype(np.complex128), x_real=not xc)
+    dal, dX = plan.grad(alphas, torch.from_numpy(X).cuda(), torch.from_numpy(GY).cuda())
+    scale = np.max(np.abs(dal_ref))
+    assert np.max(np.abs(dal - dal_ref)) <= TOL_FP32 * scale, (dal, dal_ref)
+    dX = dX.cpu().numpy()
+    dX_ref = dX_ref.sum(axis=0) if shared else dX_ref
+    assert rel_fro(dX, dX_ref) <= TOL_FP32
