@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the FGFRFT online stage on one MI355X.
+
+Workload (default): kNN graph (k=10, Gaussian weights) on 4096 points from a
+5-component 3-D Gaussian mixture, combinatorial Laplacian, F = U^T (real
+orthogonal), L = 32, 256 orders uniform in [-2, 2], 64 real N(0,1) signals per
+order.  One step = operator update for all 256 orders (coefficients on the
+GPU, one launch) followed by the apply of each operator to its 64 signals.
+Inputs are resident in HBM before timing starts; the plan (offline stage) is
+built once, outside the timed region, as in the paper's own timings.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def update_algorithmic_bytes(N, L, n_alpha):
+    # per order: 8 N^2 (complex64 Q written) + [(L+1) 4N^2 (M_0..M_L) + 4N^2 (P)] / n_alpha
+    return n_alpha * 8.0 * N * N + (L + 2) * 4.0 * N * N
+
+
+def apply_algorithmic_bytes(N, B, n_alpha):
+    # per order: 8 N^2 (Q read) + 4 N B (x read) + 8 N B (y written)
+    return n_alpha * (8.0 * N * N + 12.0 * N * B)
+
+
+def cpu_baseline(F, alphas, L, budget_s=15.0):
+    """Oracle (FP64 NumPy) update timed on the host cores for a bounded sample of orders."""
+    import oracle as O
+    t0 = time.time()
+    plan = O.Plan(F, L, route="symmetric")
+    setup = time.time() - t0
+    done, t_acc = 0, 0.0
+    for al in alphas:
+        t1 = time.perf_counter()
+        plan.combine(float(al))
+        t_acc += time.perf_counter() - t1
+        done += 1
+        if t_acc > budget_s:
+            break
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas = None
+    return dict(value=done / t_acc, unit="updates/s", cores=1, kind="oracle",
+                sample=(f"{done} of {len(alphas)} orders of the same workload, N={F.shape[0]}, L={L}, "
+                        f"complex128 Algorithm-1 combination (NumPy elementwise, 1 thread; "
+                        f"offline setup {setup:.1f}s untimed, BLAS threads {blas})"),
+                seconds=t_acc)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-alpha", type=int, default=256)
+    ap.add_argument("--signals", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stacktype", default="fp32", choices=["fp32", "bf16x2"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2602_20870_amd import Plan, apply_operator, lib
+
+    lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    cfg = synth.make_config("knn4096", seed=0, n_alpha=args.n_alpha, with_signals=False)
+    F, L, N = cfg["F"], cfg["L"], cfg["N"]
+    alphas = cfg["alphas"]
+    B, na = args.signals, args.n_alpha
+    rng = synth.streams(0, 3)[2]
+    X = torch.from_numpy(synth.real_signals((na, N, B), rng).astype(np.float32)).to(dev)
+    log(f"workload built in {time.time() - t0:.1f}s (N={N}, L={L}, n_alpha={na}, B={B})")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan(torch.from_numpy(F).to(dev), L, stacktype=args.stacktype)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    log(f"plan {plan_s:.2f}s {info}")
+
+    Q = torch.empty((na, N, N), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(times=None):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        plan.update(alphas, out=Q)
+        e1.record(stream)
+        Y = apply_operator(Q, X)
+        e2.record(stream)
+        if times is not None:
+            times.append((e0, e1, e2))
+        return Y
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(times)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in times]))
+    app_ms = float(np.mean([b.elapsed_time(c) for _, b, c in times]))
+    ms_step = wall * 1e3 / args.steps
+    log(f"update {upd_ms:.3f} ms, apply {app_ms:.3f} ms, step {ms_step:.3f} ms")
+
+    upd_bytes = update_algorithmic_bytes(N, L, na)
+    achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
+    app_gbs = apply_algorithmic_bytes(N, B, na) / (app_ms * 1e-3) / 1e9
+    out = {
+        "metric": "F^alpha updates/s (update + apply to 64 signals per order), N=4096, L=32",
+        "value": na / (ms_step * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (split fp16 MFMA operands, fp32 accumulate)" if args.stacktype == "fp32" else "bf16x2",
+        "data": "synthetic",
+        "config": {"workload": "knn4096: kNN k=10 on 5-GMM 3-D points, N=4096, L=32, 256 orders in [-2,2], "
+                               "64 real N(0,1) signals per order", "n_alpha": na, "signals_per_order": B,
+                   "stacktype": args.stacktype},
+        "signals_per_s": na * B / (ms_step * 1e-3),
+        "update": {"ms": upd_ms, "updates_per_s": na / (upd_ms * 1e-3), "algorithmic_GB": upd_bytes / 1e9},
+        "apply": {"ms": app_ms, "algorithmic_GBps": app_gbs, "hbm_frac": app_gbs / HBM_PEAK_GBS},
+        "plan_s": plan_s,
+        "plan_info": info,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_update"},
+    }
+    del Q
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(F, alphas, L)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

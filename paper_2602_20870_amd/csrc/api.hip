@@ -53,7 +53,7 @@ fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype, size_t*
   const bool cplx = intype == FGFRFT_IN_C128;
   if (cplx && L > 32) { set_error("complex F supports L <= 32"); return FGFRFT_EUNSUPPORTED; }
   const size_t NN = (size_t)N * N;
-  if (persistent) *persistent = align_up((size_t)L * NN * stack_elem_bytes(cplx), 256) + align_up(NN * (cplx ? 8 : 4), 256);
+  if (persistent) *persistent = align_up((size_t)2 * L * NN * stack_elem_bytes(cplx), 256) + align_up(NN * (cplx ? 8 : 4), 256);
   if (scratch) *scratch = plan_scratch_bytes(N, L, cplx);
   return FGFRFT_OK;
 }
@@ -80,7 +80,7 @@ fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stack
   p->tau = tau;
   p->stack_elem_bytes = stack_elem_bytes(p->cplx);
   p->stack = persistent_dev;
-  p->P = (char*)persistent_dev + align_up((size_t)L * N * N * p->stack_elem_bytes, 256);
+  p->P = (char*)persistent_dev + align_up((size_t)2 * L * N * N * p->stack_elem_bytes, 256);
   rc = plan_build(p, F_dev, tau, scratch_dev, scratch_bytes, (hipStream_t)stream);
   if (rc) { delete p; return rc; }
   *out = (fgfrft_plan_t)p;

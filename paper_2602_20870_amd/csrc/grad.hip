@@ -9,9 +9,9 @@
 //
 // Steps per chunk of orders:
 //   k_outer      G_a = GY[a] X[a]^H                     (FP32, LDS-tiled)
-//   k_inner      per tile pair {(I,J),(J,I)}: the pair's stack tiles staged in LDS once,
-//                partial sums of T over the pair's positions for every order of the chunk
-//   k_inner_sum  fixed-order sum of the partials over all tile pairs in FP64 (deterministic)
+//   k_inner      per 16x16 tile: the tile's 2L stack matrices staged in LDS once,
+//                partial sums of T over the tile's positions for every order of the chunk
+//   k_inner_sum  fixed-order sum of the partials over all tiles in FP64 (deterministic)
 #include "internal.h"
 #include <math.h>
 #include <vector>
@@ -77,10 +77,11 @@ __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, co
     }
 }
 
-// ---------------------------------------------------------------- T partials per tile pair
-// LDS: S[tile][pos][n] (n = 0..L-1 for M_{n+1}; complex interleaved), Pt[tile][pos],
-// Gs[a][tile][pos] for up to AC orders at a time.  Thread (k, tile) accumulates over the
-// tile's 256 positions for every order of the sub-chunk.
+// ---------------------------------------------------------------- T partials per tile
+// One workgroup per 16x16 tile of positions.  LDS: S[pos][k][plane] for the 2L resident
+// matrices (k < L: M_{k+1}, k >= L: M_{k-L+1}^H), Pt[pos][plane], Gs[a][pos][2] for up to AC
+// orders at a time.  Thread (k, half) accumulates conj(G) * B_k over half of the tile's
+// positions for every order of the sub-chunk; B_{2L} = P, B_{2L+1} = I.
 constexpr int AC = 4;
 
 template <bool CPLX>
@@ -89,25 +90,20 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
                                                cplx64* __restrict__ partial) {
   constexpr int NPL = CPLX ? 2 : 1;
   extern __shared__ __align__(16) float sm[];
-  float* S = sm;                                         // [2][GPOS][L][NPL]
-  float* Pt = S + (size_t)2 * GPOS * L * NPL;            // [2][GPOS][NPL]
-  float* Gs = Pt + 2 * GPOS * NPL;                       // [AC][2][GPOS][2]
+  const int L2 = 2 * L;
+  float* S = sm;                                         // [GPOS][L2][NPL]
+  float* Pt = S + (size_t)GPOS * L2 * NPL;               // [GPOS][NPL]
+  float* Gs = Pt + GPOS * NPL;                           // [AC][GPOS][2]
   const int tid = threadIdx.x;
   const int q = blockIdx.x;
-  int I = (int)((2.0 * nb + 1.0 - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * q)) * 0.5);
-  if (I < 0) I = 0;
-  while (I > 0 && I * nb - I * (I - 1) / 2 > q) --I;
-  while ((I + 1) * nb - (I + 1) * I / 2 <= q) ++I;
-  const int J = I + (q - (I * nb - I * (I - 1) / 2));
-  const bool diag = I == J;
-  const int ntiles = diag ? 1 : 2;
+  const int I = q / nb, J = q % nb;
   const size_t NN = (size_t)N * N;
-  for (int it = tid; it < ntiles * GPOS * L; it += 256) {
-    const int p = it % GPOS, n = (it / GPOS) % L, t = it / (GPOS * L);
-    const int row = (t == 0 ? I : J) * GT + p / GT, col = (t == 0 ? J : I) * GT + p % GT;
+  for (int it = tid; it < GPOS * L2; it += 256) {
+    const int p = it % GPOS, k = it / GPOS;
+    const int row = I * GT + p / GT, col = J * GT + p % GT;
     const bool inb = row < N && col < N;
-    float* dst = S + (((size_t)t * GPOS + p) * L + n) * NPL;
-    const size_t off = (size_t)n * NN + (size_t)row * N + col;
+    float* dst = S + ((size_t)p * L2 + k) * NPL;
+    const size_t off = (size_t)k * NN + (size_t)row * N + col;
     if (CPLX) {
       const float2 v = inb ? ((const float2*)stack)[off] : make_float2(0.f, 0.f);
       dst[0] = v.x;
@@ -116,79 +112,68 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
       dst[0] = inb ? ((const float*)stack)[off] : 0.f;
     }
   }
-  for (int it = tid; it < ntiles * GPOS; it += 256) {
-    const int p = it % GPOS, t = it / GPOS;
-    const int row = (t == 0 ? I : J) * GT + p / GT, col = (t == 0 ? J : I) * GT + p % GT;
+  for (int p = tid; p < GPOS; p += 256) {
+    const int row = I * GT + p / GT, col = J * GT + p % GT;
     const bool inb = row < N && col < N;
     if (CPLX) {
       const float2 v = inb ? ((const float2*)Pm)[(size_t)row * N + col] : make_float2(0.f, 0.f);
-      Pt[(t * GPOS + p) * 2] = v.x;
-      Pt[(t * GPOS + p) * 2 + 1] = v.y;
+      Pt[p * 2] = v.x;
+      Pt[p * 2 + 1] = v.y;
     } else {
-      Pt[t * GPOS + p] = inb ? ((const float*)Pm)[(size_t)row * N + col] : 0.f;
+      Pt[p] = inb ? ((const float*)Pm)[(size_t)row * N + col] : 0.f;
     }
   }
-  const int K = 2 * L + 2;
+  const int K = L2 + 2;
   for (int a0 = 0; a0 < n_chunk; a0 += AC) {
     const int na = min(AC, n_chunk - a0);
     __syncthreads();
-    for (int it = tid; it < na * ntiles * GPOS; it += 256) {
-      const int p = it % GPOS, t = (it / GPOS) % ntiles, a = it / (GPOS * ntiles);
-      const int row = (t == 0 ? I : J) * GT + p / GT, col = (t == 0 ? J : I) * GT + p % GT;
+    for (int it = tid; it < na * GPOS; it += 256) {
+      const int p = it % GPOS, a = it / GPOS;
+      const int row = I * GT + p / GT, col = J * GT + p % GT;
       cplx64 g = {0.f, 0.f};
       if (row < N && col < N) g = G[(size_t)(a0 + a) * NN + (size_t)row * N + col];
-      Gs[((a * 2 + t) * GPOS + p) * 2] = g.re;
-      Gs[((a * 2 + t) * GPOS + p) * 2 + 1] = g.im;
+      Gs[(a * GPOS + p) * 2] = g.re;
+      Gs[(a * GPOS + p) * 2 + 1] = g.im;
     }
     __syncthreads();
-    for (int w = tid; w < K * ntiles; w += 256) {
-      const int k = w % K, t = w / K;
-      const int to = diag ? 0 : 1 - t;
-      const int rowb = (t == 0 ? I : J) * GT, colb = (t == 0 ? J : I) * GT;
+    for (int w = tid; w < 2 * K; w += 256) {
+      const int k = w % K, half = w / K;
       float sr[AC], si[AC];
 #pragma unroll
       for (int a = 0; a < AC; ++a) { sr[a] = 0.f; si[a] = 0.f; }
-      for (int p = 0; p < GPOS; ++p) {
+      for (int p = half * (GPOS / 2); p < (half + 1) * (GPOS / 2); ++p) {
         float br, bi = 0.f;
-        if (k < L) {                                   // M_{k+1}[p]
-          const float* s = S + (((size_t)t * GPOS + p) * L + k) * NPL;
-          br = s[0];
-          if (CPLX) bi = s[NPL - 1];
-        } else if (k < 2 * L) {                        // (M_{k-L+1}^H)[p] = conj(M[pT])
-          const int pT = (p % GT) * GT + p / GT;
-          const float* s = S + (((size_t)to * GPOS + pT) * L + (k - L)) * NPL;
-          br = s[0];
-          if (CPLX) bi = -s[NPL - 1];
-        } else if (k == 2 * L) {                       // P[p]
-          if (CPLX) { br = Pt[(t * GPOS + p) * 2]; bi = Pt[(t * GPOS + p) * 2 + 1]; }
-          else br = Pt[t * GPOS + p];
-        } else {                                       // identity
-          br = (rowb + p / GT == colb + p % GT) ? 1.f : 0.f;
+        if (k < L2) {
+          const float* sp = S + ((size_t)p * L2 + k) * NPL;
+          br = sp[0];
+          if (CPLX) bi = sp[NPL - 1];
+        } else if (k == L2) {
+          br = Pt[p * NPL];
+          if (CPLX) bi = Pt[p * NPL + NPL - 1];
+        } else {
+          br = (I * GT + p / GT == J * GT + p % GT) ? 1.f : 0.f;
         }
 #pragma unroll
-        for (int a = 0; a < AC; ++a) {                 // conj(g) * b
+        for (int a = 0; a < AC; ++a) {  // conj(g) * b
           if (a < na) {
-            const float gr = Gs[((a * 2 + t) * GPOS + p) * 2], gi = Gs[((a * 2 + t) * GPOS + p) * 2 + 1];
+            const float gr = Gs[(a * GPOS + p) * 2], gi = Gs[(a * GPOS + p) * 2 + 1];
             sr[a] += gr * br + gi * bi;
             si[a] += gr * bi - gi * br;
           }
         }
       }
-      for (int a = 0; a < na; ++a)
-        partial[(((size_t)q * n_chunk + a0 + a) * 2 + t) * K + k] = cplx64{sr[a], si[a]};
-      if (diag)
-        for (int a = 0; a < na; ++a) partial[(((size_t)q * n_chunk + a0 + a) * 2 + 1) * K + k] = cplx64{0.f, 0.f};
+      for (int a = 0; a < na; ++a) partial[(((size_t)q * n_chunk + a0 + a) * 2 + half) * K + k] = cplx64{sr[a], si[a]};
     }
   }
 }
 
-// T[a][k] = sum over pairs and both tiles, in a fixed order, in FP64.
-__global__ __launch_bounds__(256) void k_inner_sum(const cplx64* __restrict__ partial, int npairs, int n_chunk, int K,
+// T[a][k] = sum over tiles and both halves, in a fixed order, in FP64.
+__global__ __launch_bounds__(256) void k_inner_sum(const cplx64* __restrict__ partial, int ntiles, int n_chunk, int K,
                                                    int a_first, double* __restrict__ T) {
   __shared__ double rr[256], ri[256];
   const int a = blockIdx.y, k = blockIdx.x;
   double sr = 0.0, si = 0.0;
-  for (int q = threadIdx.x; q < npairs; q += 256)
+  for (int q = threadIdx.x; q < ntiles; q += 256)
     for (int t = 0; t < 2; ++t) {
       const cplx64 v = partial[(((size_t)q * n_chunk + a) * 2 + t) * K + k];
       sr += v.re;
@@ -236,12 +221,12 @@ static int grad_chunk(const Plan* p, int n_alpha) {
 
 static size_t inner_lds(const Plan* p) {
   const int NPL = p->cplx ? 2 : 1;
-  return ((size_t)2 * GPOS * p->L * NPL + 2 * GPOS * NPL + (size_t)AC * 2 * GPOS * 2) * sizeof(float);
+  return ((size_t)GPOS * 2 * p->L * NPL + GPOS * NPL + (size_t)AC * GPOS * 2) * sizeof(float);
 }
 
 size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   const int ch = grad_chunk(p, n_alpha);
-  const int N = p->N, nb = ceil_div(N, GT), npairs = nb * (nb + 1) / 2, K = 2 * p->L + 2;
+  const int N = p->N, nb = ceil_div(N, GT), npairs = nb * nb, K = 2 * p->L + 2;
   size_t s = 0;
   s += align_up((size_t)ch * N * N * 8, 256);                       // G chunk / Q(-alpha) chunk
   s += align_up((size_t)npairs * ch * 2 * K * 8, 256);              // partials
@@ -269,7 +254,7 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
                        int B, const void* GY, double* dalpha, void* dX, void* ws, size_t ws_bytes, hipStream_t s) {
   const int N = p->N, L = p->L, K = 2 * L + 2;
   const int ch = grad_chunk(p, n_alpha);
-  const int nb = ceil_div(N, GT), npairs = nb * (nb + 1) / 2;
+  const int nb = ceil_div(N, GT), npairs = nb * nb;  // 16x16 tiles
   if (ws_bytes < grad_ws_bytes(p, n_alpha, B, x_shared)) {
     set_error("grad workspace too small: %zu < %zu", ws_bytes, grad_ws_bytes(p, n_alpha, B, x_shared));
     return FGFRFT_ENOMEM;

@@ -1,7 +1,7 @@
 // Offline stage of Algorithm 1 on the GPU, in FP64:
 //   unitarity check, eigenvalue -1 eigenspace of F (pivoted Householder QR of F + I),
 //   projector P = W W^H, power recurrence M_n = F M_{n-1} with drift checks,
-//   and conversion of M_1..M_L and P to the resident stack format.
+//   and conversion of M_1..M_L, their adjoints M_1^H..M_L^H and P to the resident format.
 #include "internal.h"
 #include <math.h>
 #include <stdio.h>
@@ -439,6 +439,36 @@ __global__ __launch_bounds__(256) void k_store(const double* __restrict__ M, siz
   }
 }
 
+// out = conj(M)^T in the resident format (the negative powers F^{-n} P_c = M_n^H of
+// Proposition 2), through 32x32 LDS tiles so both the FP64 read and the store are coalesced.
+template <bool C>
+__global__ __launch_bounds__(256) void k_store_adjoint(const double* __restrict__ M, int N, int kind, void* __restrict__ out) {
+  __shared__ double tr[32][33], ti[32][33];
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi + r, j = bj + tx;
+    cd v = {0.0, 0.0};
+    if (i < N && j < N) v = ldz<C>(M, (size_t)i * N + j);
+    tr[r][tx] = v.re;
+    ti[r][tx] = v.im;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bj + r, j = bi + tx;   // out[i][j] = conj(M[j][i])
+    if (i >= N || j >= N) continue;
+    const size_t idx = (size_t)i * N + j;
+    const double re = tr[tx][r], im = -ti[tx][r];
+    if (kind == 0) {
+      if (C) ((cplx64*)out)[idx] = cplx64{(float)re, (float)im};
+      else ((float*)out)[idx] = (float)re;
+    } else {
+      if (C) ((uint2*)out)[idx] = make_uint2(bf16_pair(re), bf16_pair(im));
+      else ((uint32_t*)out)[idx] = bf16_pair(re);
+    }
+  }
+}
+
 // ============================================================================
 // host orchestration
 // ============================================================================
@@ -549,9 +579,17 @@ fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size
   double drift = 0.0;
   for (int n = 1; n <= L; ++n) {
     if ((rc = gemm_f64(C, false, N, N, N, Fd, N, Mprev, N, Mcur, N, s))) return rc;
+    // slots 0..L-1 hold F^n P_c = M_n, slots L..2L-1 hold F^{-n} P_c = M_n^H (Proposition 2)
     void* dst = (char*)p->stack + (size_t)(n - 1) * total * p->stack_elem_bytes;
-    if (C) k_store<true><<<grid_for(total), 256, 0, s>>>(Mcur, total, kind, dst);
-    else k_store<false><<<grid_for(total), 256, 0, s>>>(Mcur, total, kind, dst);
+    void* dsth = (char*)p->stack + (size_t)(L + n - 1) * total * p->stack_elem_bytes;
+    const dim3 tg(ceil_div(N, 32), ceil_div(N, 32));
+    if (C) {
+      k_store<true><<<grid_for(total), 256, 0, s>>>(Mcur, total, kind, dst);
+      k_store_adjoint<true><<<tg, 256, 0, s>>>(Mcur, N, kind, dsth);
+    } else {
+      k_store<false><<<grid_for(total), 256, 0, s>>>(Mcur, total, kind, dst);
+      k_store_adjoint<false><<<tg, 256, 0, s>>>(Mcur, N, kind, dsth);
+    }
     FG_LAUNCHED("store stack");
     if (n == (L + 1) / 2 || n == L) {
       if ((rc = gemm_f64(C, true, N, N, N, Mcur, N, Mcur, N, Abuf, N, s))) return rc;

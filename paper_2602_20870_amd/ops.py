@@ -94,18 +94,19 @@ class Plan:
         return self.info()["r_minus1"]
 
     def buffers(self):
-        """(stack, P) as torch views of the resident data (FP32 stack only)."""
+        """(stack, P) as torch views of the resident data: stack[n-1] = F^n P_c and
+        stack[L+n-1] = F^{-n} P_c = (F^n P_c)^H for n = 1..L (typed views for the FP32 stack)."""
         N, L = self.N, self.L
         s, p = ctypes.c_void_p(), ctypes.c_void_p()
         check(lib().fgfrft_plan_buffers(self._h, ctypes.byref(s), ctypes.byref(p)), "fgfrft_plan_buffers")
         base = self.persistent.data_ptr()
         es = 8 if self.complex else 4
-        stack = self.persistent[: L * N * N * es]
+        stack = self.persistent[: 2 * L * N * N * es]
         poff = p.value - base
         P = self.persistent[poff: poff + N * N * es]
         if self.stacktype == "fp32":
             dt = torch.complex64 if self.complex else torch.float32
-            stack = stack.view(dt).view(L, N, N)
+            stack = stack.view(dt).view(2 * L, N, N)
         P = P.view(torch.complex64 if self.complex else torch.float32).view(N, N)
         return stack, P
 

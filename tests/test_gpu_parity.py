@@ -74,8 +74,10 @@ def test_plan_projector_and_stack(case):
     stack, P = plan.buffers()
     assert np.max(np.abs(P.cpu().numpy() - ref.P)) < 1e-6
     S = stack.cpu().numpy()
+    assert S.shape[0] == 2 * L
     for n in range(1, L + 1):
         assert np.max(np.abs(S[n - 1] - ref.M[n])) < 1e-6, n
+        assert np.max(np.abs(S[L + n - 1] - ref.M[n].conj().T)) < 1e-6, n
 
 
 def test_plan_rejects_non_unitary():
