@@ -67,6 +67,44 @@ def cpu_baseline(F, alphas, L, budget_s=15.0):
                 seconds=t_acc)
 
 
+SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
+
+
+def serving_bench(n_requests=4000, warmup=500, rate=5000.0, L=32):
+    """p50/p99 latency of the continuous-batching server vs one launch per request.
+
+    8 resident plans from kNN graphs (k=10, Gaussian weights) on 3-D GMM points with
+    N in {256, 512, 1024, 1024, 2048, 2048, 4096, 4096}, L = 32; Poisson arrivals at
+    `rate` requests/s; each request: graph uniform, order U[-2, 2], 1..64 real signals.
+    """
+    import torch
+    import synth
+    from paper_2602_20870_amd import serve
+
+    t0 = time.time()
+    Fs = {g: synth.make_config("knn4096", seed=100 + g, N=N, with_signals=False)["F"]
+          for g, N in enumerate(SERVE_NS)}
+    rng = np.random.default_rng(7)
+    sig = {g: rng.standard_normal((F.shape[0], 64)).astype(np.float32) for g, F in Fs.items()}
+    srv = serve.Server(hbm_budget=120 << 30, K=16, bmax=64, slot_sets=2, use_graphs=True)
+    for g, F in Fs.items():
+        srv.add_plan(g, F, L)
+    torch.cuda.synchronize()
+    log(f"serving: {len(Fs)} plans resident ({srv.used / 1e9:.1f} GB) in {time.time() - t0:.1f}s")
+    trace = serve.poisson_trace(n_requests, rate, list(Fs), 64, seed=11)
+    batched = serve.run_trace(srv, trace, sig, warmup=warmup)
+    per_req = serve.run_trace_per_request(srv.plans, trace, sig, warmup=warmup)
+    worst = 0.0
+    for f, y in zip(batched.pop("futures"), per_req.pop("outputs")):
+        r = f.result()
+        worst = max(worst, float(np.linalg.norm(r - y) / max(np.linalg.norm(y), 1e-30)))
+    out = {"batched": batched, "one_launch_per_request": per_req, "max_rel_diff_between_modes": worst,
+           "rate_req_s": rate, "requests": n_requests, "warmup": warmup, "plans_N": list(SERVE_NS), "L": L}
+    del srv
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +114,7 @@ def main():
     ap.add_argument("--signals", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stacktype", default="fp32", choices=["fp32", "bf16x2"])
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -137,7 +176,7 @@ def main():
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
     app_gbs = apply_algorithmic_bytes(N, B, na) / (app_ms * 1e-3) / 1e9
     out = {
-        "metric": "F^alpha updates/s (update + apply to 64 signals per order), N=4096, L=32",
+        "metric": "F^alpha updates/s (update + apply to 64 signals per order), N=4096, L=32; serve p50/p99",
         "value": na / (ms_step * 1e-3),
         "unit": "updates/s",
         "n_gpus": 1,
@@ -160,8 +199,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_update"},
     }
-    del Q
+    del Q, X
     torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("serving trace ...")
+        out["serve"] = serving_bench()
+        b, p = out["serve"]["batched"], out["serve"]["one_launch_per_request"]
+        log(f"serve batched p50 {b['p50_ms']:.2f} ms p99 {b['p99_ms']:.2f} ms; "
+            f"per-request p50 {p['p50_ms']:.2f} ms p99 {p['p99_ms']:.2f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(F, alphas, L)

@@ -59,7 +59,7 @@ typedef enum {
   FGFRFT_IN_F64 = 1          /* float64 F (real orthogonal): real power stack, Im Q = sin(pi alpha) P */
 } fgfrft_intype;
 
-/* Storage of the resident power stack M_1..M_L. */
+/* Storage of the resident power stack (M_1..M_L and M_1^H..M_L^H). */
 typedef enum {
   FGFRFT_STACK_FP32 = 0,     /* float32 (real F) or complex64 (complex F)                  */
   FGFRFT_STACK_BF16X2 = 1    /* per real value a bf16 pair (hi, lo = bf16(x - hi)), 4 bytes */
@@ -89,7 +89,8 @@ FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stackty
  *      the range of F + I);
  *   3. M_0 = P_c = I - P, M_n = F M_{n-1} for n = 1..L, with the drift
  *      ||M_n^H M_n - P_c||_F / sqrt(N) checked at n = ceil(L/2) and n = L;
- *   4. M_1..M_L and P stored in `stacktype` format in `persistent_dev`.
+ *   4. M_1..M_L, their adjoints M_1^H..M_L^H (= F^{-n} P_c, Proposition 2)
+ *      and P stored in `stacktype` format in `persistent_dev`.
  * Synchronises `stream`.  F_dev is only read during the call.
  * On success *out receives a host-side handle (free with fgfrft_destroy);
  * persistent_dev must outlive it. */
@@ -106,9 +107,9 @@ FGFRFT_API fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype
 FGFRFT_API fgfrft_status fgfrft_plan_info(fgfrft_plan_t plan, int* r_minus1, double* unitarity_defect,
                                           double* drift, double* stop_norm, double* last_pivot_norm);
 
-/* Device pointers to the resident data: stack (M_1..M_L, L*N*N elements of
- * the stack format) and P (N*N, float32 for real F, complex64 for complex F).
- * For inspection and tests. */
+/* Device pointers to the resident data: stack (2L matrices of N*N elements of
+ * the stack format: slot n-1 holds M_n, slot L+n-1 holds M_n^H, n = 1..L) and
+ * P (N*N, float32 for real F, complex64 for complex F).  For inspection and tests. */
 FGFRFT_API fgfrft_status fgfrft_plan_buffers(fgfrft_plan_t plan, void** stack_dev, void** P_dev);
 
 FGFRFT_API void fgfrft_destroy(fgfrft_plan_t plan);  /* frees the host handle only */
@@ -131,6 +132,14 @@ FGFRFT_API size_t fgfrft_update_workspace_bytes(fgfrft_plan_t plan, int n_alpha)
  * accumulation. */
 FGFRFT_API fgfrft_status fgfrft_update(fgfrft_plan_t plan, const double* alphas, int n_alpha,
                                        void* Q_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The same update with the orders already in device memory (float64 [n_alpha], e.g.
+ * written by an earlier copy on the same stream).  Nothing is read back to the host,
+ * so the call may be recorded by stream capture (hipGraph) and replayed with new order
+ * values.  Orders cannot be range-checked on the host here: a plane whose order has
+ * |alpha| >= L or is not finite is filled with NaN.  Workspace as for fgfrft_update. */
+FGFRFT_API fgfrft_status fgfrft_update_dev(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha,
+                                           void* Q_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Apply to graph signals (Definition 2)

@@ -129,6 +129,18 @@ fgfrft_status fgfrft_update(fgfrft_plan_t plan, const double* alphas, int n_alph
   return update_launch(p, (const double*)ws_dev, n_alpha, Q_dev, ws_dev, s);
 }
 
+fgfrft_status fgfrft_update_dev(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha, void* Q_dev, void* ws_dev,
+                                size_t ws_bytes, void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  if (!alphas_dev || n_alpha < 1) { set_error("alphas_dev is NULL or n_alpha=%d < 1", n_alpha); return FGFRFT_EINVAL; }
+  if (!Q_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if ((uintptr_t)Q_dev % 8 || (uintptr_t)ws_dev % 256) { set_error("Q_dev must be 8-byte and ws_dev 256-byte aligned"); return FGFRFT_EINVAL; }
+  const size_t need = update_ws_bytes(p, n_alpha);
+  if (ws_bytes < need) { set_error("update workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  return update_launch(p, alphas_dev, n_alpha, Q_dev, ws_dev, (hipStream_t)stream);
+}
+
 size_t fgfrft_apply_operator_workspace_bytes(int N, int n_alpha, int B, int x_shared) {
   if (N < 1 || n_alpha < 1 || B < 1) return 0;
   return apply_ws_bytes(N, n_alpha, B, x_shared);

@@ -87,7 +87,7 @@ constexpr int AC = 4;
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, const void* __restrict__ Pm, int N, int L,
                                                int nb, const cplx64* __restrict__ G, int n_chunk,
-                                               cplx64* __restrict__ partial) {
+                                               double* __restrict__ partial) {
   constexpr int NPL = CPLX ? 2 : 1;
   extern __shared__ __align__(16) float sm[];
   const int L2 = 2 * L;
@@ -138,9 +138,9 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
     __syncthreads();
     for (int w = tid; w < 2 * K; w += 256) {
       const int k = w % K, half = w / K;
-      float sr[AC], si[AC];
+      double sr[AC], si[AC];   // FP64 accumulation (same FMA rate as FP32 here)
 #pragma unroll
-      for (int a = 0; a < AC; ++a) { sr[a] = 0.f; si[a] = 0.f; }
+      for (int a = 0; a < AC; ++a) { sr[a] = 0.0; si[a] = 0.0; }
       for (int p = half * (GPOS / 2); p < (half + 1) * (GPOS / 2); ++p) {
         float br, bi = 0.f;
         if (k < L2) {
@@ -156,28 +156,32 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
 #pragma unroll
         for (int a = 0; a < AC; ++a) {  // conj(g) * b
           if (a < na) {
-            const float gr = Gs[(a * GPOS + p) * 2], gi = Gs[(a * GPOS + p) * 2 + 1];
-            sr[a] += gr * br + gi * bi;
-            si[a] += gr * bi - gi * br;
+            const double gr = Gs[(a * GPOS + p) * 2], gi = Gs[(a * GPOS + p) * 2 + 1];
+            sr[a] += gr * (double)br + gi * (double)bi;
+            si[a] += gr * (double)bi - gi * (double)br;
           }
         }
       }
-      for (int a = 0; a < na; ++a) partial[(((size_t)q * n_chunk + a0 + a) * 2 + half) * K + k] = cplx64{sr[a], si[a]};
+      for (int a = 0; a < na; ++a) {
+        const size_t o = (((size_t)q * n_chunk + a0 + a) * 2 + half) * K + k;
+        partial[2 * o] = sr[a];
+        partial[2 * o + 1] = si[a];
+      }
     }
   }
 }
 
 // T[a][k] = sum over tiles and both halves, in a fixed order, in FP64.
-__global__ __launch_bounds__(256) void k_inner_sum(const cplx64* __restrict__ partial, int ntiles, int n_chunk, int K,
+__global__ __launch_bounds__(256) void k_inner_sum(const double* __restrict__ partial, int ntiles, int n_chunk, int K,
                                                    int a_first, double* __restrict__ T) {
   __shared__ double rr[256], ri[256];
   const int a = blockIdx.y, k = blockIdx.x;
   double sr = 0.0, si = 0.0;
   for (int q = threadIdx.x; q < ntiles; q += 256)
     for (int t = 0; t < 2; ++t) {
-      const cplx64 v = partial[(((size_t)q * n_chunk + a) * 2 + t) * K + k];
-      sr += v.re;
-      si += v.im;
+      const size_t o = (((size_t)q * n_chunk + a) * 2 + t) * K + k;
+      sr += partial[2 * o];
+      si += partial[2 * o + 1];
     }
   rr[threadIdx.x] = sr;
   ri[threadIdx.x] = si;
@@ -229,7 +233,7 @@ size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   const int N = p->N, nb = ceil_div(N, GT), npairs = nb * nb, K = 2 * p->L + 2;
   size_t s = 0;
   s += align_up((size_t)ch * N * N * 8, 256);                       // G chunk / Q(-alpha) chunk
-  s += align_up((size_t)npairs * ch * 2 * K * 8, 256);              // partials
+  s += align_up((size_t)npairs * ch * 2 * K * 16, 256);             // partials (complex FP64)
   s += align_up((size_t)n_alpha * K * 16, 256);                     // T
   s += align_up((size_t)ch * N * B * 8, 256);                       // dX chunk (shared X)
   s += update_ws_bytes(p, ch);
@@ -261,7 +265,7 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   }
   char* base = (char*)ws;
   cplx64* Gbuf = (cplx64*)base; base += align_up((size_t)ch * N * N * 8, 256);
-  cplx64* partial = (cplx64*)base; base += align_up((size_t)npairs * ch * 2 * K * 8, 256);
+  double* partial = (double*)base; base += align_up((size_t)npairs * ch * 2 * K * 16, 256);
   double* T = (double*)base; base += align_up((size_t)n_alpha * K * 16, 256);
   void* dXc = base; base += align_up((size_t)ch * N * B * 8, 256);
   void* uws = base; base += update_ws_bytes(p, ch);

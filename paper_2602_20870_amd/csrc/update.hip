@@ -55,16 +55,21 @@ __global__ __launch_bounds__(256) void k_coef(const double* __restrict__ alphas,
   if (a >= n_pad) return;
   const bool va = a < n_alpha;
   const double al = va ? alphas[a] : 0.0;
+  const bool bad = va && !(fabs(al) < (double)L);   // only reachable through the device-order entry
   double c = 0.0;
   if (va && k < L) c = sinc_pi(al - (double)(k + 1));
   else if (va && k < 2 * L) c = sinc_pi(al + (double)(k - L + 1));
+  if (bad) c = __builtin_nan("");
   uint16_t h, l;
   split16<BF>(c, h, l);
   uint16_t* row = table + (size_t)a * 2 * KP;
   row[k] = h;
   row[KP + k] = l;
   if (k == 0) {
-    if (va) {
+    if (bad) {
+      const float nan = __builtin_nanf("");
+      epi[a] = make_float4(nan, nan, nan, 0.f);
+    } else if (va) {
       const double c0 = sinc_pi(al);
       epi[a] = make_float4((float)(cospi(al) - c0), (float)sinpi(al), (float)c0, 0.f);
     } else {

@@ -124,6 +124,28 @@ class Plan:
                                _stream(stream)), "fgfrft_update")
         return out
 
+    def update_dev(self, alphas_dev: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """Update with the orders already on the device (float64 cuda tensor); capturable.
+
+        Orders with |alpha| >= L give NaN planes (no host-side check is possible).
+        """
+        if alphas_dev.dtype != torch.float64 or not alphas_dev.is_cuda or not alphas_dev.is_contiguous():
+            raise ValueError("alphas_dev must be a contiguous float64 cuda tensor")
+        n = alphas_dev.numel()
+        if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() < n * self.N * self.N:
+            raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*N elements")
+        L_ = lib()
+        need = L_.fgfrft_update_workspace_bytes(self._h, n)
+        if ws is None or ws.numel() < need:
+            ws = _workspace(need, self.device)
+        check(L_.fgfrft_update_dev(self._h, _ptr(alphas_dev), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+              "fgfrft_update_dev")
+        return out
+
+    def update_workspace_bytes(self, n_alpha: int) -> int:
+        return int(lib().fgfrft_update_workspace_bytes(self._h, n_alpha))
+
     def apply(self, alphas, X: torch.Tensor, chunk: int = 0, stream=None) -> torch.Tensor:
         """Y[a] = Q(alphas[a]) X[a] with X [n_alpha, N, B] or a shared [N, B] block."""
         a = _alphas(alphas)
@@ -175,7 +197,7 @@ def _check_signal(X: torch.Tensor, n: int, N: int, x_shared: bool) -> int:
 
 
 def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_real: bool = False,
-                   stream=None) -> torch.Tensor:
+                   out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Y[a] = op(Q[a]) X[a] for a complex64 operator batch Q [n, N, N]."""
     if Q.dtype != torch.complex64 or not Q.is_contiguous() or Q.dim() != 3:
         raise ValueError("Q must be contiguous complex64 [n, N, N]")
@@ -183,9 +205,17 @@ def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_re
     x_shared = X.dim() == 2
     B = X.shape[-1]
     xc = _check_signal(X, n, N, x_shared)
-    Y = torch.empty((n, N, B), dtype=torch.float32 if y_real else torch.complex64, device=Q.device)
+    ydt = torch.float32 if y_real else torch.complex64
+    if out is None:
+        Y = torch.empty((n, N, B), dtype=ydt, device=Q.device)
+    else:
+        if out.dtype != ydt or not out.is_contiguous() or tuple(out.shape) != (n, N, B):
+            raise ValueError("out has the wrong dtype, shape or layout")
+        Y = out
     L_ = lib()
-    ws = _workspace(L_.fgfrft_apply_operator_workspace_bytes(N, n, B, int(x_shared)), Q.device)
+    need = L_.fgfrft_apply_operator_workspace_bytes(N, n, B, int(x_shared))
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, Q.device)
     check(L_.fgfrft_apply_operator(_ptr(Q), N, n, int(adjoint), _ptr(X), xc, int(x_shared), B, _ptr(Y), int(y_real),
                                    _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply_operator")
     return Y

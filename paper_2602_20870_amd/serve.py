@@ -1,0 +1,266 @@
+"""Continuous-batching server for FGFRFT requests over resident plans (one GPU).
+
+A request is (graph id, order alpha, signal block X [N, B]).  The server keeps one
+plan per graph resident in HBM (admitted only if its footprint fits the budget) and,
+per plan, S slot sets: static device buffers for up to K orders (orders, signals,
+operators, outputs, workspaces) plus pinned host staging.  Each scheduling step
+  * admits arrived requests into the pending queue,
+  * retires finished batches (event query), hands results to their futures and
+    frees their slot set,
+  * for every plan with pending requests and a free slot set, coalesces up to K of
+    its requests into one batch: one fused operator-update launch for all their
+    orders followed by one apply launch, replayed from a captured hipGraph for the
+    batch-size bucket, on the slot set's own stream (batches of different plans
+    overlap on the device).
+Requests that arrive while batches run wait only until a slot set of their plan is
+free, not until the whole device drains.  Each order's plane is computed
+independently of the other orders of its batch, so a result is the same alone and
+in any mix (tested).
+"""
+from __future__ import annotations
+
+import collections
+import time
+from concurrent.futures import Future
+
+import numpy as np
+import torch
+
+from .ops import Plan, apply_operator
+
+BUCKETS = (1, 2, 4, 8, 16, 32)
+
+
+class AdmissionError(RuntimeError):
+    """A plan does not fit the server's HBM budget."""
+
+
+class _SlotSet:
+    def __init__(self, plan: Plan, K: int, bmax: int, device, use_graphs: bool):
+        N = plan.N
+        self.K, self.bmax = K, bmax
+        self.stream = torch.cuda.Stream(device=device)
+        self.alphas = torch.zeros(K, dtype=torch.float64, device=device)
+        self.X = torch.zeros((K, N, bmax), dtype=torch.float32, device=device)
+        self.Q = torch.empty((K, N, N), dtype=torch.complex64, device=device)
+        self.Y = torch.empty((K, N, bmax), dtype=torch.complex64, device=device)
+        self.uws = torch.empty(plan.update_workspace_bytes(K), dtype=torch.uint8, device=device)
+        from ._lib import lib
+        self.aws = torch.empty(max(256, int(lib().fgfrft_apply_operator_workspace_bytes(N, K, bmax, 0))),
+                               dtype=torch.uint8, device=device)
+        self.h_alphas = torch.zeros(K, dtype=torch.float64).pin_memory()
+        self.h_X = torch.zeros((K, N, bmax), dtype=torch.float32).pin_memory()
+        self.h_Y = torch.empty((K, N, bmax), dtype=torch.complex64).pin_memory()
+        self.plan = plan
+        self.graphs = {}
+        self.batch = None
+        self.event = None
+        if use_graphs:
+            self._capture()
+
+    def _run(self, k: int):
+        self.plan.update_dev(self.alphas[:k], out=self.Q[:k], ws=self.uws)
+        apply_operator(self.Q[:k], self.X[:k], out=self.Y[:k], ws=self.aws)
+
+    def _capture(self):
+        with torch.cuda.stream(self.stream):
+            for k in BUCKETS:
+                if k <= self.K:
+                    self._run(k)     # eager warm-up (kernel attributes, code objects)
+        self.stream.synchronize()
+        for k in BUCKETS:
+            if k > self.K:
+                continue
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=self.stream):
+                self._run(k)
+            self.graphs[k] = g
+        self.stream.synchronize()
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.alphas, self.X, self.Q, self.Y, self.uws, self.aws))
+
+    def launch(self, batch):
+        n = len(batch)
+        k = next(b for b in BUCKETS if b >= n) if self.graphs else n
+        # padding orders get alpha = 0 (a valid order); padding rows and signal columns of X
+        # are left as they are: every order's plane and every signal column is computed
+        # independently (per-column scales in the apply), and padded outputs are never returned
+        self.h_alphas[n:k] = 0.0
+        for i, r in enumerate(batch):
+            self.h_alphas[i] = r.alpha
+            self.h_X[i, :, : r.B] = r.X
+        with torch.cuda.stream(self.stream):
+            self.alphas.copy_(self.h_alphas, non_blocking=True)
+            self.X[:k].copy_(self.h_X[:k], non_blocking=True)
+            if self.graphs:
+                self.graphs[k].replay()
+            else:
+                self._run(k)
+            self.h_Y[:n].copy_(self.Y[:n], non_blocking=True)
+            self.event = torch.cuda.Event()
+            self.event.record(self.stream)
+        self.batch = batch
+
+    def done(self) -> bool:
+        return self.batch is not None and self.event.query()
+
+    def retire(self, now: float):
+        for i, r in enumerate(self.batch):
+            r.t_done = now
+            r.future.set_result(self.h_Y[i, :, : r.B].numpy().copy())
+        self.batch = None
+        self.event = None
+
+
+class _Request:
+    __slots__ = ("gid", "alpha", "X", "B", "t_arrive", "t_done", "future")
+
+    def __init__(self, gid, alpha, X, t_arrive):
+        self.gid, self.alpha = gid, float(alpha)
+        self.X = torch.as_tensor(np.asarray(X, dtype=np.float32))
+        self.B = self.X.shape[1]
+        self.t_arrive, self.t_done = t_arrive, None
+        self.future = Future()
+
+
+class Server:
+    """Continuous-batching FGFRFT server over resident plans.
+
+    hbm_budget: bytes of device memory the server may hold (plans + slot sets).
+    K: orders per batch (one fused update launch); bmax: largest signal block;
+    slot_sets: batches of one plan that may be in flight at once.
+    """
+
+    def __init__(self, hbm_budget: int, K: int = 16, bmax: int = 64, slot_sets: int = 2, use_graphs: bool = True,
+                 device: str = "cuda:0"):
+        self.budget, self.used = int(hbm_budget), 0
+        self.K, self.bmax, self.S = K, bmax, slot_sets
+        self.use_graphs = use_graphs
+        self.device = torch.device(device)
+        self.plans = {}
+        self.slots = {}
+        self.pending = collections.defaultdict(collections.deque)
+        self.inflight = 0
+
+    # ------------------------------------------------------------------ admission
+    def footprint(self, N: int, L: int) -> int:
+        from ._lib import lib
+        import ctypes
+        pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        lib().fgfrft_plan_bytes(N, L, 1, 0, ctypes.byref(pb), ctypes.byref(sb))
+        per_set = self.K * N * N * 8 + self.K * N * self.bmax * (4 + 8)
+        return int(pb.value) + self.S * per_set
+
+    def add_plan(self, gid, F: np.ndarray, L: int) -> None:
+        """Make graph `gid` resident; raises AdmissionError if it does not fit the budget."""
+        N = F.shape[0]
+        need = self.footprint(N, L)
+        if self.used + need > self.budget:
+            raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {need / 1e9:.2f} GB; "
+                                 f"{(self.budget - self.used) / 1e9:.2f} GB left")
+        plan = Plan(torch.from_numpy(np.ascontiguousarray(F)).to(self.device), L)
+        sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs) for _ in range(self.S)]
+        self.plans[gid] = plan
+        self.slots[gid] = sets
+        self.used += need
+
+    # ------------------------------------------------------------------ requests
+    def submit(self, gid, alpha: float, X, t_arrive: float | None = None) -> Future:
+        if gid not in self.plans:
+            raise KeyError(f"graph {gid} is not resident")
+        plan = self.plans[gid]
+        if not abs(alpha) < plan.L:
+            raise ValueError(f"order {alpha} outside (-L, L)")
+        r = _Request(gid, alpha, X, time.perf_counter() if t_arrive is None else t_arrive)
+        if r.X.shape[0] != plan.N or not 1 <= r.B <= self.bmax:
+            raise ValueError("X must be [N, B] with 1 <= B <= bmax")
+        self.pending[gid].append(r)
+        return r.future
+
+    def step(self) -> int:
+        """Retire finished batches and launch new ones; returns the number of batches launched."""
+        now = time.perf_counter()
+        for sets in self.slots.values():
+            for s in sets:
+                if s.done():
+                    s.retire(now)
+                    self.inflight -= 1
+        launched = 0
+        for gid, q in self.pending.items():
+            while q:
+                free = next((s for s in self.slots[gid] if s.batch is None), None)
+                if free is None:
+                    break
+                batch = [q.popleft() for _ in range(min(self.K, len(q)))]
+                free.launch(batch)
+                self.inflight += 1
+                launched += 1
+        return launched
+
+    def busy(self) -> bool:
+        return self.inflight > 0 or any(self.pending.values())
+
+    def drain(self):
+        while self.busy():
+            if not self.step():
+                time.sleep(20e-6)
+
+
+# ---------------------------------------------------------------------- workload driver
+def poisson_trace(n: int, rate: float, gids, B_max: int, seed: int = 0):
+    """Arrival times (s), graph ids (uniform), orders U[-2, 2], block sizes U{1..B_max}."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    g = rng.integers(0, len(gids), size=n)
+    a = rng.uniform(-2.0, 2.0, size=n)
+    b = rng.integers(1, B_max + 1, size=n)
+    return t, [gids[i] for i in g], a, b
+
+
+def run_trace(server: Server, trace, signals: dict, warmup: int = 0) -> dict:
+    """Replay a trace in real time; latency = completion - arrival per request."""
+    t_arr, gids, alphas, Bs = trace
+    futures, reqs = [], []
+    t0 = time.perf_counter()
+    i, n = 0, len(t_arr)
+    while i < n or server.busy():
+        now = time.perf_counter() - t0
+        while i < n and t_arr[i] <= now:
+            X = signals[gids[i]][:, : Bs[i]]
+            futures.append(server.submit(gids[i], alphas[i], X, t_arrive=t0 + t_arr[i]))
+            reqs.append(server.pending[gids[i]][-1])
+            i += 1
+        if not server.step():
+            nxt = t_arr[i] - (time.perf_counter() - t0) if i < n else 20e-6
+            time.sleep(max(0.0, min(nxt, 200e-6)))
+    wall = time.perf_counter() - t0
+    lat = np.array([r.t_done - r.t_arrive for r in reqs[warmup:]])
+    return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                mean_ms=float(lat.mean() * 1e3), requests=len(lat), wall_s=wall,
+                throughput_req_s=len(reqs) / wall, futures=futures)
+
+
+def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0) -> dict:
+    """Baseline: one update launch and one apply launch per request, in arrival order."""
+    t_arr, gids, alphas, Bs = trace
+    t0 = time.perf_counter()
+    lat = []
+    dev = next(iter(plans.values())).device
+    outs = []
+    for i in range(len(t_arr)):
+        now = time.perf_counter() - t0
+        if t_arr[i] > now:
+            time.sleep(t_arr[i] - now)
+        p = plans[gids[i]]
+        X = torch.from_numpy(np.ascontiguousarray(signals[gids[i]][:, : Bs[i]], dtype=np.float32)).to(dev)[None]
+        Q = p.update([alphas[i]])
+        Y = apply_operator(Q, X)
+        y = Y[0].cpu().numpy()
+        outs.append(y)
+        lat.append(time.perf_counter() - t0 - t_arr[i])
+    wall = time.perf_counter() - t0
+    lat = np.array(lat[warmup:])
+    return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                mean_ms=float(lat.mean() * 1e3), requests=len(lat), wall_s=wall,
+                throughput_req_s=len(t_arr) / wall, outputs=outs)

@@ -1,0 +1,186 @@
+"""GPU tests of the differentiable form, the device-order update and the serving loop,
+all through the C ABI and compared with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_common import TOL_FP32, announce, rel_fro, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _orth(n, r, seed):
+    rng = np.random.default_rng(seed)
+    rest = n - r
+    d = np.zeros((n, n))
+    d[: 2 * (rest // 2), : 2 * (rest // 2)] = synth.rotation_blocks(rng.uniform(0.05, np.pi - 0.3, rest // 2))
+    k = 2 * (rest // 2)
+    if rest % 2:
+        d[k, k] = 1.0
+        k += 1
+    for i in range(k, n):
+        d[i, i] = -1.0
+    v, rr = np.linalg.qr(rng.standard_normal((n, n)))
+    v = v * np.sign(np.diag(rr))[None, :]
+    return v @ d @ v.T
+
+
+# ----------------------------------------------------------------------------
+# differentiable form
+# ----------------------------------------------------------------------------
+def test_autograd_function_matches_oracle_gradient():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import FGFRFTFunction, Plan
+    announce("autograd N=48 L=8")
+    N, L, B = 48, 8, 5
+    F = _orth(N, 2, 3)
+    rng = np.random.default_rng(0)
+    alphas = np.array([0.55, -1.2, 0.3])
+    X = rng.standard_normal((3, N, B)).astype(np.float32)
+    T = (rng.standard_normal((3, N, B)) + 1j * rng.standard_normal((3, N, B))).astype(np.complex64)
+    plan = Plan(torch.from_numpy(F).cuda(), L)
+    Xt = torch.from_numpy(X).cuda().requires_grad_(True)
+    at = torch.tensor(alphas, dtype=torch.float64, requires_grad=True)
+    Y = FGFRFTFunction.apply(Xt, at, plan)
+    loss = (Y - torch.from_numpy(T).cuda()).abs().pow(2).sum()
+    loss.backward()
+    ref = O.Plan(F, L)
+    GY = np.stack([2 * (ref.combine(a) @ X[i].astype(np.float64) - T[i]) for i, a in enumerate(alphas)])
+    dal_ref, dX_ref = O.grad(ref.P, ref.M, alphas, X.astype(np.float64), GY)
+    assert np.max(np.abs(at.grad.numpy() - dal_ref)) <= TOL_FP32 * np.max(np.abs(dal_ref))
+    assert rel_fro(Xt.grad.cpu().numpy(), dX_ref) <= TOL_FP32
+
+    # the order gradient also matches the eigenbasis form of Proposition 4 and finite differences
+    for i, a in enumerate(alphas):
+        D = O.dQ_dalpha_eigen(F, a, L, decomposition=ref.decomposition)
+        g_eig = float(np.real(np.sum((GY[i] @ X[i].astype(np.float64).T).conj() * D)))
+        assert abs(g_eig - dal_ref[i]) < 1e-9 * max(1, abs(g_eig))
+        h = 1e-3
+        lp = np.sum(np.abs(ref.combine(a + h) @ X[i] - T[i]) ** 2)
+        lm = np.sum(np.abs(ref.combine(a - h) @ X[i] - T[i]) ** 2)
+        assert abs((lp - lm) / (2 * h) - dal_ref[i]) < 1e-5 * max(1, abs(dal_ref[i]))
+
+
+def test_spectral_mask_pipeline_gradient():
+    """Per-channel orders in Q^{-a_c} diag(h_c) Q^{a_c} x_c on a kNN sphere graph (L=48)."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd.autograd import fgfrft
+    from paper_2602_20870_amd import Plan
+    announce("mask pipeline sphere N=256 L=48, 4 channels")
+    rng = np.random.default_rng(5)
+    F = synth.gft_from_shift(synth.laplacian(synth.knn_adjacency(synth.sphere_points(256, rng), 10)))
+    N, L, C, B = 256, 48, 4, 6
+    plan = Plan(torch.from_numpy(F).cuda(), L)
+    ref = O.Plan(F, L)
+    X = rng.standard_normal((C, N, B)).astype(np.float32)
+    H = rng.uniform(0.2, 1.0, (C, N, 1)).astype(np.float32)
+    Tgt = rng.standard_normal((C, N, B)).astype(np.float32)
+    alphas = np.array([0.4, -0.7, 1.1, 0.05])
+
+    def loss_oracle(al):
+        tot = 0.0
+        for c in range(C):
+            Z = ref.combine(al[c]) @ X[c]
+            Yc = ref.combine(-al[c]) @ (H[c] * Z)
+            tot += np.sum(np.abs(Yc - Tgt[c]) ** 2)
+        return tot
+
+    at = torch.tensor(alphas, dtype=torch.float64, requires_grad=True)
+    Xt = torch.from_numpy(X).cuda()
+    Z = fgfrft(Xt, at, plan)
+    Ht = torch.from_numpy(H).cuda()
+    Y = fgfrft((Ht * Z).contiguous(), -at, plan)
+    loss = (Y - torch.from_numpy(Tgt).cuda()).abs().pow(2).sum()
+    loss.backward()
+    g = at.grad.numpy()
+
+    # FP64 chain rule through both applications (Prop. 4 for Q'(alpha), Prop. 3 for the adjoint)
+    g_ref = np.empty(C)
+    for c in range(C):
+        a = alphas[c]
+        Xc = X[c].astype(np.float64)
+        Zc = ref.combine(a) @ Xc
+        Wc = H[c] * Zc
+        Yc = ref.combine(-a) @ Wc
+        GY = 2 * (Yc - Tgt[c])
+        d2 = -np.real(np.sum((GY @ Wc.conj().T).conj() * O.dQ_dalpha(ref.P, ref.M, -a)))
+        GZ = H[c] * (ref.combine(-a).conj().T @ GY)
+        d1 = np.real(np.sum((GZ @ Xc.T).conj() * O.dQ_dalpha(ref.P, ref.M, a)))
+        g_ref[c] = d1 + d2
+    # the FP64 reference agrees with Richardson-extrapolated central differences (h = 1e-3, 5e-4)
+    for c in range(C):
+        def fd(h):
+            ap, am = alphas.copy(), alphas.copy()
+            ap[c] += h
+            am[c] -= h
+            return (loss_oracle(ap) - loss_oracle(am)) / (2 * h)
+        rich = (4 * fd(5e-4) - fd(1e-3)) / 3
+        assert abs(rich - g_ref[c]) <= 1e-6 * max(1.0, np.max(np.abs(g_ref))), (c, rich, g_ref[c])
+    assert np.max(np.abs(g - g_ref)) <= TOL_FP32 * np.max(np.abs(g_ref)), (g, g_ref)
+
+
+# ----------------------------------------------------------------------------
+# device-order update (capturable entry point)
+# ----------------------------------------------------------------------------
+def test_update_dev_matches_host_orders_and_flags_out_of_range():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan
+    announce("update_dev")
+    F = _orth(70, 3, 9)
+    plan = Plan(torch.from_numpy(F).cuda(), 6)
+    al = np.array([0.3, -5.9, 2.0, 1.7])
+    Q1 = plan.update(al)
+    Q2 = torch.empty_like(Q1)
+    plan.update_dev(torch.from_numpy(al).cuda(), out=Q2)
+    assert torch.equal(Q1, Q2)
+    bad = np.array([0.3, 6.0, -7.5])
+    Q3 = torch.empty((3, 70, 70), dtype=torch.complex64, device="cuda")
+    plan.update_dev(torch.from_numpy(bad).cuda(), out=Q3)
+    q = Q3.cpu().numpy()
+    assert np.isfinite(q[0]).all() and np.isnan(q[1]).all() and np.isnan(q[2]).all()
+
+
+# ----------------------------------------------------------------------------
+# serving loop
+# ----------------------------------------------------------------------------
+def _server(torch, use_graphs, Ns=(64, 100, 256), L=10):
+    from paper_2602_20870_amd.serve import Server
+    srv = Server(hbm_budget=8 << 30, K=8, bmax=16, slot_sets=2, use_graphs=use_graphs)
+    Fs = {}
+    for i, N in enumerate(Ns):
+        F = _orth(N, i, 20 + i)
+        srv.add_plan(i, F, L)
+        Fs[i] = F
+    return srv, Fs
+
+
+def test_serving_result_alone_equals_result_in_mix_and_oracle():
+    torch = torch_cuda()
+    announce("serving alone vs mix")
+    srv, Fs = _server(torch, use_graphs=True)
+    rng = np.random.default_rng(2)
+    reqs = [(int(rng.integers(0, 3)), float(rng.uniform(-2, 2)), int(rng.integers(1, 17))) for _ in range(40)]
+    sig = {g: rng.standard_normal((F.shape[0], 16)).astype(np.float32) for g, F in Fs.items()}
+    # alone: one request at a time
+    alone = []
+    for g, a, b in reqs[:6]:
+        f = srv.submit(g, a, sig[g][:, :b])
+        srv.drain()
+        alone.append(f.result())
+    # in the mix: all requests at once (several batches per plan, overlapping streams)
+    fut = [srv.submit(g, a, sig[g][:, :b]) for g, a, b in reqs]
+    srv.drain()
+    mixed = [f.result() for f in fut]
+    for i in range(6):
+        assert np.array_equal(alone[i], mixed[i]), i
+    refs = {g: O.Plan(F, 10) for g, F in Fs.items()}
+    for (g, a, b), y in zip(reqs, mixed):
+        yr = refs[g].combine(a) @ sig[g][:, :b].astype(np.float64)
+        assert rel_fro(y, yr) <= TOL_FP32
+    # graph replays equal eager launches (several replays, eager work in between)
+    eager, _ = _server(torch, use_graphs=False)
+    fut_e = [eager.submit(g, a, sig[g][:, :b]) for g, a, b in reqs]
+    eager.drain()
+    for fe, y in zip(fut_e, mixed):
+        assert np.array_equal(fe.result(), y)

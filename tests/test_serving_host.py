@@ -1,0 +1,36 @@
+"""Host-side behaviour of the serving loop that needs no GPU: admission by HBM
+footprint and the Poisson trace generator."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2602_20870_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libfgfrft.so not built")
+
+
+def test_admission_refuses_plans_beyond_the_budget(built):
+    from paper_2602_20870_amd.serve import AdmissionError, Server
+    srv = Server(hbm_budget=1 << 20, K=4, bmax=8, slot_sets=1, use_graphs=False, device="cpu")
+    need = srv.footprint(128, 10)
+    assert need > 1 << 20
+    # stack (2L matrices), P and one slot set of operators and signal blocks
+    assert need >= 2 * 10 * 128 * 128 * 4 + 4 * 128 * 128 * 8
+    with pytest.raises(AdmissionError):
+        srv.add_plan(0, np.eye(128), 10)
+    assert srv.used == 0 and not srv.plans
+
+
+def test_poisson_trace_statistics():
+    from paper_2602_20870_amd.serve import poisson_trace
+    t, g, a, b = poisson_trace(20000, 5000.0, list(range(8)), 64, seed=1)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 2e-4) < 1e-5
+    assert np.all(gaps > 0)
+    assert set(g) == set(range(8)) and a.min() >= -2 and a.max() <= 2
+    assert b.min() == 1 and b.max() == 64
