@@ -25,6 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 31          # plain device copy used as the counter and bandwidth reference
+
+# HBM bytes per k_update launch on this workload, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch), each scaled by the same counter's reading for the plain
+# copy of COPY_BYTES that this script runs.  Valid only for the kernel sources with this digest:
+# once update.hip or internal.h change, the figure is reported as null until re-measured.
+UPDATE_TRAFFIC = {"fetch_bytes": 4413377972, "write_bytes": 34359739946,
+                  "source_sha256": "869ca1c95e03cf0853f188240bb6c9bc7459fa1fa1262b6ccc0ee088bb97eef2"}
 
 
 def log(msg):
@@ -39,6 +47,39 @@ def update_algorithmic_bytes(N, L, n_alpha):
 def apply_algorithmic_bytes(N, B, n_alpha):
     # per order: 8 N^2 (Q read) + 4 N B (x read) + 8 N B (y written)
     return n_alpha * (8.0 * N * N + 12.0 * N * B)
+
+
+def update_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("update.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2602_20870_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def update_traffic():
+    t = UPDATE_TRAFFIC
+    if t["source_sha256"] is None or t["source_sha256"] != update_source_digest():
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
+def copy_bandwidth(dev, reps=5):
+    """Plain device-to-device copy of COPY_BYTES (read + write), GB/s over `reps` launches."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES, "ms": ms, "GBps": 2 * COPY_BYTES / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(F, alphas, L, budget_s=15.0):
@@ -197,10 +238,12 @@ def main():
         "plan_s": plan_s,
         "plan_info": info,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_update"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": update_traffic(), "kernel": "k_update"},
     }
     del Q, X
     torch.cuda.empty_cache()
+    out["copy_reference"] = copy_bandwidth(dev)
+    log(f"plain copy {out['copy_reference']['GBps']:.0f} GB/s")
     if not args.no_serve:
         log("serving trace ...")
         out["serve"] = serving_bench()

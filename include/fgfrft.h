@@ -65,6 +65,13 @@ typedef enum {
   FGFRFT_STACK_BF16X2 = 1    /* per real value a bf16 pair (hi, lo = bf16(x - hi)), 4 bytes */
 } fgfrft_stacktype;
 
+/* Which operator the plan's online stage produces. */
+typedef enum {
+  FGFRFT_FORM_SPLIT = 0,     /* Definition 1: the -1 eigenspace is split off (P), powers act on P_c */
+  FGFRFT_FORM_STANDARD = 1   /* the plain truncated series sum_{n=-L}^{L} c_n(alpha) F^n without the
+                                split (P = 0, M_0 = I): the ablation of Sec. IV-F / Table VI */
+} fgfrft_form;
+
 typedef struct fgfrft_plan_s* fgfrft_plan_t;
 
 /* ---------------------------------------------------------------------------
@@ -79,7 +86,9 @@ FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stackty
                                            size_t* persistent, size_t* scratch);
 
 /* Build a plan for the unitary F (N x N, row-major, device, float64 or
- * complex128 per `intype`).  On the GPU, in FP64:
+ * complex128 per `intype`) and the operator `form` (fgfrft_form).  On the GPU,
+ * in FP64 (steps 2 and 3 only for FGFRFT_FORM_SPLIT; the standard form takes
+ * P = 0, M_0 = I and reports r_minus1 = 0):
  *   1. unitarity check max|F^H F - I| <= 1e-10, else FGFRFT_ENOTUNITARY;
  *   2. the eigenvalue -1 eigenspace as the null space of F + I, found by
  *      Householder QR with column pivoting of F + I; the pivoted QR stops
@@ -95,7 +104,7 @@ FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stackty
  * On success *out receives a host-side handle (free with fgfrft_destroy);
  * persistent_dev must outlive it. */
 FGFRFT_API fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stacktype,
-                                     double tau, void* persistent_dev, size_t persistent_bytes,
+                                     int form, double tau, void* persistent_dev, size_t persistent_bytes,
                                      void* scratch_dev, size_t scratch_bytes, void* stream,
                                      fgfrft_plan_t* out);
 
@@ -186,9 +195,9 @@ FGFRFT_API size_t fgfrft_grad_workspace_bytes(fgfrft_plan_t plan, int n_alpha, i
  *             + Re( j pi e^{j pi alpha_a} <G_a, P> ),
  *   with G_a = GY[a] X[a]^H and <A, B> = sum_ij conj(A_ij) B_ij;
  * dalpha is a host array of n_alpha doubles, written after the stream has
- * been synchronised.  The inner products are formed on the GPU in FP32 with
- * a fixed-order two-pass reduction (deterministic); the final combination
- * with c_n'(alpha) is FP64.
+ * been synchronised.  G_a is formed on the GPU in FP32; the inner products
+ * with the stack accumulate in FP64 per tile and are summed over tiles in a
+ * fixed order (deterministic); the final combination with c_n'(alpha) is FP64.
  * dX_dev (may be NULL): Q(alpha_a)^H GY[a], float32 (real part) when
  * x_complex = 0, complex64 otherwise, shaped like X (summed over orders when
  * x_shared = 1). */

@@ -15,7 +15,7 @@ P_size_t = ctypes.POINTER(ctypes.c_size_t)
 # name -> (restype, argtypes); every symbol declared in include/fgfrft.h
 SIGNATURES = {
     "fgfrft_plan_bytes": (c_int, [c_int, c_int, c_int, c_int, P_size_t, P_size_t]),
-    "fgfrft_plan": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_double, c_void_p, c_size_t, c_void_p,
+    "fgfrft_plan": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_double, c_void_p, c_size_t, c_void_p,
                             c_size_t, c_void_p, ctypes.POINTER(c_void_p)]),
     "fgfrft_plan_info": (c_int, [c_void_p, P_int, P_double, P_double, P_double, P_double]),
     "fgfrft_plan_buffers": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),

@@ -58,7 +58,8 @@ fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype, size_t*
   return FGFRFT_OK;
 }
 
-fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stacktype, double tau, void* persistent_dev,
+fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stacktype, int form, double tau,
+                          void* persistent_dev,
                           size_t persistent_bytes, void* scratch_dev, size_t scratch_bytes, void* stream,
                           fgfrft_plan_t* out) {
   if (!out) { set_error("out is NULL"); return FGFRFT_EINVAL; }
@@ -66,6 +67,7 @@ fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stack
   size_t need_p = 0, need_s = 0;
   fgfrft_status rc = fgfrft_plan_bytes(N, L, intype, stacktype, &need_p, &need_s);
   if (rc) return rc;
+  if (form != FGFRFT_FORM_SPLIT && form != FGFRFT_FORM_STANDARD) { set_error("bad form %d", form); return FGFRFT_EINVAL; }
   if (!F_dev || !persistent_dev || !scratch_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
   if (persistent_bytes < need_p) { set_error("persistent buffer %zu < %zu bytes", persistent_bytes, need_p); return FGFRFT_ENOMEM; }
   if (scratch_bytes < need_s) { set_error("scratch buffer %zu < %zu bytes", scratch_bytes, need_s); return FGFRFT_ENOMEM; }
@@ -77,6 +79,7 @@ fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stack
   p->LP = L <= 32 ? 32 : 64;
   p->cplx = intype == FGFRFT_IN_C128;
   p->stacktype = stacktype;
+  p->form = form;
   p->tau = tau;
   p->stack_elem_bytes = stack_elem_bytes(p->cplx);
   p->stack = persistent_dev;

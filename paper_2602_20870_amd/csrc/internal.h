@@ -30,6 +30,7 @@ struct Plan {
   int N = 0, L = 0, LP = 0;        // LP: L padded to a multiple of 32 (MFMA k extent)
   int cplx = 0;                    // 1: complex F, complex power stack
   int stacktype = 0;               // fgfrft_stacktype
+  int form = 0;                    // fgfrft_form
   int r_minus1 = 0;
   double unitarity_defect = 0, drift = 0, stop_norm = 0, last_pivot_norm = 0, tau = 1e-6;
   void* stack = nullptr;           // [L][N][N] elements (4 B real / 8 B complex)

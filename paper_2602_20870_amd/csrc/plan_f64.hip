@@ -533,32 +533,39 @@ fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size
     return FGFRFT_ENOTUNITARY;
   }
 
-  // ---- 2. pivoted Householder QR of F + I (column-major)
-  if (C) k_plus_identity_colmajor<true><<<grid_for(total), 256, 0, s>>>(Fd, N, Abuf);
-  else k_plus_identity_colmajor<false><<<grid_for(total), 256, 0, s>>>(Fd, N, Abuf);
-  FG_LAUNCHED("plus_identity");
-  if (C) k_colnorms<true><<<ceil_div(N, 4), 256, 0, s>>>(Abuf, N, cn2);
-  else k_colnorms<false><<<ceil_div(N, 4), 256, 0, s>>>(Abuf, N, cn2);
-  FG_LAUNCHED("colnorms");
-  FG_HIP(hipMemsetAsync(st, 0, sizeof(QRState), s));
-  const double tol2 = tau * tau;
-  for (int j = 0; j < N; ++j) {
-    if (C) k_qr_pivot_house<true><<<1, 1024, 0, s>>>(Abuf, N, j, cn2, taub, st, tol2);
-    else k_qr_pivot_house<false><<<1, 1024, 0, s>>>(Abuf, N, j, cn2, taub, st, tol2);
-    const int ncols = N - j - 1;
-    if (ncols > 0) {
-      if (C) k_qr_update<true><<<ceil_div(ncols, 4), 256, 0, s>>>(Abuf, N, j, cn2, taub, st);
-      else k_qr_update<false><<<ceil_div(ncols, 4), 256, 0, s>>>(Abuf, N, j, cn2, taub, st);
+  // ---- 2. pivoted Householder QR of F + I (column-major); the standard form has no split
+  const bool split = p->form == FGFRFT_FORM_SPLIT;
+  int k = N;
+  p->r_minus1 = 0;
+  p->stop_norm = 0.0;
+  p->last_pivot_norm = 0.0;
+  if (split) {
+    if (C) k_plus_identity_colmajor<true><<<grid_for(total), 256, 0, s>>>(Fd, N, Abuf);
+    else k_plus_identity_colmajor<false><<<grid_for(total), 256, 0, s>>>(Fd, N, Abuf);
+    FG_LAUNCHED("plus_identity");
+    if (C) k_colnorms<true><<<ceil_div(N, 4), 256, 0, s>>>(Abuf, N, cn2);
+    else k_colnorms<false><<<ceil_div(N, 4), 256, 0, s>>>(Abuf, N, cn2);
+    FG_LAUNCHED("colnorms");
+    FG_HIP(hipMemsetAsync(st, 0, sizeof(QRState), s));
+    const double tol2 = tau * tau;
+    for (int j = 0; j < N; ++j) {
+      if (C) k_qr_pivot_house<true><<<1, 1024, 0, s>>>(Abuf, N, j, cn2, taub, st, tol2);
+      else k_qr_pivot_house<false><<<1, 1024, 0, s>>>(Abuf, N, j, cn2, taub, st, tol2);
+      const int ncols = N - j - 1;
+      if (ncols > 0) {
+        if (C) k_qr_update<true><<<ceil_div(ncols, 4), 256, 0, s>>>(Abuf, N, j, cn2, taub, st);
+        else k_qr_update<false><<<ceil_div(ncols, 4), 256, 0, s>>>(Abuf, N, j, cn2, taub, st);
+      }
     }
+    FG_LAUNCHED("qr steps");
+    QRState hs;
+    FG_HIP(hipMemcpyAsync(&hs, st, sizeof(QRState), hipMemcpyDeviceToHost, s));
+    FG_HIP(hipStreamSynchronize(s));
+    k = hs.done ? hs.k : N;
+    p->r_minus1 = N - k;
+    p->stop_norm = hs.done ? hs.stop_norm : 0.0;
+    p->last_pivot_norm = hs.last_pivot;
   }
-  FG_LAUNCHED("qr steps");
-  QRState hs;
-  FG_HIP(hipMemcpyAsync(&hs, st, sizeof(QRState), hipMemcpyDeviceToHost, s));
-  FG_HIP(hipStreamSynchronize(s));
-  const int k = hs.done ? hs.k : N;
-  p->r_minus1 = N - k;
-  p->stop_norm = hs.done ? hs.stop_norm : 0.0;
-  p->last_pivot_norm = hs.last_pivot;
 
   // ---- 3. W, P = W W^H, P_c = I - P
   const int r = p->r_minus1;

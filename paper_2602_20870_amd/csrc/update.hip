@@ -6,11 +6,12 @@
 //
 // This is a contraction [n_alpha x 2L] . [2L x N^2] on the matrix cores.  A workgroup
 // owns a strip of TR rows x 64 columns of positions: it stages the 2L stack tiles of the
-// strip in LDS once, then its 4 waves produce those positions of Q for every order of the
-// call (all waves on the same group of 32 orders at a time), so
-// each stack element is read from HBM once per call and each store writes 256-byte runs
-// of a row.  The P and identity terms ride in one extra MFMA k-step whose B operand is
-// built in registers, so the epilogue is only the power-of-two unscale.
+// strip in LDS once (direct HBM-to-LDS loads), then its 4 waves produce those positions of
+// Q for every order of the call (all waves on the same group of 32 orders at a time), so
+// each stack element is read from HBM once per call.  With paired blocks a lane holds two
+// neighbouring positions and each store writes 512-byte runs of a row.  The P and identity
+// terms ride in one extra MFMA k-step whose B operand is built in registers, so the
+// epilogue is only the power-of-two unscale.
 //
 // Precision: each FP32 operand x is split into 16-bit parts hi = h(x), lo = h(x - hi);
 // the products hi*hi + hi*lo + lo*hi accumulate in FP32.  With fp16 parts (after a 2^12
@@ -79,6 +80,9 @@ __global__ __launch_bounds__(256) void k_coef(const double* __restrict__ alphas,
 }
 
 // ------------------------------------------------------------ update kernel (a-2)
+// s_waitcnt immediate (gfx9 encoding) that waits for vmcnt = 0 only (expcnt 7, lgkmcnt 15: no wait)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 __device__ __forceinline__ int swz(int p, int c) { return (c & ~7) | ((c ^ p) & 7); }
 
 template <bool BF>
@@ -106,223 +110,344 @@ __device__ __forceinline__ void split_f32(float x, short& hi, short& lo) {
   }
 }
 
-// Phase 1 stages the strip's 2L stack tiles in LDS as S[plane][pos][chunk] (chunk = 8 x 16-bit
-// values; chunks 0..KP/8-1 hold the hi parts of S_0..S_{KP-1}, KP/8..KP/4-1 the lo parts; chunk
-// index swizzled by position).  Phase 2 moves each wave's B fragments (its position block(s), all
-// k) into registers.  Phase 3 reuses the LDS for the coefficient table of up to CAP orders,
-// T[order][chunk] (same hi/lo chunking, swizzled by order) and E[order] = epi.  The order loop
-// then reads only LDS, so nothing in it waits on the memory counter that the stores also use.
-template <bool CPLX, int KP, int TR, bool BF, int NT, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_update(const void* __restrict__ stack, const void* __restrict__ Pm, int N,
-                                                   int L, int nJ, const uint16_t* __restrict__ table,
-                                                   const float4* __restrict__ epi, int n_alpha, int n_pad,
-                                                   cplx64* __restrict__ Q) {
+// One group of 32 orders (a0 .. a0+31, local table index g0 ..) for one 32-position block:
+// KS x 3 split products over the stack, 6 over the P/identity step, then 16 stores per lane
+// (lane: position p = blk*32 + l32; orders a0 + 8(r/4) + 4 lh + r%4).
+//
+// OFF32: the per-lane part of the store address, (4 lh N^2 + row N + col) * 8 bytes, fits 32 bits
+// (N <= 10240); the plane part is uniform, so every store is one scalar base plus one fixed 32-bit
+// vector offset and no per-store 64-bit vector addresses are kept in registers.
+template <bool CPLX, int KP, bool BF, bool OFF32>
+__device__ __forceinline__ void order_group(const shortx8* T, const float4* E, int g0, int a0, int n_alpha,
+                                            bool fast, int row, int col, int N, size_t NN, int l32, int lh,
+                                            const shortx8 (&bh)[CPLX ? 2 : 1][KP / 16],
+                                            const shortx8 (&bl)[CPLX ? 2 : 1][KP / 16], shortx8 bxh, shortx8 bxl,
+                                            cplx64* __restrict__ Q) {
   constexpr int NPL = CPLX ? 2 : 1;
   constexpr int CH = KP / 4, G8 = KP / 8, KS = KP / 16;
-  constexpr int PT = TR * TCOLS;          // positions per strip
-  constexpr int NBLK = PT / 32;           // 32-position MFMA column blocks
-  constexpr int NW = NT / 64;             // waves
-  constexpr int BPW = NBLK >= NW ? NBLK / NW : 1;   // blocks per wave
-  constexpr int CAP = KP <= 64 ? 256 : 128;         // orders per LDS table chunk
-  extern __shared__ __align__(16) shortx8 smem[];
-  shortx8* S = smem;                                          // phase 1: [NPL][PT][CH]
-  float* Pt = (float*)(smem + (size_t)NPL * PT * CH);         // phase 1: [PT][NPL]
-  shortx8* T = smem;                                          // phase 3: [CAP][CH]
-  float4* E = (float4*)(smem + (size_t)CAP * CH);             // phase 3: [CAP]
+  const float unscale = BF ? 1.0f : kUnscale;
+  const int al = g0 + l32;   // this lane's order (A row), local index
+  floatx16 acc_re = {}, acc_im = {};
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl) {
+    floatx16 acc = {};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const shortx8 aH = T[al * CH + swz(al, 2 * ks + lh)];
+      const shortx8 aL = T[al * CH + swz(al, G8 + 2 * ks + lh)];
+      acc = mfma16<BF>(aH, bh[pl][ks], acc);
+      acc = mfma16<BF>(aH, bl[pl][ks], acc);
+      acc = mfma16<BF>(aL, bh[pl][ks], acc);
+    }
+    if (pl == 0) acc_re = acc; else acc_im = acc;
+  }
+  // extra-step A rows: Re (cos - c_0, -sin, c_0), Im (sin, cos - c_0, 0) on k = 0..2
+  shortx8 xrH = {}, xrL = {}, xiH = {}, xiL = {};
+  if (lh == 0) {
+    const float4 e = E[al];
+    short h, l;
+    split_f32<BF>(e.x, h, l); xrH[0] = h; xrL[0] = l; xiH[1] = h; xiL[1] = l;
+    split_f32<BF>(-e.y, h, l); xrH[1] = h; xrL[1] = l;
+    split_f32<BF>(e.y, h, l); xiH[0] = h; xiL[0] = l;
+    split_f32<BF>(e.z, h, l); xrH[2] = h; xrL[2] = l;
+  }
+  acc_re = mfma16<BF>(xrH, bxh, acc_re);
+  acc_re = mfma16<BF>(xrH, bxl, acc_re);
+  acc_re = mfma16<BF>(xrL, bxh, acc_re);
+  acc_im = mfma16<BF>(xiH, bxh, acc_im);
+  acc_im = mfma16<BF>(xiH, bxl, acc_im);
+  acc_im = mfma16<BF>(xiL, bxh, acc_im);
+  if (OFF32) {
+    const uint32_t voff = (uint32_t)(((size_t)4 * lh * NN + (size_t)row * N + col) * sizeof(cplx64));
+    char* qa = (char*)(Q + (size_t)a0 * NN);
+    if (fast) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        *(cplx64*)(qa + (size_t)(8 * (r >> 2) + (r & 3)) * NN * sizeof(cplx64) + voff) =
+            cplx64{acc_re[r] * unscale, acc_im[r] * unscale};
+    } else if (row < N && col < N) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha)
+          *(cplx64*)(qa + (size_t)(8 * (r >> 2) + (r & 3)) * NN * sizeof(cplx64) + voff) =
+              cplx64{acc_re[r] * unscale, acc_im[r] * unscale};
+    }
+  } else {
+    cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
+    if (fast) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        ql[(size_t)(8 * (r >> 2) + (r & 3)) * NN] = cplx64{acc_re[r] * unscale, acc_im[r] * unscale};
+    } else if (row < N && col < N) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha)
+          ql[(size_t)(8 * (r >> 2) + (r & 3)) * NN] = cplx64{acc_re[r] * unscale, acc_im[r] * unscale};
+    }
+  }
+}
 
+// ---- staging layout
+// R[k][pos][plane] holds the strip's stack values exactly as stored in HBM (fp32, or one bf16
+// hi/lo pair per real value), k < KP (rows 2L..KP-1 stay zero), followed by Pt[pos][plane] (fp32).
+// The 16-bit split happens when a consumer moves its fragments into registers.
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Interior strip whose rows start 16-byte aligned: every instruction moves 1 KB of R (64 lanes
+// x 16 bytes) from HBM straight into LDS; producer wave pw of NPW issues instructions pw, pw+NPW, ..
+template <bool CPLX, int TR, int NPW>
+__device__ __forceinline__ void stage_direct(const void* __restrict__ stack, int N, int L, int row0, int col0, char* R,
+                                             int pw, int lane) {
+  constexpr int EB = CPLX ? 8 : 4, PT = TR * TCOLS;
+  const int ninst = 2 * L * PT * EB / 1024;      // 2L * PT * EB is a multiple of 1 KB (PT * EB >= 512)
+  const size_t NN = (size_t)N * N;
+  for (int i = pw; i < ninst; i += NPW) {
+    const int e0 = (i * 1024 + 16 * lane) / EB;  // first element of this lane's 16 bytes in R
+    const int k = e0 / PT, pos = e0 % PT;
+    const char* g = (const char*)stack + ((size_t)k * NN + (size_t)(row0 + pos / TCOLS) * N + col0 + pos % TCOLS) * EB;
+    __builtin_amdgcn_global_load_lds(g, (lds_void*)(R + i * 1024), 16, 0, 0);
+  }
+}
+
+// Any strip (edges, unaligned N): element by element through registers, zero outside the matrix.
+template <bool CPLX, int TR, int NTH>
+__device__ __forceinline__ void stage_generic(const void* __restrict__ stack, int N, int L, int row0, int col0,
+                                              char* R, int t) {
+  constexpr int NPL = CPLX ? 2 : 1, PT = TR * TCOLS;
+  const size_t NN = (size_t)N * N;
+  uint32_t* dst = (uint32_t*)R;
+  const uint32_t* src = (const uint32_t*)stack;
+  for (int e = t; e < 2 * L * PT; e += NTH) {
+    const int k = e / PT, pos = e % PT;
+    const int row = row0 + pos / TCOLS, col = col0 + pos % TCOLS;
+    const bool inb = row < N && col < N;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+      dst[e * NPL + pl] = inb ? src[((size_t)k * NN + (size_t)row * N + col) * NPL + pl] : 0u;
+  }
+}
+
+template <bool CPLX, int TR, int NTH>
+__device__ __forceinline__ void stage_p(const void* __restrict__ Pm, int N, int row0, int col0, float* Pt, int t) {
+  constexpr int NPL = CPLX ? 2 : 1, PT = TR * TCOLS;
+  for (int p = t; p < PT; p += NTH) {
+    const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
+    const bool inb = row < N && col < N;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) Pt[p * NPL + pl] = inb ? ((const float*)Pm)[((size_t)row * N + col) * NPL + pl] : 0.f;
+  }
+}
+
+// B fragments for this lane's position p of the strip (all k, split into 16-bit parts) and the
+// extra k-step operand (P_re, P_im, identity at k = 0..2 for lanes lh == 0, zero elsewhere).
+template <bool CPLX, int KP, int TR, bool BF>
+__device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const float* Pt, int N, int row0, int col0,
+                                                   int p, int lh, shortx8 (&bh)[CPLX ? 2 : 1][KP / 16],
+                                                   shortx8 (&bl)[CPLX ? 2 : 1][KP / 16], shortx8& bxh, shortx8& bxl) {
+  constexpr int NPL = CPLX ? 2 : 1;
+  constexpr int KS = KP / 16, PT = TR * TCOLS;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 16 * ks + 8 * lh + j;
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) {
+        const uint32_t bits = R[((size_t)k * PT + p) * NPL + pl];
+        short h, l;
+        if (BF) { h = (short)(bits & 0xffff); l = (short)(bits >> 16); }
+        else split_f32<false>(__builtin_bit_cast(float, bits), h, l);
+        bh[pl][ks][j] = h;
+        bl[pl][ks][j] = l;
+      }
+    }
+  bxh = shortx8{};
+  bxl = shortx8{};
+  if (lh == 0) {
+    const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
+    const float pr = CPLX ? Pt[2 * p] : Pt[p];
+    const float pi = CPLX ? Pt[2 * p + 1] : 0.f;
+    short h, l;
+    split_f32<BF>(pr, h, l);
+    bxh[0] = h; bxl[0] = l;
+    split_f32<BF>(pi, h, l);
+    bxh[1] = h; bxl[1] = l;
+    split_f32<BF>((row == col && row < N) ? 1.f : 0.f, h, l);
+    bxh[2] = h; bxl[2] = l;
+  }
+}
+
+template <bool CPLX, int KP, int TR, int CAP_ = (KP <= 64 ? 256 : 128)>
+struct StripLayout {
+  static constexpr int NPL = CPLX ? 2 : 1, PT = TR * TCOLS, CH = KP / 4;
+  static constexpr int CAP = CAP_;                                     // orders per LDS table chunk
+  static constexpr size_t RB = (size_t)KP * PT * NPL * 4;              // raw stack tiles
+  static constexpr size_t PB = ((size_t)PT * NPL * 4 + 15) / 16 * 16;  // P tile
+  static constexpr size_t TB = (size_t)CAP * CH * 16;                  // coefficient table
+  static constexpr size_t bytes = RB + PB + TB + (size_t)CAP * 16;      // + epilogue table
+};
+
+// Two 32-position blocks whose lanes hold the even (block 0) and odd (block 1) position of one
+// column pair: the same MFMA sequence per block as order_group, then one 16-byte store per order
+// and lane (two neighbouring complex values), so each half-wave writes a 512-byte row run.
+template <bool CPLX, int KP, bool BF, bool OFF32>
+__device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, int g0, int a0, int n_alpha, bool fast,
+                                           int row, int col, int N, size_t NN, int l32, int lh,
+                                           const shortx8 (&bh0)[CPLX ? 2 : 1][KP / 16],
+                                           const shortx8 (&bl0)[CPLX ? 2 : 1][KP / 16], shortx8 bxh0, shortx8 bxl0,
+                                           const shortx8 (&bh1)[CPLX ? 2 : 1][KP / 16],
+                                           const shortx8 (&bl1)[CPLX ? 2 : 1][KP / 16], shortx8 bxh1, shortx8 bxl1,
+                                           cplx64* __restrict__ Q) {
+  constexpr int NPL = CPLX ? 2 : 1;
+  constexpr int CH = KP / 4, G8 = KP / 8, KS = KP / 16;
+  const float unscale = BF ? 1.0f : kUnscale;
+  const int al = g0 + l32;
+  floatx16 re0 = {}, im0 = {}, re1 = {}, im1 = {};
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl) {
+    floatx16 c0 = {}, c1 = {};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const shortx8 aH = T[al * CH + swz(al, 2 * ks + lh)];
+      const shortx8 aL = T[al * CH + swz(al, G8 + 2 * ks + lh)];
+      c0 = mfma16<BF>(aH, bh0[pl][ks], c0);
+      c1 = mfma16<BF>(aH, bh1[pl][ks], c1);
+      c0 = mfma16<BF>(aH, bl0[pl][ks], c0);
+      c1 = mfma16<BF>(aH, bl1[pl][ks], c1);
+      c0 = mfma16<BF>(aL, bh0[pl][ks], c0);
+      c1 = mfma16<BF>(aL, bh1[pl][ks], c1);
+    }
+    if (pl == 0) { re0 = c0; re1 = c1; } else { im0 = c0; im1 = c1; }
+  }
+  shortx8 xrH = {}, xrL = {}, xiH = {}, xiL = {};
+  if (lh == 0) {
+    const float4 e = E[al];
+    short h, l;
+    split_f32<BF>(e.x, h, l); xrH[0] = h; xrL[0] = l; xiH[1] = h; xiL[1] = l;
+    split_f32<BF>(-e.y, h, l); xrH[1] = h; xrL[1] = l;
+    split_f32<BF>(e.y, h, l); xiH[0] = h; xiL[0] = l;
+    split_f32<BF>(e.z, h, l); xrH[2] = h; xrL[2] = l;
+  }
+  re0 = mfma16<BF>(xrH, bxh0, re0); re1 = mfma16<BF>(xrH, bxh1, re1);
+  re0 = mfma16<BF>(xrH, bxl0, re0); re1 = mfma16<BF>(xrH, bxl1, re1);
+  re0 = mfma16<BF>(xrL, bxh0, re0); re1 = mfma16<BF>(xrL, bxh1, re1);
+  im0 = mfma16<BF>(xiH, bxh0, im0); im1 = mfma16<BF>(xiH, bxh1, im1);
+  im0 = mfma16<BF>(xiH, bxl0, im0); im1 = mfma16<BF>(xiH, bxl1, im1);
+  im0 = mfma16<BF>(xiL, bxh0, im0); im1 = mfma16<BF>(xiL, bxh1, im1);
+  if (fast) {   // interior, full group of orders, N even: 16-byte aligned pairs
+    if (OFF32) {
+      const uint32_t voff = (uint32_t)(((size_t)4 * lh * NN + (size_t)row * N + col) * sizeof(cplx64));
+      char* qa = (char*)(Q + (size_t)a0 * NN);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        *(float4*)(qa + (size_t)(8 * (r >> 2) + (r & 3)) * NN * sizeof(cplx64) + voff) =
+            make_float4(re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale);
+    } else {
+      cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        *(float4*)(ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN) =
+            make_float4(re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale);
+    }
+  } else if (row < N) {
+    cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha) {
+        cplx64* q = ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN;
+        if (col < N) q[0] = cplx64{re0[r] * unscale, im0[r] * unscale};
+        if (col + 1 < N) q[1] = cplx64{re1[r] * unscale, im1[r] * unscale};
+      }
+  }
+}
+
+// Table chunk of ncap orders into LDS with direct HBM/L2-to-LDS loads: LDS 16-byte chunk m =
+// a * CH + c' receives table chunk a * CH + swz(a, c') (the swizzle is its own inverse), so a
+// lane's destination is contiguous per instruction as the direct loads require.  Rows past ncap
+// are not loaded (never read).  Wave w of NW.
+template <int KP, int NW>
+__device__ __forceinline__ void load_table_direct(const uint16_t* __restrict__ table, int c0, int ncap, shortx8* T,
+                                                  int w, int lane) {
+  constexpr int CH = KP / 4;
+  const shortx8* tsrc = (const shortx8*)(table + (size_t)c0 * 2 * KP);
+  const int nchunk = ncap * CH;                 // multiple of 64 (ncap is a multiple of 32, CH of 8)
+  for (int i = w; i * 64 < nchunk; i += NW) {
+    const int m = i * 64 + lane, a = m / CH, c = m % CH;
+    __builtin_amdgcn_global_load_lds((const void*)(tsrc + a * CH + swz(a, c)), (lds_void*)(T + i * 64), 16, 0, 0);
+  }
+}
+
+// Operator update kernel: one workgroup per strip of TR x 64 positions (two per CU).  It stages the
+// strip's 2L stack tiles in LDS with direct loads, moves each wave's B fragments into registers,
+// then reuses the LDS for the coefficient table, CAP orders at a time, and runs the order loop,
+// which touches only LDS, the matrix cores and stores: nothing in it waits on the memory counter
+// the stores also use, so the stores stream without drains.
+template <bool CPLX, int KP, int TR, bool BF, int NT, int MINW, bool OFF32, int CAPV, bool PAIR>
+__global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restrict__ stack, const void* __restrict__ Pm,
+                                                           int N, int L, int nJ, const uint16_t* __restrict__ table,
+                                                           const float4* __restrict__ epi, int n_alpha, int n_pad,
+                                                           cplx64* __restrict__ Q) {
+  using LY = StripLayout<CPLX, KP, TR, CAPV>;
+  constexpr int NPL = LY::NPL, CH = LY::CH, KS = KP / 16, PT = LY::PT, CAP = LY::CAP;
+  constexpr int NW = NT / 64, NBLK = PT / 32, BPW = NBLK >= NW ? NBLK / NW : 1;
+  extern __shared__ __align__(16) shortx8 smem[];
+  char* R = (char*)smem;
+  float* Pt = (float*)(R + LY::RB);
+  shortx8* T = smem;
+  float4* E = (float4*)(T + CAP * CH);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
   const int I = blockIdx.x / nJ, J = blockIdx.x % nJ;
   const int row0 = I * TR, col0 = J * TCOLS;
   const size_t NN = (size_t)N * N;
-
-  // ---- phase 1: stage the strip (unit = 8 consecutive stack matrices x V positions of one row,
-  // V elements per 16-byte load; all loads of a thread are issued before any is used)
-  constexpr int EB = CPLX ? 8 : 4;
-  constexpr int V = 16 / EB;
-  constexpr int NUNIT = (PT / V) * G8;
-  constexpr int UPT = (NUNIT + NT - 1) / NT;
-  {
-    const bool vec_ok = (N % V) == 0;
-    uint4 raw[UPT][8];
-#pragma unroll
-    for (int m = 0; m < UPT; ++m) {
-      const int u = tid + NT * m;
-      const int vq = u % (PT / V), g = u / (PT / V);
-      const int p0 = vq * V;
-      const int row = row0 + p0 / TCOLS, col = col0 + p0 % TCOLS;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = g * 8 + e;
-        raw[m][e] = make_uint4(0, 0, 0, 0);
-        if (u >= NUNIT || k >= 2 * L || row >= N) continue;
-        const char* base = (const char*)stack + ((size_t)k * NN + (size_t)row * N + col) * EB;
-        if (vec_ok && col + V <= N) {
-          raw[m][e] = *(const uint4*)base;
-        } else {
-          uint32_t w[4] = {0, 0, 0, 0};
-          for (int q = 0; q < V; ++q)
-            if (col + q < N) {
-              if (EB == 4) w[q] = ((const uint32_t*)base)[q];
-              else { w[2 * q] = ((const uint32_t*)base)[2 * q]; w[2 * q + 1] = ((const uint32_t*)base)[2 * q + 1]; }
-            }
-          raw[m][e] = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < UPT; ++m) {
-      const int u = tid + NT * m;
-      if (u >= NUNIT) continue;
-      const int vq = u % (PT / V), g = u / (PT / V);
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const int p = vq * V + q;
-        shortx8 vh[NPL], vl[NPL];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t w[4] = {raw[m][e].x, raw[m][e].y, raw[m][e].z, raw[m][e].w};
-#pragma unroll
-          for (int pl = 0; pl < NPL; ++pl) {
-            const uint32_t bits = w[q * NPL + pl];
-            short h, l;
-            if (BF) { h = (short)(bits & 0xffff); l = (short)(bits >> 16); }
-            else split_f32<false>(__builtin_bit_cast(float, bits), h, l);
-            vh[pl][e] = h;
-            vl[pl][e] = l;
-          }
-        }
-#pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
-          shortx8* base = S + ((size_t)pl * PT + p) * CH;
-          base[swz(p, g)] = vh[pl];
-          base[swz(p, G8 + g)] = vl[pl];
-        }
-      }
-    }
-  }
-  for (int p = tid; p < PT; p += NT) {
-    const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
-    const bool inb = row < N && col < N;
-    if (CPLX) {
-      const float2 v = inb ? ((const float2*)Pm)[(size_t)row * N + col] : make_float2(0.f, 0.f);
-      Pt[p * 2] = v.x;
-      Pt[p * 2 + 1] = v.y;
-    } else {
-      Pt[p] = inb ? ((const float*)Pm)[(size_t)row * N + col] : 0.f;
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 2: this wave's B fragments (blocks wave + NW j) into registers
-  shortx8 bh[BPW][NPL][KS], bl[BPW][NPL][KS], bxh[BPW], bxl[BPW];
-#pragma unroll
-  for (int j = 0; j < BPW; ++j) {
-    const int blk = wave + NW * j < NBLK ? wave + NW * j : NBLK - 1;
-    const int p = blk * 32 + l32;
-#pragma unroll
-    for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const shortx8* rowS = S + ((size_t)pl * PT + p) * CH;
-        bh[j][pl][ks] = rowS[swz(p, 2 * ks + lh)];
-        bl[j][pl][ks] = rowS[swz(p, G8 + 2 * ks + lh)];
-      }
-    // extra k-step: (P_re, P_im, identity) at k = 0..2 for lanes lh == 0, zero elsewhere
-    bxh[j] = shortx8{};
-    bxl[j] = shortx8{};
-    if (lh == 0) {
-      const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
-      const float pr = CPLX ? Pt[2 * p] : Pt[p];
-      const float pi = CPLX ? Pt[2 * p + 1] : 0.f;
-      short h, l;
-      split_f32<BF>(pr, h, l);
-      bxh[j][0] = h; bxl[j][0] = l;
-      split_f32<BF>(pi, h, l);
-      bxh[j][1] = h; bxl[j][1] = l;
-      split_f32<BF>((row == col && row < N) ? 1.f : 0.f, h, l);
-      bxh[j][2] = h; bxl[j][2] = l;
-    }
-  }
-  const float unscale = BF ? 1.0f : kUnscale;
   const bool interior = row0 + TR <= N && col0 + TCOLS <= N;
 
-  // ---- phase 3: orders in chunks of CAP through LDS
+  for (int e = tid; e < (KP - 2 * L) * PT * NPL; e += NT) ((uint32_t*)R)[2 * L * PT * NPL + e] = 0u;
+  if (((size_t)N * (CPLX ? 8 : 4)) % 16 == 0 && interior) stage_direct<CPLX, TR, NW>(stack, N, L, row0, col0, R, wave, lane);
+  else stage_generic<CPLX, TR, NT>(stack, N, L, row0, col0, R, tid);
+  stage_p<CPLX, TR, NT>(Pm, N, row0, col0, Pt, tid);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  __syncthreads();
+  // PAIR: wave w owns strip rows w * BPW/2 .. (BPW/2 per wave); block j holds the positions of row
+  // w * BPW/2 + j/2 with column parity j & 1.  Otherwise block j is positions (wave + NW j) * 32 + 0..31.
+  static_assert(!PAIR || (BPW % 2 == 0 && NW * BPW / 2 == TR), "paired blocks cover whole strip rows");
+  auto pos_of = [&](int j) {
+    if (PAIR) return (wave * (BPW / 2) + j / 2) * TCOLS + 2 * l32 + (j & 1);
+    const int blk = wave + NW * j < NBLK ? wave + NW * j : NBLK - 1;
+    return blk * 32 + l32;
+  };
+  shortx8 bh[BPW][NPL][KS], bl[BPW][NPL][KS], bxh[BPW], bxl[BPW];
+#pragma unroll
+  for (int j = 0; j < BPW; ++j)
+    load_fragments_raw<CPLX, KP, TR, BF>((const uint32_t*)R, Pt, N, row0, col0, pos_of(j), lh, bh[j], bl[j], bxh[j],
+                                         bxl[j]);
   for (int c0 = 0; c0 < n_pad; c0 += CAP) {
     const int ncap = n_pad - c0 < CAP ? n_pad - c0 : CAP;
     __syncthreads();   // previous users of the LDS are done
-    // copy the table chunk in batches of 4 loads per thread, all in flight before any is used
-    constexpr int TPT = CAP * CH / NT;
-    static_assert(TPT % 4 == 0, "table copy batches");
-    const shortx8* tsrc = (const shortx8*)(table + (size_t)c0 * 2 * KP);
-#pragma unroll
-    for (int b = 0; b < TPT; b += 4) {
-      shortx8 v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int it = tid + NT * (b + q);
-        v[q] = it / CH < ncap ? tsrc[it] : shortx8{};
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int it = tid + NT * (b + q), a = it / CH, c = it % CH;
-        T[a * CH + swz(a, c)] = v[q];
-      }
-    }
+    load_table_direct<KP, NW>(table, c0, ncap, T, wave, lane);
     for (int a = tid; a < ncap; a += NT) E[a] = epi[c0 + a];
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     if (wave >= NBLK) continue;
     for (int g0 = 0; g0 < ncap; g0 += 32) {
       const int a0 = c0 + g0;
-      const int al = g0 + l32;                 // this lane's order (A row), local index
       const bool fast = interior && a0 + 32 <= n_alpha;
+      if constexpr (PAIR) {
 #pragma unroll
-      for (int j = 0; j < BPW; ++j) {
-        const int blk = wave + NW * j;
-        if (blk >= NBLK) break;
-        const int p = blk * 32 + l32;
-        floatx16 acc_re = {}, acc_im = {};
-#pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
-          floatx16 acc = {};
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
-            const shortx8 aH = T[al * CH + swz(al, 2 * ks + lh)];
-            const shortx8 aL = T[al * CH + swz(al, G8 + 2 * ks + lh)];
-            acc = mfma16<BF>(aH, bh[j][pl][ks], acc);
-            acc = mfma16<BF>(aH, bl[j][pl][ks], acc);
-            acc = mfma16<BF>(aL, bh[j][pl][ks], acc);
-          }
-          if (pl == 0) acc_re = acc; else acc_im = acc;
+        for (int j = 0; j < BPW; j += 2) {
+          const int p = pos_of(j);
+          order_pair<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast && (N % 2) == 0, row0 + p / TCOLS,
+                                          col0 + p % TCOLS, N, NN, l32, lh, bh[j], bl[j], bxh[j], bxl[j], bh[j + 1],
+                                          bl[j + 1], bxh[j + 1], bxl[j + 1], Q);
         }
-        // extra-step A rows: Re (cos - c_0, -sin, c_0), Im (sin, cos - c_0, 0) on k = 0..2
-        shortx8 xrH = {}, xrL = {}, xiH = {}, xiL = {};
-        if (lh == 0) {
-          const float4 e = E[al];
-          short h, l;
-          split_f32<BF>(e.x, h, l); xrH[0] = h; xrL[0] = l; xiH[1] = h; xiL[1] = l;
-          split_f32<BF>(-e.y, h, l); xrH[1] = h; xrL[1] = l;
-          split_f32<BF>(e.y, h, l); xiH[0] = h; xiL[0] = l;
-          split_f32<BF>(e.z, h, l); xrH[2] = h; xrL[2] = l;
-        }
-        acc_re = mfma16<BF>(xrH, bxh[j], acc_re);
-        acc_re = mfma16<BF>(xrH, bxl[j], acc_re);
-        acc_re = mfma16<BF>(xrL, bxh[j], acc_re);
-        acc_im = mfma16<BF>(xiH, bxh[j], acc_im);
-        acc_im = mfma16<BF>(xiH, bxl[j], acc_im);
-        acc_im = mfma16<BF>(xiL, bxh[j], acc_im);
-        // store: lane holds position p (column), orders a0 + 8(r/4) + 4 lh + r%4
-        const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
-        cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
-        if (fast) {
+      } else {
 #pragma unroll
-          for (int r = 0; r < 16; ++r)
-            ql[(size_t)(8 * (r >> 2) + (r & 3)) * NN] = cplx64{acc_re[r] * unscale, acc_im[r] * unscale};
-        } else if (row < N && col < N) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha)
-              ql[(size_t)(8 * (r >> 2) + (r & 3)) * NN] = cplx64{acc_re[r] * unscale, acc_im[r] * unscale};
+        for (int j = 0; j < BPW; ++j) {
+          const int blk = wave + NW * j;
+          if (blk >= NBLK) break;
+          const int p = blk * 32 + l32;
+          order_group<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast, row0 + p / TCOLS, col0 + p % TCOLS, N, NN,
+                                           l32, lh, bh[j], bl[j], bxh[j], bxl[j], Q);
         }
       }
     }
@@ -349,19 +474,19 @@ fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, 
   return FGFRFT_OK;
 }
 
-template <bool CPLX, int KP, int TR, bool BF, int NT, int MINW>
-static fgfrft_status launch_update_t(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha, int n_pad,
-                                     void* Q, hipStream_t s) {
-  constexpr int NPL = CPLX ? 2 : 1;
-  constexpr int CAP = KP <= 64 ? 256 : 128;
-  const size_t lds_stage = (size_t)NPL * TR * TCOLS * (KP / 4) * 16 + (size_t)TR * TCOLS * NPL * 4;
-  const size_t lds_table = (size_t)CAP * (KP / 4) * 16 + (size_t)CAP * 16;
-  const size_t lds = lds_stage > lds_table ? lds_stage : lds_table;
-  auto kern = k_update<CPLX, KP, TR, BF, NT, MINW>;
-  static bool attr_set = false;
-  if (!attr_set) {
+template <bool CPLX, int KP, int TR, bool BF, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false>
+static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha,
+                                         int n_pad, void* Q, hipStream_t s) {
+  using LY = StripLayout<CPLX, KP, TR, CAPV>;
+  constexpr size_t lds = LY::RB + LY::PB > LY::TB + (size_t)LY::CAP * 16 ? LY::RB + LY::PB : LY::TB + (size_t)LY::CAP * 16;
+  static_assert(lds <= 160 * 1024, "LDS budget");
+  const bool off32 = (size_t)5 * p->N * p->N * sizeof(cplx64) < ((size_t)1 << 32);
+  auto kern = off32 ? k_update_strip<CPLX, KP, TR, BF, NT, MINW, true, CAPV, PAIR>
+                    : k_update_strip<CPLX, KP, TR, BF, NT, MINW, false, CAPV, PAIR>;
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[off32]) {
     FG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = true;
+    attr_set[off32] = true;
   }
   const int nI = ceil_div(p->N, TR), nJ = ceil_div(p->N, TCOLS);
   kern<<<nI * nJ, NT, lds, s>>>(p->stack, p->P, p->N, p->L, nJ, table, epi, n_alpha, n_pad, (cplx64*)Q);
@@ -369,23 +494,23 @@ static fgfrft_status launch_update_t(const Plan* p, const uint16_t* table, const
   return FGFRFT_OK;
 }
 
-// (KP, TR): strips of TR rows x 64 columns sized so the staged tiles (and the order table)
-// fit 64-68 KB of LDS, two workgroups of 4 waves per CU.
+// (KP, TR, pairing): strips of TR rows x 64 columns; the staged tiles, and then the order table
+// (up to 256 orders for KP <= 64, 128 beyond), fit 64-68 KB of LDS, two workgroups of 4 waves per CU.
 template <bool BF>
 static fgfrft_status dispatch(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha, int np, void* Q,
                               hipStream_t s) {
   const int KP = kp_of(p->L);
   if (!p->cplx) {
     switch (KP) {
-      case 32: return launch_update_t<false, 32, 8, BF, 256, 2>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_t<false, 64, 4, BF, 256, 2>(p, table, epi, n_alpha, np, Q, s);
-      case 96: return launch_update_t<false, 96, 2, BF, 256, 2>(p, table, epi, n_alpha, np, Q, s);
-      case 128: return launch_update_t<false, 128, 2, BF, 256, 2>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<false, 32, 8, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<false, 64, 4, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
+      case 96: return launch_update_strip<false, 96, 2, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
+      case 128: return launch_update_strip<false, 128, 2, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
     }
   } else {
     switch (KP) {
-      case 32: return launch_update_t<true, 32, 4, BF, 256, 2>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_t<true, 64, 2, BF, 256, 2>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<true, 32, 4, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<true, 64, 2, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
     }
   }
   set_error("unsupported L=%d for %s F", p->L, p->cplx ? "complex" : "real");

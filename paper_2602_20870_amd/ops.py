@@ -16,6 +16,7 @@ import torch
 from ._lib import P_double, check, lib
 
 STACK_TYPES = {"fp32": 0, "bf16x2": 1}
+FORMS = {"split": 0, "standard": 1}
 
 
 def _stream(stream=None) -> ctypes.c_void_p:
@@ -45,7 +46,8 @@ class Plan:
     by this object; the FP64 planning scratch is released when planning ends.
     """
 
-    def __init__(self, F: torch.Tensor, L: int, stacktype: str = "fp32", tau: float = 0.0, stream=None):
+    def __init__(self, F: torch.Tensor, L: int, stacktype: str = "fp32", tau: float = 0.0, stream=None,
+                 form: str = "split"):
         if not F.is_cuda:
             raise ValueError("F must be a cuda tensor")
         if F.dtype == torch.float64:
@@ -66,13 +68,17 @@ class Plan:
         self.persistent = _workspace(pb.value, F.device)
         scratch = _workspace(sb.value, F.device)
         h = ctypes.c_void_p()
-        check(L_.fgfrft_plan(_ptr(F), N, L, intype, STACK_TYPES[stacktype], float(tau), _ptr(self.persistent),
+        if form not in FORMS:
+            raise ValueError(f"form must be one of {sorted(FORMS)}")
+        check(L_.fgfrft_plan(_ptr(F), N, L, intype, STACK_TYPES[stacktype], FORMS[form], float(tau),
+                             _ptr(self.persistent),
                              pb.value, _ptr(scratch), sb.value, _stream(stream), ctypes.byref(h)), "fgfrft_plan")
         del scratch
         self._h = h
         self.N, self.L = N, L
         self.complex = intype == 0
         self.stacktype = stacktype
+        self.form = form
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -64,9 +64,12 @@ def test_plan_bytes_validation(L):
 def test_null_and_small_arguments_are_rejected_on_host(L):
     h = ctypes.c_void_p()
     # NULL device pointers: rejected before any HIP call
-    rc = L.fgfrft_plan(None, 16, 4, 1, 0, 0.0, None, 0, None, 0, None, ctypes.byref(h))
+    rc = L.fgfrft_plan(None, 16, 4, 1, 0, 0, 0.0, None, 0, None, 0, None, ctypes.byref(h))
     assert rc == -1 and not h.value
     assert b"NULL" in L.fgfrft_last_error()
+    # an unknown operator form is rejected too (0: split, 1: standard)
+    rc = L.fgfrft_plan(None, 16, 4, 1, 0, 2, 0.0, None, 0, None, 0, None, ctypes.byref(h))
+    assert rc == -1 and b"form" in L.fgfrft_last_error()
     a = (ctypes.c_double * 2)(0.5, 0.25)
     assert L.fgfrft_update(None, a, 2, None, None, 0, None) == -1
     assert L.fgfrft_grad(None, a, 2, None, 0, 0, 4, None, None, None, None, 0, None) == -1

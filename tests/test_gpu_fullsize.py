@@ -1,0 +1,137 @@
+"""Parity at the full workload sizes, in the launch configurations the benchmark times,
+on sampled outputs the FP64 oracle computes row by row.
+
+* knn4096: N = 4096, L = 32, one update launch of 256 orders (34 GB of Q), then one apply
+  launch to 64 real signals per order, as in the benchmark step.
+* grid8192 (precision form): N = 8192, L = 64, one update launch of a 32-order chunk for the
+  FP32 stack and for the BF16 hi/lo stack; per-order errors against the oracle are printed
+  (and written as JSON to $FGFRFT_REPORT_DIR when that is set).
+
+The oracle's rows come from the row/column power recurrences of the stack (no N x N FP64
+stack is formed) and its projector from the symmetric-part route for real orthogonal F.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_common import TOL_BF16X2, TOL_FP32, announce, rel_fro, torch_cuda
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+ROWS = 64
+
+
+def _rows(N, seed):
+    rng = np.random.default_rng(seed)
+    r = rng.choice(np.arange(1, N - 1), ROWS - 2, replace=False)
+    return np.sort(np.concatenate([[0, N - 1], r]))      # first and last row always included
+
+
+def _report(name, payload):
+    d = os.environ.get("FGFRFT_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name), "w") as f:
+            json.dump(payload, f, indent=1)
+
+
+def _sample_rows(torch, Q, sample, rows):
+    s = torch.as_tensor(np.asarray(sample), device=Q.device)
+    r = torch.as_tensor(rows, device=Q.device)
+    return Q[s[:, None], r[None, :]].cpu().numpy()         # [len(sample), ROWS, N]
+
+
+@pytest.mark.timeout(600)
+def test_knn4096_bench_launch_sampled_rows():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan, apply_operator
+    t0 = time.time()
+    announce("knn4096: building F (kNN k=10 on GMM points, N=4096)")
+    cfg = synth.make_config("knn4096", seed=0, with_signals=False)
+    F, L, N = cfg["F"], cfg["L"], cfg["N"]
+    alphas = cfg["alphas"].copy()
+    assert alphas.size == 256
+    alphas[:6] = [0.0, 1.0, -1.0, 0.5, 0.73, -0.73]       # identity, F, F^H, a half order, an adjoint pair
+    sample = list(range(6)) + list(range(16, 256, 24))
+    rows = _rows(N, 1)
+
+    announce("knn4096: GPU plan + one 256-order update launch")
+    plan = Plan(torch.from_numpy(F).cuda(), L)
+    Q = torch.empty((256, N, N), dtype=torch.complex64, device="cuda")
+    plan.update(alphas, out=Q)
+    rng = synth.streams(0, 3)[2]
+    X = torch.from_numpy(synth.real_signals((256, N, 64), rng).astype(np.float32)).cuda()
+    Y = apply_operator(Q, X)
+    torch.cuda.synchronize()
+    Qr = _sample_rows(torch, Q, sample, rows)
+    Yr = _sample_rows(torch, Y, sample, rows)
+    Qcol = Q[4][:, torch.as_tensor(rows, device="cuda")].cpu().numpy()    # columns R of Q^{0.73}
+    Xs = X[torch.as_tensor(sample, device="cuda")].cpu().numpy().astype(np.float64)
+    del Q, Y, X
+    torch.cuda.empty_cache()
+
+    # properties that need no oracle: Q^0 = I, Q^1 = F, Q^{-1} = F^T (Definition 1), and
+    # Q^{-a}[R, :] = (Q^{a}[:, R])^H (Proposition 3)
+    eye_rows = np.zeros((ROWS, N))
+    eye_rows[np.arange(ROWS), rows] = 1.0
+    assert rel_fro(Qr[0], eye_rows) <= TOL_FP32
+    assert rel_fro(Qr[1], F[rows, :]) <= TOL_FP32
+    assert rel_fro(Qr[2], F.T[rows, :]) <= TOL_FP32
+    assert rel_fro(Qr[5], Qcol.conj().T) <= 1e-6
+
+    announce(f"knn4096: oracle projector (symmetric route) and sampled rows [{time.time() - t0:.0f}s]")
+    P, _, r, nxt = O.projectors_symmetric_route(F)
+    assert plan.r_minus1 == r
+    ref = O.sampled_rows(F, P, alphas[sample], L, rows)
+    errs_q, errs_y = [], []
+    for i, a in enumerate(sample):
+        errs_q.append(rel_fro(Qr[i], ref[i]))
+        errs_y.append(rel_fro(Yr[i], ref[i] @ Xs[i]))
+    announce(f"knn4096: r_-1={r}, worst Q row error {max(errs_q):.2e}, worst Y row error {max(errs_y):.2e} "
+             f"[{time.time() - t0:.0f}s]")
+    _report("knn4096_fullsize.json", dict(alphas=[float(alphas[a]) for a in sample], rows=rows.tolist(),
+                                          q_err=errs_q, y_err=errs_y, r_minus1=r))
+    assert max(errs_q) <= TOL_FP32, errs_q
+    assert max(errs_y) <= TOL_FP32, errs_y
+
+
+@pytest.mark.timeout(900)
+def test_grid8192_precision_forms_sampled_rows():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan
+    t0 = time.time()
+    announce("grid8192: building F (128x64 grid, lognormal weights, N=8192)")
+    cfg = synth.make_config("grid8192", seed=0, with_signals=False)
+    F, L, N = cfg["F"], cfg["L"], cfg["N"]
+    chunk = cfg["alphas"][:32].copy()                      # one 32-order launch of the 1024
+    chunk[:4] = [0.0, 1.0, -1.0, 0.5]
+    rows = _rows(N, 2)
+    Ft = torch.from_numpy(F).cuda()
+    got = {}
+    for st in ("fp32", "bf16x2"):
+        announce(f"grid8192: GPU plan ({st}) + one 32-order update launch [{time.time() - t0:.0f}s]")
+        plan = Plan(Ft, L, stacktype=st)
+        Q = plan.update(chunk)
+        torch.cuda.synchronize()
+        got[st] = (_sample_rows(torch, Q, range(32), rows), plan.r_minus1)
+        del Q, plan
+        torch.cuda.empty_cache()
+    del Ft
+
+    announce(f"grid8192: oracle projector and sampled rows [{time.time() - t0:.0f}s]")
+    P, _, r, nxt = O.projectors_symmetric_route(F)
+    ref = O.sampled_rows(F, P, chunk, L, rows)
+    report = dict(alphas=chunk.tolist(), rows=rows.tolist(), r_minus1=r, next_cos=nxt)
+    for st, tol in (("fp32", TOL_FP32), ("bf16x2", TOL_BF16X2)):
+        Qr, r_gpu = got[st]
+        assert r_gpu == r
+        errs = [rel_fro(Qr[i], ref[i]) for i in range(32)]
+        report[st] = errs
+        announce(f"grid8192 {st}: worst row error {max(errs):.2e}, median {np.median(errs):.2e}")
+        assert max(errs) <= tol, (st, errs)
+    _report("grid8192_precision.json", report)
