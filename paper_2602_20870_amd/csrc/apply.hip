@@ -97,72 +97,83 @@ __global__ __launch_bounds__(256) void k_apply(const cplx64* __restrict__ Q, int
   float xsc = 1.f;
   if (b0 + xc < B) xsc = xs[b0 + xc].x;
 
-  for (int k0 = 0; k0 < N; k0 += AK) {
-    // ---- stage op(Q)[i0 + qr][k0 + qk .. +7]
-    {
-      cplx64 v[8];
-      const int gi = i0 + qr, gk0 = k0 + qk;
-      if (!ADJ && (N & 1) == 0 && gi < N && gk0 + 7 < N) {  // 16-byte aligned when N is even
-        const float4* src = (const float4*)(Qa + (size_t)gi * N + gk0);
+  // register staging of one k-chunk: op(Q)[i0 + qr][k0 + qk .. +7] and X[k0 + xk .. +7][b0 + xc].
+  // The next chunk's global loads are issued before the current chunk's MFMAs, so they are in
+  // flight while the matrix cores work (nothing in this loop stores to global memory).
+  cplx64 qv[8];
+  float xv[8], xw[8];
+  auto fetch = [&](int k0) {
+    const int gi = i0 + qr, gk0 = k0 + qk;
+    if (!ADJ && (N & 1) == 0 && gi < N && gk0 + 7 < N) {  // 16-byte aligned when N is even
+      const float4* src = (const float4*)(Qa + (size_t)gi * N + gk0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float4 f = src[e];
-          v[2 * e] = cplx64{f.x, f.y};
-          v[2 * e + 1] = cplx64{f.z, f.w};
-        }
-      } else {
+      for (int e = 0; e < 4; ++e) {
+        const float4 f = src[e];
+        qv[2 * e] = cplx64{f.x, f.y};
+        qv[2 * e + 1] = cplx64{f.z, f.w};
+      }
+    } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int gk = gk0 + e;
-          v[e] = cplx64{0.f, 0.f};
-          if (gi < N && gk < N) {
-            if (!ADJ) v[e] = Qa[(size_t)gi * N + gk];
-            else { v[e] = Qa[(size_t)gk * N + gi]; v[e].im = -v[e].im; }
-          }
+      for (int e = 0; e < 8; ++e) {
+        const int gk = gk0 + e;
+        qv[e] = cplx64{0.f, 0.f};
+        if (gi < N && gk < N) {
+          if (!ADJ) qv[e] = Qa[(size_t)gi * N + gk];
+          else { qv[e] = Qa[(size_t)gk * N + gi]; qv[e].im = -qv[e].im; }
         }
       }
+    }
+    const int gb = b0 + xc;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gk = k0 + xk + e;
+      xv[e] = 0.f;
+      xw[e] = 0.f;
+      if (gb < B && gk < N) {
+        const size_t off = xoff + (size_t)gk * B + gb;
+        if (XC) { const float2 v = ((const float2*)X)[off]; xv[e] = v.x; xw[e] = v.y; }
+        else xv[e] = ((const float*)X)[off];
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < N; k0 += AK) {
+    // ---- split the fetched chunk into fp16 hi/lo parts in LDS (X scaled per column, transposed)
+    {
       shortx8 vrh, vrl, vih, vil;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         short a_, b_, c_, d_;
-        split_h(v[e].re * kStackScale, a_, b_);
-        split_h(v[e].im * kStackScale, c_, d_);
+        split_h(qv[e].re * kStackScale, a_, b_);
+        split_h(qv[e].im * kStackScale, c_, d_);
         vrh[e] = a_; vrl[e] = b_; vih[e] = c_; vil[e] = d_;
       }
       *(shortx8*)&Qs[0][0][qr][qk] = vrh;
       *(shortx8*)&Qs[0][1][qr][qk] = vrl;
       *(shortx8*)&Qs[1][0][qr][qk] = vih;
       *(shortx8*)&Qs[1][1][qr][qk] = vil;
-    }
-    // ---- stage X[k0 + xk .. +7][b0 + xc] (scaled per column), transposed to Xs[..][col][k]
-    {
-      short h0[8], l0[8], h1[8], l1[8];
-      const int gb = b0 + xc;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + xk + e;
-        float xr = 0.f, xi = 0.f;
-        if (gb < B && gk < N) {
-          const size_t off = xoff + (size_t)gk * B + gb;
-          if (XC) { const float2 v = ((const float2*)X)[off]; xr = v.x; xi = v.y; }
-          else xr = ((const float*)X)[off];
-        }
-        split_h(xr * xsc, h0[e], l0[e]);
-        if (XC) split_h(xi * xsc, h1[e], l1[e]);
-      }
       shortx8 v0, v1;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) { v0[e] = h0[e]; v1[e] = l0[e]; }
+      for (int e = 0; e < 8; ++e) {
+        short h, l;
+        split_h(xv[e] * xsc, h, l);
+        v0[e] = h; v1[e] = l;
+      }
       *(shortx8*)&Xs[0][0][xc][xk] = v0;
       *(shortx8*)&Xs[0][1][xc][xk] = v1;
       if (XC) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) { v0[e] = h1[e]; v1[e] = l1[e]; }
+        for (int e = 0; e < 8; ++e) {
+          short h, l;
+          split_h(xw[e] * xsc, h, l);
+          v0[e] = h; v1[e] = l;
+        }
         *(shortx8*)&Xs[XPL - 1][0][xc][xk] = v0;
         *(shortx8*)&Xs[XPL - 1][1][xc][xk] = v1;
       }
     }
     __syncthreads();
+    if (k0 + AK < N) fetch(k0 + AK);
 #pragma unroll
     for (int ks = 0; ks < AK; ks += 16) {
       const int kk = ks + 8 * lh;
