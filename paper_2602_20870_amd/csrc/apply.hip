@@ -20,15 +20,21 @@ constexpr int RS = 40;   // LDS row stride in 16-bit values (32 + 8 pad)
 
 // ---------------------------------------------------------------- per-signal scales
 // scale[(a, b)] = 2^e with max_i |X[a][i][b]| * 2^e in [2^13, 2^14); stored (s, 1/s).
-__global__ __launch_bounds__(256) void k_colscale(const void* __restrict__ X, int x_complex, int N, int B, int nx,
-                                                  float2* __restrict__ scale) {
-  const int a = blockIdx.y;
-  const int b = blockIdx.x * 64 + (threadIdx.x & 63);
+// Two passes: column maxima over chunks of CR rows (grid: (order, column block) x chunks),
+// then the maximum over chunks and the power of two (fixed order, no atomics).
+constexpr int CR = 256;
+
+__global__ __launch_bounds__(256) void k_colmax(const void* __restrict__ X, int x_complex, int N, int B,
+                                                float* __restrict__ partial) {
+  const int ncb = (B + 63) / 64;
+  const int a = blockIdx.x / ncb, ch = blockIdx.y, nch = gridDim.y;
+  const int b = (blockIdx.x % ncb) * 64 + (threadIdx.x & 63);
   const int rg = threadIdx.x >> 6;
   __shared__ float red[4][64];
   float m = 0.f;
-  if (b < B && a < nx) {
-    for (int i = rg; i < N; i += 4) {
+  if (b < B) {
+    const int i1 = (ch + 1) * CR < N ? (ch + 1) * CR : N;
+    for (int i = ch * CR + rg; i < i1; i += 4) {
       const size_t off = ((size_t)a * N + i) * B + b;
       if (x_complex) {
         const float2 v = ((const float2*)X)[off];
@@ -40,18 +46,27 @@ __global__ __launch_bounds__(256) void k_colscale(const void* __restrict__ X, in
   }
   red[rg][threadIdx.x & 63] = m;
   __syncthreads();
-  if (rg == 0 && b < B && a < nx) {
-    m = fmaxf(fmaxf(red[0][threadIdx.x], red[1][threadIdx.x]), fmaxf(red[2][threadIdx.x], red[3][threadIdx.x]));
-    int e = 0;
-    if (m > 0.f && isfinite(m)) {
-      int E;
-      frexpf(m, &E);
-      e = 14 - E;
-      if (e > 100) e = 100;
-      if (e < -100) e = -100;
-    }
-    scale[(size_t)a * B + b] = make_float2(ldexpf(1.f, e), ldexpf(1.f, -e));
+  if (rg == 0 && b < B)
+    partial[((size_t)a * nch + ch) * B + b] =
+        fmaxf(fmaxf(red[0][threadIdx.x], red[1][threadIdx.x]), fmaxf(red[2][threadIdx.x], red[3][threadIdx.x]));
+}
+
+__global__ __launch_bounds__(256) void k_colscale(const float* __restrict__ partial, int nch, int B, int nx,
+                                                  float2* __restrict__ scale) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nx * B) return;
+  const int a = idx / B, b = idx % B;
+  float m = 0.f;
+  for (int c = 0; c < nch; ++c) m = fmaxf(m, partial[((size_t)a * nch + c) * B + b]);
+  int e = 0;
+  if (m > 0.f && isfinite(m)) {
+    int E;
+    frexpf(m, &E);
+    e = 14 - E;
+    if (e > 100) e = 100;
+    if (e < -100) e = -100;
   }
+  scale[idx] = make_float2(ldexpf(1.f, e), ldexpf(1.f, -e));
 }
 
 __device__ __forceinline__ void split_h(float v, short& hi, short& lo) {
@@ -219,9 +234,154 @@ __global__ __launch_bounds__(256) void k_apply(const cplx64* __restrict__ Q, int
   }
 }
 
+// ---------------------------------------------------------------- streaming apply
+// Y[a] = Q[a] X[a] for N % 16 == 0 and B % 64 == 0: 128 output rows x 64 signals per
+// workgroup (wave w: rows 32w..32w+31, both 32-signal blocks), k in stages of 16.  Each stage
+// (16 KB of Q, 4 or 8 KB of X) moves from HBM/L2 straight into LDS with direct loads into a
+// ring of NS stages, so NS - 1 stages are in flight while the matrix cores work on the
+// current one; operands are split into fp16 hi/lo when a wave reads its fragments.  Q rows
+// sit in LDS with their 16-byte chunks swizzled by row (chunk c of row r at c ^ (r & 7)) so
+// the fragment reads of 32 rows hit every bank.
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr int M2 = 128, K2 = 16;
+
+template <bool XC>
+struct Apply2Layout {
+  static constexpr int QB = M2 * K2 * 8;              // Q stage bytes
+  static constexpr int XB = K2 * 64 * (XC ? 8 : 4);   // X stage bytes
+  static constexpr int SB = QB + XB;
+  static constexpr int LW = 4 + XB / 4096;            // direct loads per wave per stage
+};
+
+__host__ __device__ constexpr int vmcnt_wait_imm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+template <bool XC, bool YREAL, int NS>
+__global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q, int N, int n_alpha,
+                                                   const void* __restrict__ X, int x_shared, int B,
+                                                   const float2* __restrict__ xscale, void* __restrict__ Y, int nrb,
+                                                   int ncb) {
+  using LY = Apply2Layout<XC>;
+  constexpr int XE = XC ? 8 : 4;
+  extern __shared__ __align__(16) char sm[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per_a = nrb * ncb;
+  const int a = xcd + 8 * (slot / per_a);
+  if (a >= n_alpha) return;
+  const int rem = slot % per_a, rb = rem / ncb, cb = rem % ncb;
+  const int i0 = rb * M2, b0 = cb * 64;
+  const size_t NN = (size_t)N * N;
+  const char* Qa = (const char*)(Q + (size_t)a * NN);
+  const char* Xa = (const char*)X + (x_shared ? 0 : (size_t)a * N * B * XE);
+  const float2* xs = xscale + (x_shared ? 0 : (size_t)a * B);
+  const int nch = N / K2;
+
+  auto issue = [&](int it) {
+    char* st = sm + (it % NS) * LY::SB;
+    const int k0 = it * K2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {   // Q: 16 instructions of 8 rows x 128 bytes
+      const int i = wave + 4 * q;
+      const int row = 8 * i + (lane >> 3), c = (lane & 7) ^ (row & 7);
+      const int grow = i0 + row < N ? i0 + row : N - 1;   // rows past N: any valid row, never written
+      __builtin_amdgcn_global_load_lds(Qa + ((size_t)grow * N + k0 + 2 * c) * 8, (lds_void*)(st + i * 1024), 16, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < LY::XB / 4096; ++q) {   // X: rows of 64 signals
+      const int i = wave + 4 * q;
+      const int kk = XC ? 2 * i + (lane >> 5) : 4 * i + (lane >> 4);
+      const int cc = XC ? 2 * (lane & 31) : 4 * (lane & 15);
+      __builtin_amdgcn_global_load_lds(Xa + ((size_t)(k0 + kk) * B + b0 + cc) * XE, (lds_void*)(st + LY::QB + i * 1024),
+                                       16, 0, 0);
+    }
+  };
+
+  float xsc[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) xsc[c] = xs[b0 + 32 * c + l32].x;
+  floatx16 acc_re[2] = {}, acc_im[2] = {};
+  const int r = 32 * wave + l32;
+
+  for (int it = 0; it < NS - 1 && it < nch; ++it) issue(it);
+  for (int it = 0; it < nch; ++it) {
+    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(vmcnt_wait_imm((NS - 2) * LY::LW));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_wait_imm(0));
+    __syncthreads();   // stage it has landed for every wave; stage it - 1 is no longer read
+    const char* st = sm + (it % NS) * LY::SB;
+    // A: Q[r][8 lh .. 8 lh + 7] (4 chunks of two complex values)
+    shortx8 arh, arl, aih, ail;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = (4 * lh + q) ^ (r & 7);
+      const float4 v = *(const float4*)(st + r * 128 + c * 16);
+      short h, l;
+      split_h(v.x * kStackScale, h, l); arh[2 * q] = h; arl[2 * q] = l;
+      split_h(v.y * kStackScale, h, l); aih[2 * q] = h; ail[2 * q] = l;
+      split_h(v.z * kStackScale, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
+      split_h(v.w * kStackScale, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+    }
+    shortx8 bxrh[2], bxrl[2], bxih[2], bxil[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int col = 32 * c + l32;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 8 * lh + j;
+        short h, l;
+        if (XC) {
+          const float2 v = *(const float2*)(st + LY::QB + (k * 64 + col) * 8);
+          split_h(v.x * xsc[c], h, l); bxrh[c][j] = h; bxrl[c][j] = l;
+          split_h(v.y * xsc[c], h, l); bxih[c][j] = h; bxil[c][j] = l;
+        } else {
+          const float v = *(const float*)(st + LY::QB + (k * 64 + col) * 4);
+          split_h(v * xsc[c], h, l); bxrh[c][j] = h; bxrl[c][j] = l;
+        }
+      }
+    }
+    // the stage's fragments are in registers: refill the ring slot read one iteration ago
+    if (it + NS - 1 < nch) issue(it + NS - 1);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const shortx8 xrh = bxrh[c], xrl = bxrl[c], xih = bxih[c], xil = bxil[c];
+      acc_re[c] = mma(arh, xrh, acc_re[c]);
+      acc_re[c] = mma(arh, xrl, acc_re[c]);
+      acc_re[c] = mma(arl, xrh, acc_re[c]);
+      acc_im[c] = mma(aih, xrh, acc_im[c]);
+      acc_im[c] = mma(aih, xrl, acc_im[c]);
+      acc_im[c] = mma(ail, xrh, acc_im[c]);
+      if (XC) {
+        const shortx8 naih = aih ^ (short)0x8000, nail = ail ^ (short)0x8000;
+        acc_re[c] = mma(naih, xih, acc_re[c]);
+        acc_re[c] = mma(naih, xil, acc_re[c]);
+        acc_re[c] = mma(nail, xih, acc_re[c]);
+        acc_im[c] = mma(arh, xih, acc_im[c]);
+        acc_im[c] = mma(arh, xil, acc_im[c]);
+        acc_im[c] = mma(arl, xih, acc_im[c]);
+      }
+    }
+  }
+  // write back: lane holds signal b0 + 32c + l32, rows 32 wave + 8(r/4) + 4 lh + r%4
+  const size_t yoff = (size_t)a * N * B;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int gb = b0 + 32 * c + l32;
+    const float u = xs[gb].y * (1.0f / kStackScale);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int gi = i0 + 32 * wave + 8 * (e >> 2) + 4 * lh + (e & 3);
+      if (gi < N) {
+        const size_t off = yoff + (size_t)gi * B + gb;
+        if (YREAL) ((float*)Y)[off] = acc_re[c][e] * u;
+        else ((cplx64*)Y)[off] = cplx64{acc_re[c][e] * u, acc_im[c][e] * u};
+      }
+    }
+  }
+}
+
 size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared) {
-  (void)N;
-  return align_up((size_t)(x_shared ? 1 : n_alpha) * B * sizeof(float2), 256);
+  const size_t nx = x_shared ? 1 : n_alpha;
+  return align_up(nx * B * sizeof(float2), 256) + align_up(nx * ceil_div(N, CR) * B * sizeof(float), 256);
 }
 
 template <bool ADJ, bool XC, bool YR>
@@ -230,12 +390,46 @@ static void launch_apply_t(dim3 g, hipStream_t s, const cplx64* Q, int N, int n_
   k_apply<ADJ, XC, YR><<<g, 256, 0, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
+template <bool XC, bool YR, int NS>
+static void launch_apply2_t(unsigned g, hipStream_t s, const cplx64* Q, int N, int n_alpha, const void* X, int x_shared,
+                            int B, const float2* sc, void* Y, int nrb, int ncb) {
+  constexpr int lds = NS * Apply2Layout<XC>::SB;
+  static_assert(lds <= 80 * 1024, "two workgroups per CU");
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_apply2<XC, YR, NS>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    attr_set = true;
+  }
+  k_apply2<XC, YR, NS><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
+}
+
 fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex, int x_shared,
                            int B, void* Y, int y_real, void* ws, hipStream_t s) {
   float2* sc = (float2*)ws;
   const int nx = x_shared ? 1 : n_alpha;
-  k_colscale<<<dim3(ceil_div(B, 64), nx), 256, 0, s>>>(X, x_complex, N, B, nx, sc);
+  const int nch = ceil_div(N, CR);
+  float* partial = (float*)((char*)ws + align_up((size_t)nx * B * sizeof(float2), 256));
+  k_colmax<<<dim3(ceil_div(B, 64) * nx, nch), 256, 0, s>>>(X, x_complex, N, B, partial);
+  k_colscale<<<ceil_div(nx * B, 256), 256, 0, s>>>(partial, nch, B, nx, sc);
   FG_LAUNCHED("colscale");
+  if (!adjoint && N % K2 == 0 && B % 64 == 0) {
+    const int nrb = ceil_div(N, M2), ncb = B / 64;
+    const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
+    if (nblocks > 0x7fffffff) {
+      set_error("apply grid too large");
+      return FGFRFT_EUNSUPPORTED;
+    }
+    const cplx64* q = (const cplx64*)Q;
+    const int key = (x_complex ? 2 : 0) | (y_real ? 1 : 0);
+    switch (key) {
+      case 0: launch_apply2_t<false, false, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 1: launch_apply2_t<false, true, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 2: launch_apply2_t<true, false, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 3: launch_apply2_t<true, true, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+    }
+    FG_LAUNCHED("apply");
+    return FGFRFT_OK;
+  }
   const int nrb = ceil_div(N, AM), ncb = ceil_div(B, AN);
   const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
   if (nblocks > 0x7fffffff) {
