@@ -108,6 +108,37 @@ def cpu_baseline(F, alphas, L, budget_s=15.0):
                 seconds=t_acc)
 
 
+def grad_bench(reps=3):
+    """Order and signal gradients (Proposition 4) on the sphere workload: kNN (k=10) graph on 2048
+    points of the unit sphere, L = 48, 64 orders (one per channel), 64 real signals per order."""
+    import torch
+    import synth
+    from paper_2602_20870_amd import Plan
+
+    cfg = synth.make_config("sphere2048", seed=0, with_signals=False)
+    F, L, N = cfg["F"], cfg["L"], cfg["N"]
+    na, B = 64, 64
+    rng = np.random.default_rng(3)
+    alphas = rng.uniform(-1.5, 1.5, na)
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(rng.standard_normal((na, N, B)).astype(np.float32)).to(dev)
+    GY = torch.from_numpy((rng.standard_normal((na, N, B)) + 1j * rng.standard_normal((na, N, B)))
+                          .astype(np.complex64)).to(dev)
+    plan = Plan(torch.from_numpy(F).to(dev), L)
+    plan.grad(alphas, X, GY, want_dX=True)       # warm-up (kernel attributes, workspace)
+    torch.cuda.synchronize()
+    out = {"workload": f"sphere2048: N={N}, L={L}, {na} orders, {B} real signals per order"}
+    for want_dx in (False, True):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.grad(alphas, X, GY, want_dX=want_dx)
+        torch.cuda.synchronize()
+        out["ms_with_dX" if want_dx else "ms_dalpha_only"] = (time.perf_counter() - t0) * 1e3 / reps
+    del plan, X, GY
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
 
 
@@ -156,6 +187,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stacktype", default="fp32", choices=["fp32", "bf16x2"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -244,6 +276,10 @@ def main():
     torch.cuda.empty_cache()
     out["copy_reference"] = copy_bandwidth(dev)
     log(f"plain copy {out['copy_reference']['GBps']:.0f} GB/s")
+    if not args.no_grad:
+        log("gradients ...")
+        out["grad"] = grad_bench()
+        log(f"grad {out['grad']}")
     if not args.no_serve:
         log("serving trace ...")
         out["serve"] = serving_bench()

@@ -235,33 +235,56 @@ __global__ __launch_bounds__(256) void k_apply(const cplx64* __restrict__ Q, int
 }
 
 // ---------------------------------------------------------------- streaming apply
-// Y[a] = Q[a] X[a] for N % 16 == 0 and B % 64 == 0: 128 output rows x 64 signals per
-// workgroup (wave w: rows 32w..32w+31, both 32-signal blocks), k in stages of 16.  Each stage
-// (16 KB of Q, 4 or 8 KB of X) moves from HBM/L2 straight into LDS with direct loads into a
-// ring of NS stages, so NS - 1 stages are in flight while the matrix cores work on the
+// Y[a] = Q[a] X[a] for N % K2 == 0 and B % 64 == 0: 128 output rows x 64 signals per
+// workgroup (wave w: rows 32w..32w+31, both 32-signal blocks), k in stages of K2.  Each stage
+// (K2 KB of Q, K2/4 or K2/2 KB of X) moves from HBM/L2 straight into LDS with direct loads
+// into a ring of NS stages, so NS - 1 stages are in flight while the matrix cores work on the
 // current one; operands are split into fp16 hi/lo when a wave reads its fragments.  Q rows
-// sit in LDS with their 16-byte chunks swizzled by row (chunk c of row r at c ^ (r & 7)) so
-// the fragment reads of 32 rows hit every bank.
-typedef __attribute__((address_space(3))) void lds_void;
-constexpr int M2 = 128, K2 = 16;
+// sit in LDS with their 16-byte chunks swizzled by row (chunk c of row r at c ^ (r mod CPR),
+// CPR chunks per row) so the fragment reads of 32 rows spread over the banks.
+typedef __attribute__((address_space(3))) char lds_char;
+constexpr int M2 = 128;
 
-template <bool XC>
+__device__ __forceinline__ uint32_t lds_addr(const char* p) { return (uint32_t)(size_t)(const lds_char*)p; }
+
+template <bool XC, int K2>
 struct Apply2Layout {
   static constexpr int QB = M2 * K2 * 8;              // Q stage bytes
   static constexpr int XB = K2 * 64 * (XC ? 8 : 4);   // X stage bytes
   static constexpr int SB = QB + XB;
-  static constexpr int LW = 4 + XB / 4096;            // direct loads per wave per stage
+  static constexpr int QROW = K2 * 8, CPR = K2 / 2, RPI = 1024 / QROW;   // row bytes, chunks, rows per load
+  static constexpr int LW = QB / 4096 + XB / 4096;    // direct loads per wave per stage
+  static_assert((RPI * 4) % CPR == 0, "row swizzle constant per wave");
 };
 
-__host__ __device__ constexpr int vmcnt_wait_imm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (15 << 8); }
+// s_waitcnt immediate (gfx9 encoding): vmcnt <= v and lgkmcnt == 0, expcnt not waited on
+__host__ __device__ constexpr int wait_vm_lgkm0(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
 
-template <bool XC, bool YREAL, int NS>
+// One 16-byte direct HBM-to-LDS load per lane (LDS destination: lds_base + 16 * lane).  Written
+// out here rather than through the builtin so the compiler does not add its own "wait for every
+// direct load" before each LDS read: the ring below waits explicitly for exactly the stage it
+// reads.  The instruction has no register result; hardware reads the address at issue.
+__device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_base), "v"(g)
+               : "memory", "m0");
+}
+
+// Workgroup barrier without a memory fence: the waits it needs are explicit at the call site
+// (a fence here would also wait for every direct LDS load still in flight, i.e. for the whole
+// ring).  The signal fences keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void barrier_nofence() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <bool XC, bool YREAL, int NS, int K2>
 __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q, int N, int n_alpha,
                                                    const void* __restrict__ X, int x_shared, int B,
                                                    const float2* __restrict__ xscale, void* __restrict__ Y, int nrb,
                                                    int ncb) {
-  using LY = Apply2Layout<XC>;
-  constexpr int XE = XC ? 8 : 4;
+  using LY = Apply2Layout<XC, K2>;
+  constexpr int XE = XC ? 8 : 4, CPR = LY::CPR, RPI = LY::RPI;
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
@@ -277,44 +300,62 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
   const float2* xs = xscale + (x_shared ? 0 : (size_t)a * B);
   const int nch = N / K2;
 
+  // Each direct load is a wave-uniform base plus a fixed per-lane 32-bit offset, so the offsets
+  // stay in the same registers for the whole loop.  Q instruction i (i = wave + 4q) moves rows
+  // i0 + RPI i .. + RPI - 1 (a row group past N: any valid rows, never written back; N % 8 == 0
+  // so groups are whole); lane: row + lane / CPR, stored chunk lane % CPR holds chunk
+  // (lane % CPR) ^ (row mod CPR), which is the same for every q of a wave.  X instruction i moves
+  // the next rows of k of the 64 signals.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int qrow = lane / CPR;
+  const uint32_t qoff =
+      (uint32_t)(((size_t)qrow * N + 2 * ((lane % CPR) ^ ((RPI * wv + qrow) % CPR))) * 8);
+  const uint32_t xoff_l = XC ? (uint32_t)(((size_t)(lane >> 5) * B + 2 * (lane & 31)) * 8)
+                             : (uint32_t)(((size_t)(lane >> 4) * B + 4 * (lane & 15)) * 4);
   auto issue = [&](int it) {
     char* st = sm + (it % NS) * LY::SB;
     const int k0 = it * K2;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {   // Q: 16 instructions of 8 rows x 128 bytes
-      const int i = wave + 4 * q;
-      const int row = 8 * i + (lane >> 3), c = (lane & 7) ^ (row & 7);
-      const int grow = i0 + row < N ? i0 + row : N - 1;   // rows past N: any valid row, never written
-      __builtin_amdgcn_global_load_lds(Qa + ((size_t)grow * N + k0 + 2 * c) * 8, (lds_void*)(st + i * 1024), 16, 0, 0);
+    for (int q = 0; q < LY::QB / 4096; ++q) {
+      const int i = wv + 4 * q;
+      const int row0 = i0 + RPI * i < N ? i0 + RPI * i : N - RPI;
+      const char* gb = Qa + ((size_t)row0 * N + k0) * 8;
+      lds_dma16(gb + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
     }
 #pragma unroll
-    for (int q = 0; q < LY::XB / 4096; ++q) {   // X: rows of 64 signals
-      const int i = wave + 4 * q;
-      const int kk = XC ? 2 * i + (lane >> 5) : 4 * i + (lane >> 4);
-      const int cc = XC ? 2 * (lane & 31) : 4 * (lane & 15);
-      __builtin_amdgcn_global_load_lds(Xa + ((size_t)(k0 + kk) * B + b0 + cc) * XE, (lds_void*)(st + LY::QB + i * 1024),
-                                       16, 0, 0);
+    for (int q = 0; q < LY::XB / 4096; ++q) {
+      const int i = wv + 4 * q;
+      const char* gb = Xa + ((size_t)(k0 + (XC ? 2 * i : 4 * i)) * B + b0) * XE;
+      lds_dma16(gb + xoff_l, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
     }
   };
 
   float xsc[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) xsc[c] = xs[b0 + 32 * c + l32].x;
+  // settle these loads before the ring starts: a wait for them inside the loop would also wait
+  // for every direct load issued after them
+  asm volatile("" ::"v"(xsc[0]), "v"(xsc[1]));
   floatx16 acc_re[2] = {}, acc_im[2] = {};
   const int r = 32 * wave + l32;
 
   for (int it = 0; it < NS - 1 && it < nch; ++it) issue(it);
   for (int it = 0; it < nch; ++it) {
-    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(vmcnt_wait_imm((NS - 2) * LY::LW));
-    else __builtin_amdgcn_s_waitcnt(vmcnt_wait_imm(0));
-    __syncthreads();   // stage it has landed for every wave; stage it - 1 is no longer read
+    // this wave's loads of stage it have landed (only the NS - 2 younger stages may still be in
+    // flight) and its reads of stage it - 1 are done; after the barrier that holds for every wave
+    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NS - 2) * LY::LW));
+    else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    barrier_nofence();
+    if (it + NS - 1 < nch) issue(it + NS - 1);   // refills the slot of stage it - 1
     const char* st = sm + (it % NS) * LY::SB;
-    // A: Q[r][8 lh .. 8 lh + 7] (4 chunks of two complex values)
+#pragma unroll
+    for (int ks = 0; ks < K2 / 16; ++ks) {
+    // A: Q[r][16 ks + 8 lh .. + 7] (4 chunks of two complex values)
     shortx8 arh, arl, aih, ail;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int c = (4 * lh + q) ^ (r & 7);
-      const float4 v = *(const float4*)(st + r * 128 + c * 16);
+      const int c = (8 * ks + 4 * lh + q) ^ (r % CPR);
+      const float4 v = *(const float4*)(st + r * LY::QROW + c * 16);
       short h, l;
       split_h(v.x * kStackScale, h, l); arh[2 * q] = h; arl[2 * q] = l;
       split_h(v.y * kStackScale, h, l); aih[2 * q] = h; ail[2 * q] = l;
@@ -327,7 +368,7 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
       const int col = 32 * c + l32;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int k = 8 * lh + j;
+        const int k = 16 * ks + 8 * lh + j;
         short h, l;
         if (XC) {
           const float2 v = *(const float2*)(st + LY::QB + (k * 64 + col) * 8);
@@ -339,8 +380,6 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
         }
       }
     }
-    // the stage's fragments are in registers: refill the ring slot read one iteration ago
-    if (it + NS - 1 < nch) issue(it + NS - 1);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const shortx8 xrh = bxrh[c], xrl = bxrl[c], xih = bxih[c], xil = bxil[c];
@@ -359,6 +398,7 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
         acc_im[c] = mma(arh, xil, acc_im[c]);
         acc_im[c] = mma(arl, xih, acc_im[c]);
       }
+    }
     }
   }
   // write back: lane holds signal b0 + 32c + l32, rows 32 wave + 8(r/4) + 4 lh + r%4
@@ -390,17 +430,17 @@ static void launch_apply_t(dim3 g, hipStream_t s, const cplx64* Q, int N, int n_
   k_apply<ADJ, XC, YR><<<g, 256, 0, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
-template <bool XC, bool YR, int NS>
+template <bool XC, bool YR, int NS, int K2>
 static void launch_apply2_t(unsigned g, hipStream_t s, const cplx64* Q, int N, int n_alpha, const void* X, int x_shared,
                             int B, const float2* sc, void* Y, int nrb, int ncb) {
-  constexpr int lds = NS * Apply2Layout<XC>::SB;
+  constexpr int lds = NS * Apply2Layout<XC, K2>::SB;
   static_assert(lds <= 80 * 1024, "two workgroups per CU");
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_apply2<XC, YR, NS>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_apply2<XC, YR, NS, K2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     attr_set = true;
   }
-  k_apply2<XC, YR, NS><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
+  k_apply2<XC, YR, NS, K2><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
 fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex, int x_shared,
@@ -412,7 +452,8 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
   k_colmax<<<dim3(ceil_div(B, 64) * nx, nch), 256, 0, s>>>(X, x_complex, N, B, partial);
   k_colscale<<<ceil_div(nx * B, 256), 256, 0, s>>>(partial, nch, B, nx, sc);
   FG_LAUNCHED("colscale");
-  if (!adjoint && N % K2 == 0 && B % 64 == 0) {
+  // streaming kernel: k stages of 32 (real signals, 2-stage ring) or 16 (complex, 3-stage ring)
+  if (!adjoint && N % (x_complex ? 16 : 32) == 0 && B % 64 == 0) {
     const int nrb = ceil_div(N, M2), ncb = B / 64;
     const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
     if (nblocks > 0x7fffffff) {
@@ -422,10 +463,10 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
     const cplx64* q = (const cplx64*)Q;
     const int key = (x_complex ? 2 : 0) | (y_real ? 1 : 0);
     switch (key) {
-      case 0: launch_apply2_t<false, false, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
-      case 1: launch_apply2_t<false, true, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
-      case 2: launch_apply2_t<true, false, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
-      case 3: launch_apply2_t<true, true, 3>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 0: launch_apply2_t<false, false, 2, 32>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 1: launch_apply2_t<false, true, 2, 32>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 2: launch_apply2_t<true, false, 3, 16>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+      case 3: launch_apply2_t<true, true, 3, 16>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
     }
     FG_LAUNCHED("apply");
     return FGFRFT_OK;
