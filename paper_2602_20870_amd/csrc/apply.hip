@@ -242,10 +242,7 @@ __global__ __launch_bounds__(256) void k_apply(const cplx64* __restrict__ Q, int
 // current one; operands are split into fp16 hi/lo when a wave reads its fragments.  Q rows
 // sit in LDS with their 16-byte chunks swizzled by row (chunk c of row r at c ^ (r mod CPR),
 // CPR chunks per row) so the fragment reads of 32 rows spread over the banks.
-typedef __attribute__((address_space(3))) char lds_char;
 constexpr int M2 = 128;
-
-__device__ __forceinline__ uint32_t lds_addr(const char* p) { return (uint32_t)(size_t)(const lds_char*)p; }
 
 template <bool XC, int K2>
 struct Apply2Layout {
@@ -256,27 +253,6 @@ struct Apply2Layout {
   static constexpr int LW = QB / 4096 + XB / 4096;    // direct loads per wave per stage
   static_assert((RPI * 4) % CPR == 0, "row swizzle constant per wave");
 };
-
-// s_waitcnt immediate (gfx9 encoding): vmcnt <= v and lgkmcnt == 0, expcnt not waited on
-__host__ __device__ constexpr int wait_vm_lgkm0(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
-
-// One 16-byte direct HBM-to-LDS load per lane (LDS destination: lds_base + 16 * lane).  Written
-// out here rather than through the builtin so the compiler does not add its own "wait for every
-// direct load" before each LDS read: the ring below waits explicitly for exactly the stage it
-// reads.  The instruction has no register result; hardware reads the address at issue.
-__device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds_base) {
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_base), "v"(g)
-               : "memory", "m0");
-}
-
-// Workgroup barrier without a memory fence: the waits it needs are explicit at the call site
-// (a fence here would also wait for every direct LDS load still in flight, i.e. for the whole
-// ring).  The signal fences keep the compiler from moving memory accesses across it.
-__device__ __forceinline__ void barrier_nofence() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 
 template <bool XC, bool YREAL, int NS, int K2>
 __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q, int N, int n_alpha,

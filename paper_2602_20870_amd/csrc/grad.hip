@@ -24,7 +24,8 @@ constexpr int GT = 16, GPOS = 256;
 // 64x64 output tile, 256 threads with 4x4 outputs each, k (signals) in chunks of 16.
 template <bool XC>
 __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, const void* __restrict__ X, int x_shared,
-                                               int N, int B, int a_first, cplx64* __restrict__ G) {
+                                               int N, int B, int a_first, cplx64* __restrict__ G,
+                                               float* __restrict__ gmax) {
   __shared__ float Ar[16][65], Ai[16][65], Br[16][65], Bi[16][65];
   const int tid = threadIdx.x, a = a_first + blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
@@ -68,13 +69,56 @@ __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, co
     __syncthreads();
   }
   cplx64* g = G + (size_t)blockIdx.z * N * N;
+  float m = 0.f;
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
       const int gi = i0 + ti + x, gj = j0 + tj + y;
-      if (gi < N && gj < N) g[(size_t)gi * N + gj] = cplx64{accr[x][y], acci[x][y]};
+      if (gi < N && gj < N) {
+        g[(size_t)gi * N + gj] = cplx64{accr[x][y], acci[x][y]};
+        m = fmaxf(m, fmaxf(fabsf(accr[x][y]), fabsf(acci[x][y])));
+      }
     }
+  // largest |Re|, |Im| of this tile -> gmax[order][tile] (the scale of the split operands)
+  if (gmax) {
+    __syncthreads();
+    float* red = &Ar[0][0];
+    red[tid] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] = fmaxf(red[tid], red[tid + st]);
+      __syncthreads();
+    }
+    if (tid == 0) gmax[(size_t)blockIdx.z * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  }
+}
+
+// per order: 2^e with max |G_a| 2^e in [2^13, 2^14) (fp16 parts stay normal and far from
+// overflow), stored as (scale, 1 / scale)
+__global__ __launch_bounds__(256) void k_gscale(const float* __restrict__ gmax, int ntile, float2* __restrict__ gsc) {
+  __shared__ float red[256];
+  const int a = blockIdx.x;
+  float m = 0.f;
+  for (int t = threadIdx.x; t < ntile; t += 256) m = fmaxf(m, gmax[(size_t)a * ntile + t]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    m = red[0];
+    int e = 0;
+    if (m > 0.f && isfinite(m)) {
+      int E;
+      frexpf(m, &E);
+      e = 14 - E;
+      if (e > 100) e = 100;
+      if (e < -100) e = -100;
+    }
+    gsc[a] = make_float2(ldexpf(1.f, e), ldexpf(1.f, -e));
+  }
 }
 
 // ---------------------------------------------------------------- T partials per tile
@@ -171,6 +215,233 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
   }
 }
 
+// ---------------------------------------------------------------- T partials on the matrix cores
+// T[a][k] = sum_p conj(G_a[p]) B_k[p] is a contraction over the N^2 positions p of
+// [orders x positions] . [positions x k].  One workgroup per CU streams a contiguous range of
+// positions in stages of PC: the stage's G values (64 orders) and its 2L + 1 stack/P rows move
+// into LDS with direct loads (two-stage ring), the identity row is written in place, and 8
+// waves (a-block = w & 1, k-block kb0 + (w >> 1)) run v_mfma_f32_32x32x16_f16 on operands
+// split into fp16 hi/lo (scaled by 2^12 each).  FP32 accumulators are flushed into FP64 every
+// FL stages; per-workgroup FP64 partials are summed over workgroups in a fixed order.
+// Rows of B in LDS: 0..2L-1 stack, 2L P, 2L+1..RD-1 copies (ignored columns), RD identity,
+// then zero rows up to KP2 = 32 KB.  G rows and B rows keep their 16-byte chunks swizzled by
+// row so fragment reads of 32 rows spread over the banks.
+constexpr int IM_NA = 64, IM_NW = 8, IM_FL = 4;
+
+__device__ __forceinline__ void split16h(float v, short& hi, short& lo) {
+  const _Float16 h = (_Float16)v;
+  const _Float16 l = (_Float16)(v - (float)h);
+  hi = __builtin_bit_cast(short, h);
+  lo = __builtin_bit_cast(short, l);
+}
+__device__ __forceinline__ floatx16 mma16(shortx8 a, shortx8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0, 0, 0);
+}
+
+template <bool CPLX, int PC>
+struct InnerLayout {
+  static constexpr int EB = CPLX ? 8 : 4;
+  static constexpr int GROW = PC * 8, GCPR = GROW / 16, GB = IM_NA * GROW;
+  static constexpr int SROW = PC * EB, SCPR = SROW / 16, SRPI = 1024 / SROW;
+  __host__ __device__ static int rd(int L) { return (2 * L + 1 + SRPI - 1) / SRPI * SRPI; }   // rows moved by direct loads
+  __host__ __device__ static int kp2(int L) { return (rd(L) + 1 + 31) / 32 * 32; }
+  __host__ __device__ static size_t stage_bytes(int L) { return (size_t)GB + (size_t)kp2(L) * SROW; }
+};
+
+template <bool CPLX, int PC, int KBW>
+__global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __restrict__ stack, const void* __restrict__ Pm,
+                                                             int N, int L, const cplx64* __restrict__ G, int n_c,
+                                                             const float2* __restrict__ gsc, int spw, int nstage,
+                                                             int kb0, double* __restrict__ partial) {
+  using LY = InnerLayout<CPLX, PC>;
+  constexpr int EB = LY::EB, NPL = CPLX ? 2 : 1;
+  extern __shared__ __align__(16) char smc[];
+  char* sm = smc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int ab = wave & 1, kg = wave >> 1;
+  const int RD = LY::rd(L), KP2 = LY::kp2(L), KB = KP2 / 32;
+  const size_t SB = LY::stage_bytes(L);
+  const size_t NN = (size_t)N * N;
+  const int st0 = blockIdx.x * spw, st1 = st0 + spw < nstage ? st0 + spw : nstage;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+
+  // zero rows past the identity row (both ring slots); never written afterwards
+  for (int s = 0; s < 2; ++s) {
+    uint32_t* z = (uint32_t*)(sm + s * SB + LY::GB + (size_t)(RD + 1) * LY::SROW);
+    for (int e = tid; e < (KP2 - RD - 1) * LY::SROW / 4; e += 64 * IM_NW) z[e] = 0u;
+  }
+
+  auto issue = [&](int st) {
+    char* buf = sm + (st & 1) * SB;
+    const size_t p0 = (size_t)st * PC;
+    // G: instruction i moves order rows 1024/GROW * i .. (orders past n_c read order 0)
+    for (int i = wv; i < LY::GB / 1024; i += IM_NW) {
+      const int r = i * (1024 / LY::GROW) + lane / LY::GCPR, sl = lane % LY::GCPR;
+      const int c = sl ^ (r % LY::GCPR);
+      const int a = r < n_c ? r : 0;
+      lds_dma16((const char*)(G + (size_t)a * NN + p0 + 2 * c), __builtin_amdgcn_readfirstlane(lds_addr(buf + i * 1024)));
+    }
+    // B rows 0..RD-1: stack matrices, P, then copies of P
+    for (int i = wv; i < RD / LY::SRPI; i += IM_NW) {
+      const int k = i * LY::SRPI + lane / LY::SCPR, sl = lane % LY::SCPR;
+      const int c = sl ^ (k % LY::SCPR);
+      const char* src = k < 2 * L ? (const char*)stack + (size_t)k * NN * EB : (const char*)Pm;
+      lds_dma16(src + (p0 + (size_t)c * (16 / EB)) * EB,
+                __builtin_amdgcn_readfirstlane(lds_addr(buf + LY::GB + i * 1024)));
+    }
+    // identity row RD
+    for (int e = tid; e < PC; e += 64 * IM_NW) {
+      const size_t p = p0 + e;
+      const int c = (e * EB / 16) ^ (RD % LY::SCPR);
+      float* dst = (float*)(buf + LY::GB + (size_t)RD * LY::SROW + c * 16 + (e * EB) % 16);
+      dst[0] = (p % (size_t)(N + 1)) == 0 ? 1.f : 0.f;
+      if (CPLX) dst[1] = 0.f;
+    }
+  };
+
+  floatx16 fre[KBW], fim[KBW];
+  double dre[KBW][16], dim[KBW][16];
+#pragma unroll
+  for (int m = 0; m < KBW; ++m) {
+    fre[m] = floatx16{}; fim[m] = floatx16{};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) { dre[m][e] = 0.0; dim[m][e] = 0.0; }
+  }
+  const int r = 32 * ab + l32;
+  const float ascale = r < n_c ? gsc[r].x : 1.f;   // this lane's order row
+  // settle that load before the ring starts (a wait for it later would wait for the ring too)
+  asm volatile("" ::"v"(ascale));
+  if (st0 < st1) issue(st0);
+  int since = 0;
+  for (int st = st0; st < st1; ++st) {
+    // this wave's loads of stage st (the only ones in flight) and its LDS reads are complete
+    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    barrier_nofence();
+    if (st + 1 < st1) issue(st + 1);   // fills the slot read in the previous stage
+    const char* buf = sm + (st & 1) * SB;
+#pragma unroll
+    for (int ks = 0; ks < PC / 16; ++ks) {
+      shortx8 arh, arl, aih, ail;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {   // G[r][16 ks + 8 lh .. + 7]: chunks of two complex
+        const int c = (8 * ks + 4 * lh + q) ^ (r % LY::GCPR);
+        const float4 v = *(const float4*)(buf + (size_t)r * LY::GROW + c * 16);
+        short h, l;
+        split16h(v.x * ascale, h, l); arh[2 * q] = h; arl[2 * q] = l;
+        split16h(v.y * ascale, h, l); aih[2 * q] = h; ail[2 * q] = l;
+        split16h(v.z * ascale, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
+        split16h(v.w * ascale, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+      }
+#pragma unroll
+      for (int m = 0; m < KBW; ++m) {
+        const int kb = kb0 + kg + 4 * m;
+        if (kb >= KB) break;
+        const int k = 32 * kb + l32;
+        shortx8 brh, brl, bih, bil;
+        const char* row = buf + LY::GB + (size_t)k * LY::SROW;
+        if (CPLX) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {   // two complex per chunk
+            const int c = (8 * ks + 4 * lh + q) ^ (k % LY::SCPR);
+            const float4 v = *(const float4*)(row + c * 16);
+            short h, l;
+            split16h(v.x * kStackScale, h, l); brh[2 * q] = h; brl[2 * q] = l;
+            split16h(v.y * kStackScale, h, l); bih[2 * q] = h; bil[2 * q] = l;
+            split16h(v.z * kStackScale, h, l); brh[2 * q + 1] = h; brl[2 * q + 1] = l;
+            split16h(v.w * kStackScale, h, l); bih[2 * q + 1] = h; bil[2 * q + 1] = l;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {   // four reals per chunk
+            const int c = (4 * ks + 2 * lh + q) ^ (k % LY::SCPR);
+            const float4 v = *(const float4*)(row + c * 16);
+            short h, l;
+            split16h(v.x * kStackScale, h, l); brh[4 * q] = h; brl[4 * q] = l;
+            split16h(v.y * kStackScale, h, l); brh[4 * q + 1] = h; brl[4 * q + 1] = l;
+            split16h(v.z * kStackScale, h, l); brh[4 * q + 2] = h; brl[4 * q + 2] = l;
+            split16h(v.w * kStackScale, h, l); brh[4 * q + 3] = h; brl[4 * q + 3] = l;
+          }
+        }
+        // conj(g) b: Re = gr br + gi bi, Im = gr bi - gi br (real b: Re = gr b, Im = -gi b)
+        fre[m] = mma16(arh, brh, fre[m]);
+        fre[m] = mma16(arh, brl, fre[m]);
+        fre[m] = mma16(arl, brh, fre[m]);
+        fim[m] = mma16(aih, brh, fim[m]);
+        fim[m] = mma16(aih, brl, fim[m]);
+        fim[m] = mma16(ail, brh, fim[m]);
+        if (CPLX) {
+          fre[m] = mma16(aih, bih, fre[m]);
+          fre[m] = mma16(aih, bil, fre[m]);
+          fre[m] = mma16(ail, bih, fre[m]);
+          // Im accumulates gi br (subtracted at the end) minus gr bi: add (-gr) bi here
+          const shortx8 narh = arh ^ (short)0x8000, narl = arl ^ (short)0x8000;
+          fim[m] = mma16(narh, bih, fim[m]);
+          fim[m] = mma16(narh, bil, fim[m]);
+          fim[m] = mma16(narl, bih, fim[m]);
+        }
+      }
+    }
+    if (++since == IM_FL || st + 1 == st1) {   // flush into FP64
+      since = 0;
+#pragma unroll
+      for (int m = 0; m < KBW; ++m)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          dre[m][e] += (double)fre[m][e];
+          dim[m][e] += (double)fim[m][e];
+          fre[m][e] = 0.f;
+          fim[m][e] = 0.f;
+        }
+    }
+  }
+  // partial[blockIdx][a][kk][re, im]: lane holds k column 32 kb + l32, orders
+  // 32 ab + 8 (e / 4) + 4 lh + e % 4; column RD is the identity (kk = 2L + 1)
+  const int K = 2 * L + 2;
+#pragma unroll
+  for (int m = 0; m < KBW; ++m) {
+    const int kb = kb0 + kg + 4 * m;
+    if (kb >= KB) break;
+    const int k = 32 * kb + l32;
+    const int kk = k <= 2 * L ? k : (k == RD ? 2 * L + 1 : -1);
+    if (kk < 0) continue;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int a = 32 * ab + 8 * (e >> 2) + 4 * lh + (e & 3);
+      if (a < n_c) {
+        const double unscale = (double)gsc[a].y / (double)kStackScale;
+        const size_t o = (((size_t)blockIdx.x * n_c + a) * K + kk) * 2;
+        partial[o] = dre[m][e] * unscale;
+        partial[o + 1] = -dim[m][e] * unscale;
+      }
+    }
+  }
+}
+
+// T[a][k] = sum over workgroups in a fixed order (FP64).
+__global__ __launch_bounds__(256) void k_inner_sum_wg(const double* __restrict__ partial, int nwg, int n_c, int K,
+                                                      int a_first, double* __restrict__ T) {
+  __shared__ double rr[256], ri[256];
+  const int a = blockIdx.y, k = blockIdx.x;
+  double sr = 0.0, si = 0.0;
+  for (int g = threadIdx.x; g < nwg; g += 256) {
+    const size_t o = (((size_t)g * n_c + a) * K + k) * 2;
+    sr += partial[o];
+    si += partial[o + 1];
+  }
+  rr[threadIdx.x] = sr;
+  ri[threadIdx.x] = si;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { rr[threadIdx.x] += rr[threadIdx.x + s]; ri[threadIdx.x] += ri[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    T[((size_t)(a_first + a) * K + k) * 2] = rr[0];
+    T[((size_t)(a_first + a) * K + k) * 2 + 1] = ri[0];
+  }
+}
+
 // T[a][k] = sum over tiles and both halves, in a fixed order, in FP64.
 __global__ __launch_bounds__(256) void k_inner_sum(const double* __restrict__ partial, int ntiles, int n_chunk, int K,
                                                    int a_first, double* __restrict__ T) {
@@ -218,9 +489,14 @@ __global__ __launch_bounds__(256) void k_sum_orders(const void* __restrict__ Y, 
 }
 
 // ---------------------------------------------------------------- host
+// Orders per pass: the G (and Q(-alpha)) chunk buffer holds ch N x N complex64 matrices; up to 64
+// orders (two MFMA row blocks) within about 4 GB, at least 8.
 static int grad_chunk(const Plan* p, int n_alpha) {
-  (void)p;
-  return n_alpha < 8 ? n_alpha : 8;
+  const size_t per = (size_t)p->N * p->N * 8;
+  size_t ch = ((size_t)4 << 30) / per;
+  if (ch > 64) ch = 64;
+  if (ch < 8) ch = 8;
+  return n_alpha < (int)ch ? n_alpha : (int)ch;
 }
 
 static size_t inner_lds(const Plan* p) {
@@ -228,17 +504,32 @@ static size_t inner_lds(const Plan* p) {
   return ((size_t)GPOS * 2 * p->L * NPL + GPOS * NPL + (size_t)AC * GPOS * 2) * sizeof(float);
 }
 
+// matrix-core inner products: stages of 64 positions (real stack) or 32 (complex), N % 8 == 0
+static bool inner_mfma_ok(const Plan* p) {
+  if (p->N % 8) return false;
+  const size_t lds = 2 * (p->cplx ? InnerLayout<true, 32>::stage_bytes(p->L) : InnerLayout<false, 64>::stage_bytes(p->L));
+  const int kp2 = p->cplx ? InnerLayout<true, 32>::kp2(p->L) : InnerLayout<false, 64>::kp2(p->L);
+  return lds <= 160 * 1024 && kp2 <= 256;
+}
+static int inner_mfma_wgs() { return 256; }
+
 size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   const int ch = grad_chunk(p, n_alpha);
   const int N = p->N, nb = ceil_div(N, GT), npairs = nb * nb, K = 2 * p->L + 2;
+  const size_t ntile = (size_t)ceil_div(N, 64) * ceil_div(N, 64);
+  size_t part = (size_t)npairs * ch * 2 * K * 16;                   // partials (complex FP64)
+  const size_t part2 = (size_t)inner_mfma_wgs() * ch * K * 16;
+  if (part2 > part) part = part2;
   size_t s = 0;
   s += align_up((size_t)ch * N * N * 8, 256);                       // G chunk / Q(-alpha) chunk
-  s += align_up((size_t)npairs * ch * 2 * K * 16, 256);             // partials (complex FP64)
+  s += align_up(part, 256);
   s += align_up((size_t)n_alpha * K * 16, 256);                     // T
   s += align_up((size_t)ch * N * B * 8, 256);                       // dX chunk (shared X)
   s += update_ws_bytes(p, ch);
   s += apply_ws_bytes(N, ch, B, 0);
   s += align_up((size_t)n_alpha * 8, 256);
+  s += align_up((size_t)ch * ntile * 4, 256);                       // tile maxima of G
+  s += align_up((size_t)ch * 8, 256);                               // G scales
   (void)x_shared;
   return s;
 }
@@ -254,6 +545,29 @@ static void coefficient_derivatives(double alpha, int L, std::vector<double>& d)
   }
 }
 
+static int inner_mfma_grid(const Plan* p) {
+  const int pc = p->cplx ? 32 : 64;
+  const int nstage = (int)(((size_t)p->N * p->N) / pc);
+  return nstage < inner_mfma_wgs() ? nstage : inner_mfma_wgs();
+}
+
+template <bool CPLX, int PC>
+static fgfrft_status inner_mfma_launch(const Plan* p, const cplx64* G, int nc, const float2* gsc, double* partial,
+                                       hipStream_t s) {
+  using LY = InnerLayout<CPLX, PC>;
+  const int nstage = (int)(((size_t)p->N * p->N) / PC);
+  const int nwg = inner_mfma_grid(p), spw = ceil_div(nstage, nwg);
+  const int lds = (int)(2 * LY::stage_bytes(p->L));
+  const int KB = LY::kp2(p->L) / 32;
+  FG_HIP(hipFuncSetAttribute((const void*)k_inner_mfma<CPLX, PC, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  // four k-blocks (one per wave pair) per pass over the positions
+  for (int kb0 = 0; kb0 < KB; kb0 += 4)
+    k_inner_mfma<CPLX, PC, 1><<<nwg, 64 * IM_NW, lds, s>>>(p->stack, p->P, p->N, p->L, G, nc, gsc, spw, nstage, kb0,
+                                                           partial);
+  FG_LAUNCHED("inner_mfma");
+  return FGFRFT_OK;
+}
+
 fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const void* X, int x_complex, int x_shared,
                        int B, const void* GY, double* dalpha, void* dX, void* ws, size_t ws_bytes, hipStream_t s) {
   const int N = p->N, L = p->L, K = 2 * L + 2;
@@ -263,14 +577,21 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
     set_error("grad workspace too small: %zu < %zu", ws_bytes, grad_ws_bytes(p, n_alpha, B, x_shared));
     return FGFRFT_ENOMEM;
   }
+  const size_t ntile = (size_t)ceil_div(N, 64) * ceil_div(N, 64);
+  size_t part = (size_t)npairs * ch * 2 * K * 16;
+  const size_t part2 = (size_t)inner_mfma_wgs() * ch * K * 16;
+  if (part2 > part) part = part2;
   char* base = (char*)ws;
   cplx64* Gbuf = (cplx64*)base; base += align_up((size_t)ch * N * N * 8, 256);
-  double* partial = (double*)base; base += align_up((size_t)npairs * ch * 2 * K * 16, 256);
+  double* partial = (double*)base; base += align_up(part, 256);
   double* T = (double*)base; base += align_up((size_t)n_alpha * K * 16, 256);
   void* dXc = base; base += align_up((size_t)ch * N * B * 8, 256);
   void* uws = base; base += update_ws_bytes(p, ch);
   void* aws = base; base += apply_ws_bytes(N, ch, B, 0);
-  double* neg_dev = (double*)base;
+  double* neg_dev = (double*)base; base += align_up((size_t)n_alpha * 8, 256);
+  float* gmax = (float*)base; base += align_up((size_t)ch * ntile * 4, 256);
+  float2* gsc = (float2*)base;
+  const bool use_mfma = inner_mfma_ok(p);
 
   const size_t lds = inner_lds(p);
   static bool attr[2] = {false, false};
@@ -304,15 +625,26 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
     {
       dim3 g(ceil_div(N, 64), ceil_div(N, 64), nc);
       const void* xa = x_shared ? X : (const void*)((const char*)X + (size_t)a0 * NB * (x_complex ? 8 : 4));
-      if (x_complex) k_outer<true><<<g, 256, 0, s>>>(gy + (size_t)a0 * NB, xa, x_shared, N, B, 0, Gbuf);
-      else k_outer<false><<<g, 256, 0, s>>>(gy + (size_t)a0 * NB, xa, x_shared, N, B, 0, Gbuf);
+      float* gm = use_mfma ? gmax : nullptr;
+      if (x_complex) k_outer<true><<<g, 256, 0, s>>>(gy + (size_t)a0 * NB, xa, x_shared, N, B, 0, Gbuf, gm);
+      else k_outer<false><<<g, 256, 0, s>>>(gy + (size_t)a0 * NB, xa, x_shared, N, B, 0, Gbuf, gm);
       FG_LAUNCHED("outer");
     }
-    if (p->cplx) k_inner<true><<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
-    else k_inner<false><<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
-    FG_LAUNCHED("inner");
-    k_inner_sum<<<dim3(K, nc), 256, 0, s>>>(partial, npairs, nc, K, a0, T);
-    FG_LAUNCHED("inner_sum");
+    if (use_mfma) {
+      k_gscale<<<nc, 256, 0, s>>>(gmax, (int)ntile, gsc);
+      FG_LAUNCHED("gscale");
+      fgfrft_status rc = p->cplx ? inner_mfma_launch<true, 32>(p, Gbuf, nc, gsc, partial, s)
+                                 : inner_mfma_launch<false, 64>(p, Gbuf, nc, gsc, partial, s);
+      if (rc) return rc;
+      k_inner_sum_wg<<<dim3(K, nc), 256, 0, s>>>(partial, inner_mfma_grid(p), nc, K, a0, T);
+      FG_LAUNCHED("inner_sum");
+    } else {
+      if (p->cplx) k_inner<true><<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
+      else k_inner<false><<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
+      FG_LAUNCHED("inner");
+      k_inner_sum<<<dim3(K, nc), 256, 0, s>>>(partial, npairs, nc, K, a0, T);
+      FG_LAUNCHED("inner_sum");
+    }
   }
   std::vector<double> Th((size_t)n_alpha * K * 2);
   FG_HIP(hipMemcpyAsync(Th.data(), T, Th.size() * 8, hipMemcpyDeviceToHost, s));

@@ -25,6 +25,32 @@ constexpr float kStackScale = 4096.0f;
 constexpr float kCoefScale = 4096.0f;
 constexpr float kUnscale = 1.0f / (4096.0f * 4096.0f);
 
+// ---------------------------------------------------------------- device helpers
+typedef __attribute__((address_space(3))) char lds_char;
+__device__ __forceinline__ uint32_t lds_addr(const char* p) { return (uint32_t)(size_t)(const lds_char*)p; }
+
+// s_waitcnt immediate (gfx9 encoding): vmcnt <= v and lgkmcnt == 0, expcnt not waited on
+__host__ __device__ constexpr int wait_vm_lgkm0(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4); }
+
+// One 16-byte direct HBM-to-LDS load per lane (LDS destination: lds_base + 16 * lane).  Written
+// out here rather than through the builtin so the compiler does not add its own "wait for every
+// direct load" before each LDS read: a multi-stage ring waits explicitly for exactly the stage
+// it reads.  The instruction has no register result; hardware reads the address at issue.  Callers
+// wait for these loads with explicit s_waitcnt (vmcnt) before reading the LDS they fill.
+__device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds_base), "v"(g)
+               : "memory", "m0");
+}
+
+// Workgroup barrier without a memory fence: the waits it needs are explicit at the call site
+// (a fence here would also wait for every direct LDS load still in flight, i.e. for the whole
+// ring).  The signal fences keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void barrier_nofence() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // ---------------------------------------------------------------- plan object
 struct Plan {
   int N = 0, L = 0, LP = 0;        // LP: L padded to a multiple of 32 (MFMA k extent)

@@ -236,3 +236,28 @@ def test_grad_against_oracle(xc, shared, cplxF):
     dX = dX.cpu().numpy()
     dX_ref = dX_ref.sum(axis=0) if shared else dX_ref
     assert rel_fro(dX, dX_ref) <= TOL_FP32
+
+
+@pytest.mark.parametrize("N,L,n,cplxF", [(50, 9, 5, False),    # N % 8 != 0: per-tile inner products
+                                         (64, 64, 3, False),   # five k-blocks: two passes over the positions
+                                         (40, 5, 70, False),   # two chunks of orders
+                                         (56, 32, 4, True)])   # complex stack, three k-blocks
+def test_grad_paths(N, L, n, cplxF):
+    torch = torch_cuda()
+    announce(f"grad paths N={N} L={L} n={n} complexF={cplxF}")
+    rng = np.random.default_rng(N + L + n)
+    F = synth.haar_unitary(N, rng) if cplxF else _real_orthogonal_with_minus1(N, 3, 13)
+    alphas = rng.uniform(-min(L - 0.5, 3.0), min(L - 0.5, 3.0), n)
+    alphas[0] = 1.0
+    B = 7
+    X = synth.real_signals((n, N, B), rng).astype(np.float32)
+    # G = GY X^H spans several decades across orders: the per-order operand scale must follow it
+    GY = ((rng.standard_normal((n, N, B)) + 1j * rng.standard_normal((n, N, B)))
+          * np.logspace(-3, 3, n)[:, None, None]).astype(np.complex64)
+    plan = _gpu_plan(torch, F, L)
+    ref = O.Plan(F, L)
+    dal_ref, dX_ref = O.grad(ref.P, ref.M, alphas, X.astype(np.float64), GY.astype(np.complex128), x_real=True)
+    dal, dX = plan.grad(alphas, torch.from_numpy(X).cuda(), torch.from_numpy(GY).cuda())
+    for a in range(n):   # each order against its own magnitude
+        assert abs(dal[a] - dal_ref[a]) <= TOL_FP32 * max(abs(dal_ref[a]), 1e-3 * np.max(np.abs(GY[a]))), a
+    assert rel_fro(dX.cpu().numpy(), dX_ref) <= TOL_FP32
