@@ -139,15 +139,62 @@ def grad_bench(reps=3):
     return out
 
 
+def table4_bench(sizes=(1000, 2000, 3000, 4000, 5000, 6000, 7000, 8000), L=10, alpha=0.5, reps=5):
+    """Online time of FGFRFT (operator update for one order) and of the exact GFRFT from a cached
+    eigendecomposition (V diag(e^{j alpha theta}) V^H), both on the GPU, plus the accuracy of FGFRFT
+    against the exact operator: Haar-random eigenvectors, uniform eigenphases, L = 10, alpha = 0.5."""
+    import torch
+    import synth
+    from paper_2602_20870_amd import Plan, gfrft_exact
+
+    dev = torch.device("cuda:0")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    rows = []
+    for N in sizes:
+        t0 = time.time()
+        rng = np.random.default_rng(N)
+        V = torch.from_numpy(synth.haar_unitary(N, rng)).to(dev)
+        theta = torch.from_numpy(rng.uniform(-np.pi, np.pi, N)).to(dev)
+        Vh = V.conj().T.contiguous()
+        F = gfrft_exact(V, Vh, theta, 1.0)            # F = V diag(e^{j theta}) V^H
+        plan = Plan(F, L)
+        Q = torch.empty((1, N, N), dtype=torch.complex64, device=dev)
+        Fa = torch.empty((N, N), dtype=torch.complex128, device=dev)
+        times = {}
+        for name, fn in (("fgfrft", lambda: plan.update([alpha], out=Q)),
+                         ("exact", lambda: gfrft_exact(V, Vh, theta, alpha, out=Fa))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            times[name] = e0.elapsed_time(e1) / reps
+        E = Q[0].to(torch.complex128) - Fa
+        f2 = float((E.abs() ** 2).sum())
+        row = dict(N=N, fgfrft_ms=times["fgfrft"], exact_ms=times["exact"], speedup=times["exact"] / times["fgfrft"],
+                   MSE=f2 / N ** 2, MAE=float(E.abs().sum()) / N ** 2, NMSE=f2 / N)
+        log(f"table4 {row} ({time.time() - t0:.0f}s)")
+        rows.append(row)
+        del V, Vh, F, plan, Q, Fa, E, theta
+        torch.cuda.empty_cache()
+    return {"workload": f"Haar eigenvectors, uniform phases, L={L}, alpha={alpha}", "rows": rows}
+
+
 SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
 
 
-def serving_bench(n_requests=4000, warmup=500, rate=5000.0, L=32):
+def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=16, slot_sets=1, per_request=True,
+                  warm_trace=4000):
     """p50/p99 latency of the continuous-batching server vs one launch per request.
 
     8 resident plans from kNN graphs (k=10, Gaussian weights) on 3-D GMM points with
     N in {256, 512, 1024, 1024, 2048, 2048, 4096, 4096}, L = 32; Poisson arrivals at
     `rate` requests/s; each request: graph uniform, order U[-2, 2], 1..64 real signals.
+    After an untimed warm-up trace, `n_requests` are replayed and the first `warmup` of them
+    are left out of the statistics.
     """
     import torch
     import synth
@@ -158,20 +205,26 @@ def serving_bench(n_requests=4000, warmup=500, rate=5000.0, L=32):
           for g, N in enumerate(SERVE_NS)}
     rng = np.random.default_rng(7)
     sig = {g: rng.standard_normal((F.shape[0], 64)).astype(np.float32) for g, F in Fs.items()}
-    srv = serve.Server(hbm_budget=120 << 30, K=16, bmax=64, slot_sets=2, use_graphs=True)
+    srv = serve.Server(hbm_budget=120 << 30, K=K, bmax=64, slot_sets=slot_sets, use_graphs=True)
     for g, F in Fs.items():
         srv.add_plan(g, F, L)
     torch.cuda.synchronize()
     log(f"serving: {len(Fs)} plans resident ({srv.used / 1e9:.1f} GB) in {time.time() - t0:.1f}s")
+    if warm_trace:   # an untimed trace first: first-use costs of graphs, staging and caches
+        serve.run_trace(srv, serve.poisson_trace(warm_trace, rate, list(Fs), 64, seed=10), sig)
     trace = serve.poisson_trace(n_requests, rate, list(Fs), 64, seed=11)
     batched = serve.run_trace(srv, trace, sig, warmup=warmup)
-    per_req = serve.run_trace_per_request(srv.plans, trace, sig, warmup=warmup)
-    worst = 0.0
-    for f, y in zip(batched.pop("futures"), per_req.pop("outputs")):
-        r = f.result()
-        worst = max(worst, float(np.linalg.norm(r - y) / max(np.linalg.norm(y), 1e-30)))
-    out = {"batched": batched, "one_launch_per_request": per_req, "max_rel_diff_between_modes": worst,
-           "rate_req_s": rate, "requests": n_requests, "warmup": warmup, "plans_N": list(SERVE_NS), "L": L}
+    out = {"batched": batched, "rate_req_s": rate, "requests": n_requests, "warmup": warmup,
+           "plans_N": list(SERVE_NS), "L": L, "K": K, "slot_sets": slot_sets}
+    futures = batched.pop("futures")
+    if per_request:
+        per_req = serve.run_trace_per_request(srv.plans, trace, sig, warmup=warmup)
+        worst = 0.0
+        for f, y in zip(futures, per_req.pop("outputs")):
+            r = f.result()
+            worst = max(worst, float(np.linalg.norm(r - y) / max(np.linalg.norm(y), 1e-30)))
+        out["one_launch_per_request"] = per_req
+        out["max_rel_diff_between_modes"] = worst
     del srv
     torch.cuda.empty_cache()
     return out
@@ -188,6 +241,8 @@ def main():
     ap.add_argument("--stacktype", default="fp32", choices=["fp32", "bf16x2"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--table4", action="store_true",
+                    help="only the Table IV workload (FGFRFT vs exact GFRFT online time, N = 1000..8000)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -198,6 +253,9 @@ def main():
     from paper_2602_20870_amd import Plan, apply_operator, lib
 
     lib()  # fail loudly if the HIP library is missing
+    if args.table4:
+        print(json.dumps({"table4": table4_bench()}), flush=True)
+        return
     dev = torch.device("cuda:0")
     t0 = time.time()
     cfg = synth.make_config("knn4096", seed=0, n_alpha=args.n_alpha, with_signals=False)

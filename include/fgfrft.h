@@ -207,6 +207,23 @@ FGFRFT_API fgfrft_status fgfrft_grad(fgfrft_plan_t plan, const double* alphas, i
                                      void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Exact GFRFT online stage (the comparison method, Sec. II / Table IV)
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for fgfrft_gfrft_exact: one N x N complex128 matrix. */
+FGFRFT_API size_t fgfrft_gfrft_exact_workspace_bytes(int N);
+
+/* F^alpha = V diag(e^{j alpha theta}) V^H from a cached eigendecomposition of the unitary F
+ * (the offline eigendecomposition is the caller's; the paper also excludes it from its online
+ * timings).  V_dev and Vh_dev = V^H: complex128 N x N row-major; theta_dev: float64 [N] phases
+ * in (-pi, pi]; out_dev: complex128 N x N.  FP64 throughout: the columns of V are scaled by
+ * e^{j alpha theta_k} (FP64 sin/cos), then one complex FP64 GEMM on the matrix cores
+ * (8 N^3 flops).  Any finite alpha.  1 <= N <= 32768. */
+FGFRFT_API fgfrft_status fgfrft_gfrft_exact(const void* V_dev, const void* Vh_dev, const double* theta_dev, int N,
+                                            double alpha, void* out_dev, void* ws_dev, size_t ws_bytes,
+                                            void* stream);
+
+/* ---------------------------------------------------------------------------
  * Errors
  * ------------------------------------------------------------------------- */
 FGFRFT_API const char* fgfrft_strerror(int status);

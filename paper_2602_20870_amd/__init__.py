@@ -7,7 +7,7 @@ from ._lib import FGFRFTError, LIB_PATH, lib  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("Plan", "apply_operator"):
+    if name in ("Plan", "apply_operator", "gfrft_exact"):
         from . import ops
         return getattr(ops, name)
     if name == "FGFRFTFunction":

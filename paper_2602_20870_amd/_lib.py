@@ -32,6 +32,9 @@ SIGNATURES = {
     "fgfrft_grad_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "fgfrft_grad": (c_int, [c_void_p, P_double, c_int, c_void_p, c_int, c_int, c_int, c_void_p, P_double,
                             c_void_p, c_void_p, c_size_t, c_void_p]),
+    "fgfrft_gfrft_exact_workspace_bytes": (c_size_t, [c_int]),
+    "fgfrft_gfrft_exact": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_size_t,
+                                   c_void_p]),
     "fgfrft_strerror": (ctypes.c_char_p, [c_int]),
     "fgfrft_last_error": (ctypes.c_char_p, []),
 }

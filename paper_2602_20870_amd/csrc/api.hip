@@ -1,5 +1,6 @@
 // C ABI of the FGFRFT library: argument validation, buffer carving and dispatch.
 #include "internal.h"
+#include <cmath>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -248,5 +249,22 @@ const char* fgfrft_strerror(int status) {
 }
 
 const char* fgfrft_last_error(void) { return g_err; }
+
+size_t fgfrft_gfrft_exact_workspace_bytes(int N) {
+  if (N < 1 || N > 32768) return 0;
+  return align_up((size_t)N * N * 16, 256);
+}
+
+fgfrft_status fgfrft_gfrft_exact(const void* V_dev, const void* Vh_dev, const double* theta_dev, int N, double alpha,
+                                 void* out_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > 32768) { set_error("N=%d outside [1, 32768]", N); return FGFRFT_EINVAL; }
+  if (!std::isfinite(alpha)) { set_error("alpha is not finite"); return FGFRFT_EALPHA; }
+  if (!V_dev || !Vh_dev || !theta_dev || !out_dev || !ws_dev) { set_error("NULL pointer"); return FGFRFT_EINVAL; }
+  if (ws_bytes < fgfrft_gfrft_exact_workspace_bytes(N)) {
+    set_error("workspace %zu < %zu bytes", ws_bytes, fgfrft_gfrft_exact_workspace_bytes(N));
+    return FGFRFT_ENOMEM;
+  }
+  return gfrft_exact_run(V_dev, Vh_dev, theta_dev, N, alpha, out_dev, ws_dev, (hipStream_t)stream);
+}
 
 }  // extern "C"

@@ -88,6 +88,8 @@ fgfrft_status gemm_f64(bool cplx, bool conj_a, int M, int Ncols, int K, const vo
 fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size_t scratch_bytes,
                          hipStream_t s);
 size_t plan_scratch_bytes(int N, int L, bool cplx);
+fgfrft_status gfrft_exact_run(const void* V, const void* Vh, const double* theta, int N, double alpha, void* out,
+                              void* ws, hipStream_t s);
 
 // Online side (update.hip)
 size_t update_ws_bytes(const Plan* p, int n_alpha);

@@ -500,6 +500,28 @@ static int grid_for(size_t total) {
   return (int)g;
 }
 
+// ---- exact GFRFT online stage: W = V diag(e^{j alpha theta}), F^alpha = W V^H
+__global__ __launch_bounds__(256) void k_phase_columns(const double* __restrict__ V, const double* __restrict__ theta,
+                                                       int N, double alpha, double* __restrict__ W) {
+  const size_t total = (size_t)N * N;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int k = (int)(e % N);
+    double sn, cs;
+    sincos(alpha * theta[k], &sn, &cs);
+    const double vr = V[2 * e], vi = V[2 * e + 1];
+    W[2 * e] = vr * cs - vi * sn;
+    W[2 * e + 1] = vr * sn + vi * cs;
+  }
+}
+
+fgfrft_status gfrft_exact_run(const void* V, const void* Vh, const double* theta, int N, double alpha, void* out,
+                              void* ws, hipStream_t s) {
+  const size_t total = (size_t)N * N;
+  k_phase_columns<<<grid_for(total), 256, 0, s>>>((const double*)V, theta, N, alpha, (double*)ws);
+  FG_LAUNCHED("phase_columns");
+  return gemm_f64(true, false, N, N, N, ws, N, Vh, N, out, N, s);
+}
+
 fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size_t scratch_bytes, hipStream_t s) {
   const int N = p->N, L = p->L;
   const bool C = p->cplx != 0;

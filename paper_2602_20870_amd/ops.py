@@ -225,3 +225,21 @@ def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_re
     check(L_.fgfrft_apply_operator(_ptr(Q), N, n, int(adjoint), _ptr(X), xc, int(x_shared), B, _ptr(Y), int(y_real),
                                    _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply_operator")
     return Y
+
+
+def gfrft_exact(V: torch.Tensor, Vh: torch.Tensor, theta: torch.Tensor, alpha: float,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Exact GFRFT from a cached eigendecomposition: V diag(e^{j alpha theta}) V^H (complex128)."""
+    for t, name in ((V, "V"), (Vh, "Vh")):
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+            raise ValueError(f"{name} must be a contiguous complex128 cuda matrix")
+    N = V.shape[0]
+    if theta.dtype != torch.float64 or not theta.is_cuda or theta.numel() != N:
+        raise ValueError("theta must be a float64 cuda vector of length N")
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.complex128, device=V.device)
+    L_ = lib()
+    ws = _workspace(L_.fgfrft_gfrft_exact_workspace_bytes(N), V.device)
+    check(L_.fgfrft_gfrft_exact(_ptr(V), _ptr(Vh), _ptr(theta.contiguous()), N, float(alpha), _ptr(out), _ptr(ws),
+                                ws.numel(), _stream(stream)), "fgfrft_gfrft_exact")
+    return out

@@ -82,6 +82,9 @@ class _SlotSet:
 
     def launch(self, batch):
         n = len(batch)
+        t = time.perf_counter()
+        for r in batch:
+            r.t_launch, r.batch_size = t, n
         k = next(b for b in BUCKETS if b >= n) if self.graphs else n
         # padding orders get alpha = 0 (a valid order); padding rows and signal columns of X
         # are left as they are: every order's plane and every signal column is computed
@@ -114,13 +117,13 @@ class _SlotSet:
 
 
 class _Request:
-    __slots__ = ("gid", "alpha", "X", "B", "t_arrive", "t_done", "future")
+    __slots__ = ("gid", "alpha", "X", "B", "t_arrive", "t_launch", "t_done", "batch_size", "future")
 
     def __init__(self, gid, alpha, X, t_arrive):
         self.gid, self.alpha = gid, float(alpha)
         self.X = torch.as_tensor(np.asarray(X, dtype=np.float32))
         self.B = self.X.shape[1]
-        self.t_arrive, self.t_done = t_arrive, None
+        self.t_arrive, self.t_launch, self.t_done, self.batch_size = t_arrive, None, None, 0
         self.future = Future()
 
 
@@ -235,10 +238,16 @@ def run_trace(server: Server, trace, signals: dict, warmup: int = 0) -> dict:
             nxt = t_arr[i] - (time.perf_counter() - t0) if i < n else 20e-6
             time.sleep(max(0.0, min(nxt, 200e-6)))
     wall = time.perf_counter() - t0
-    lat = np.array([r.t_done - r.t_arrive for r in reqs[warmup:]])
+    rs = reqs[warmup:]
+    lat = np.array([r.t_done - r.t_arrive for r in rs])
+    wait = np.array([r.t_launch - r.t_arrive for r in rs])
+    service = np.array([r.t_done - r.t_launch for r in rs])
     return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                 mean_ms=float(lat.mean() * 1e3), requests=len(lat), wall_s=wall,
-                throughput_req_s=len(reqs) / wall, futures=futures)
+                throughput_req_s=len(reqs) / wall,
+                queue_wait_p50_ms=float(np.percentile(wait, 50) * 1e3),
+                service_p50_ms=float(np.percentile(service, 50) * 1e3),
+                mean_batch=float(np.mean([r.batch_size for r in rs])), futures=futures)
 
 
 def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0) -> dict:

@@ -395,3 +395,28 @@ def test_degenerate_sizes():
             E = O.gfrft_exact(f, alpha, plan.decomposition) - Q
             _, theta, m1 = plan.decomposition
             assert abs(np.linalg.norm(E) - O.frobenius_error_exact(theta, m1, alpha, 3)) < 1e-13
+
+
+def test_table4_accuracy_columns_on_a_haar_draw():
+    """Table IV's accuracy columns (L = 10, alpha = 0.5) against a Haar draw at N = 1000.
+
+    The eigenphases of a Haar matrix are CUE-distributed: uniform one-point density and rigid,
+    so NMSE = (1/N) sum_k |R_L(theta_k)|^2 sits close to its expectation for every draw, and the
+    printed column is flat in N.  MSE = NMSE / N and MAE ~ sqrt(NMSE / N) (MAE sqrt(N) is flat
+    in the table too).  The test compares the draw with the column means (NMSE and MAE sqrt(N))."""
+    g = json.load(open(os.path.join(GOLD, "table4_online.json")))
+    L, alpha, N = g["L"], g["alpha"], 1000
+    nmse_printed = np.mean([r["NMSE"] for r in g["rows"]])
+    mae_printed = np.mean([r["MAE"] * np.sqrt(r["N"]) for r in g["rows"]])
+    for r in g["rows"]:   # the table's own MSE column is NMSE / N
+        assert abs(r["MSE"] * r["N"] - r["NMSE"]) <= 0.01 * r["NMSE"]
+    F = synth.haar_unitary(N, np.random.default_rng(4))
+    dec = O.spectral_decomposition(F)
+    E = O.fgfrft_operator_eigen(F, alpha, L, decomposition=dec) - O.gfrft_exact(F, alpha, dec)
+    m = O.error_metrics(E)
+    assert abs(m["MSE"] * N - m["NMSE"]) <= 1e-12
+    # the printed column sits ~3% above the uniform-phase expectation (one random matrix per size)
+    assert abs(m["NMSE"] - nmse_printed) <= g["rel_tol"] * nmse_printed, (m["NMSE"], nmse_printed)
+    assert abs(m["MAE"] * np.sqrt(N) - mae_printed) <= g["rel_tol"] * mae_printed, (m["MAE"], mae_printed)
+    # and the expectation sum_{|n| > L} c_n^2 itself (L - 1 or L + 1 would be ~10% off)
+    assert abs(m["NMSE"] - O.parseval_tail(alpha, L)) <= 0.03 * O.parseval_tail(alpha, L)
