@@ -274,3 +274,52 @@ def test_table4_accuracy_on_gpu():
         assert abs(m_gpu[key] - m_ref[key]) <= 1e-4 * m_ref[key], (key, m_gpu[key], m_ref[key])
     nmse_printed = np.mean([r["NMSE"] for r in g["rows"]])
     assert abs(m_gpu["NMSE"] - nmse_printed) <= g["rel_tol"] * nmse_printed
+
+
+# ----------------------------------------------------------------------------
+# learnable-order pipelines (order learning and fractional-domain denoising)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_order_cascade_learns_the_target_total_order(K):
+    """K FGFRFT layers from alpha = 0.1 each, target F^{1.5} (exact GFRFT), X = I, loss ||.||_F^2 / N^2,
+    Adam lr 0.01 for 200 steps (the cascade setup of Sec. IV) on the ER graph N = 64, L = 10."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan
+    from paper_2602_20870_amd.learn import OrderCascade, train
+    announce(f"order cascade K={K}")
+    cfg = synth.make_config("er64", seed=0, with_signals=False)
+    F, N = cfg["F"], cfg["N"]
+    plan = Plan(torch.from_numpy(F).cuda(), 10)
+    dec = O.spectral_decomposition(F)
+    target = torch.from_numpy(O.gfrft_exact(F, 1.5, dec).astype(np.complex64)).cuda()
+    X = torch.eye(N, dtype=torch.float32, device="cuda")
+    model = OrderCascade(plan, K, alpha_init=0.1)
+    hist = train(model, lambda m: (m(X) - target).abs().pow(2).sum() / N ** 2, steps=200, lr=0.01)
+    announce(f"K={K}: loss {hist[0]:.3e} -> {hist[-1]:.3e}, total order {model.total_order():.4f}")
+    assert hist[-1] < 0.05 * hist[0]
+    assert abs(model.total_order() - 1.5) < 0.05
+
+
+def test_fractional_mask_denoiser_reduces_the_error():
+    """Q^{-a} diag(h) Q^{a} y on a 16 x 16 grid graph (L = 10, a from 0.9): smooth signals
+    (20 lowest graph frequencies) plus white noise; the learned order and mask must cut the error."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan
+    from paper_2602_20870_amd.learn import FractionalMaskDenoiser, train
+    announce("fractional mask denoiser")
+    rng = np.random.default_rng(8)
+    A = synth.grid_adjacency(16, 16, lambda m: rng.uniform(0.5, 1.5, m))
+    F = synth.gft_from_shift(synth.laplacian(A))
+    N = F.shape[0]
+    x = (F.T[:, :20] @ rng.standard_normal((20, 8))).astype(np.float32)     # 8 smooth signals
+    y = (x + 0.3 * x.std() * rng.standard_normal(x.shape)).astype(np.float32)
+    plan = Plan(torch.from_numpy(F).cuda(), 10)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    model = FractionalMaskDenoiser(plan, alpha_init=0.9)
+    noisy = float(((yt - xt) ** 2).sum())
+    groups = [{"params": [model.alpha], "lr": 0.01}, {"params": [model.h], "lr": 0.05}]
+    hist = train(model, lambda m: (m(yt) - xt).abs().pow(2).sum(), steps=200, params=groups)
+    announce(f"denoiser: noisy {noisy:.3e}, loss {hist[0]:.3e} -> {hist[-1]:.3e}, "
+             f"alpha {float(model.alpha.detach()):.3f}")
+    assert hist[-1] < 0.5 * noisy
+    assert np.isfinite(float(model.alpha))
