@@ -289,7 +289,9 @@ struct StripLayout {
 
 // Two 32-position blocks whose lanes hold the even (block 0) and odd (block 1) position of one
 // column pair: the same MFMA sequence per block as order_group, then one 16-byte store per order
-// and lane (two neighbouring complex values), so each half-wave writes a 512-byte row run.
+// and lane (two neighbouring complex values), so each half-wave writes a 512-byte row run.  The
+// operator planes are streamed out with nontemporal stores (they are far larger than the caches).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <bool CPLX, int KP, bool BF, bool OFF32>
 __device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, int g0, int a0, int n_alpha, bool fast,
                                            int row, int col, int N, size_t NN, int l32, int lh,
@@ -340,14 +342,14 @@ __device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, in
       char* qa = (char*)(Q + (size_t)a0 * NN);
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        *(float4*)(qa + (size_t)(8 * (r >> 2) + (r & 3)) * NN * sizeof(cplx64) + voff) =
-            make_float4(re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale);
+        __builtin_nontemporal_store(f32x4{re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale},
+                                    (f32x4*)(qa + (size_t)(8 * (r >> 2) + (r & 3)) * NN * sizeof(cplx64) + voff));
     } else {
       cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        *(float4*)(ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN) =
-            make_float4(re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale);
+        __builtin_nontemporal_store(f32x4{re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale},
+                                    (f32x4*)(ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN));
     }
   } else if (row < N) {
     cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;

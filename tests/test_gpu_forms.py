@@ -322,4 +322,4 @@ def test_fractional_mask_denoiser_reduces_the_error():
     announce(f"denoiser: noisy {noisy:.3e}, loss {hist[0]:.3e} -> {hist[-1]:.3e}, "
              f"alpha {float(model.alpha.detach()):.3f}")
     assert hist[-1] < 0.5 * noisy
-    assert np.isfinite(float(model.alpha))
+    assert np.isfinite(float(model.alpha.detach()))
