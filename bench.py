@@ -186,7 +186,7 @@ def table4_bench(sizes=(1000, 2000, 3000, 4000, 5000, 6000, 7000, 8000), L=10, a
 SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
 
 
-def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=16, slot_sets=1, per_request=True,
+def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_sets=1, per_request=True,
                   warm_trace=4000):
     """p50/p99 latency of the continuous-batching server vs one launch per request.
 

@@ -20,6 +20,7 @@ in any mix (tested).
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from concurrent.futures import Future
 
@@ -222,7 +223,21 @@ def poisson_trace(n: int, rate: float, gids, B_max: int, seed: int = 0):
 
 
 def run_trace(server: Server, trace, signals: dict, warmup: int = 0) -> dict:
-    """Replay a trace in real time; latency = completion - arrival per request."""
+    """Replay a trace in real time; latency = completion - arrival per request.
+
+    The cyclic garbage collector is paused during the replay: its full collections over the
+    trace's many request objects stall the scheduling loop for tens of milliseconds (they set
+    the p99 otherwise)."""
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        return _run_trace(server, trace, signals, warmup)
+    finally:
+        if gc_was:
+            gc.enable()
+
+
+def _run_trace(server: Server, trace, signals: dict, warmup: int) -> dict:
     t_arr, gids, alphas, Bs = trace
     futures, reqs = [], []
     t0 = time.perf_counter()
@@ -246,12 +261,25 @@ def run_trace(server: Server, trace, signals: dict, warmup: int = 0) -> dict:
                 mean_ms=float(lat.mean() * 1e3), requests=len(lat), wall_s=wall,
                 throughput_req_s=len(reqs) / wall,
                 queue_wait_p50_ms=float(np.percentile(wait, 50) * 1e3),
+                queue_wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
                 service_p50_ms=float(np.percentile(service, 50) * 1e3),
+                service_p99_ms=float(np.percentile(service, 99) * 1e3),
                 mean_batch=float(np.mean([r.batch_size for r in rs])), futures=futures)
 
 
 def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0) -> dict:
-    """Baseline: one update launch and one apply launch per request, in arrival order."""
+    """Baseline: one update launch and one apply launch per request, in arrival order (garbage
+    collector paused as in run_trace)."""
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        return _run_trace_per_request(plans, trace, signals, warmup)
+    finally:
+        if gc_was:
+            gc.enable()
+
+
+def _run_trace_per_request(plans: dict, trace, signals: dict, warmup: int) -> dict:
     t_arr, gids, alphas, Bs = trace
     t0 = time.perf_counter()
     lat = []

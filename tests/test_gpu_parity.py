@@ -115,7 +115,8 @@ def test_update_grid1024_launch_config():
     _check_update(torch, c["F"], c["L"], c["alphas"], sample=[0, 1, 77, 128, 255])
 
 
-@pytest.mark.parametrize("N,L,n_alpha", [(1, 3, 5), (2, 4, 1), (17, 5, 33), (50, 40, 3), (100, 64, 40)])
+@pytest.mark.parametrize("N,L,n_alpha", [(1, 3, 5), (2, 4, 1), (17, 5, 33), (50, 40, 3), (100, 64, 40),
+                                         (17, 5, 70), (100, 64, 70), (33, 20, 65)])
 def test_update_ragged_and_edge_sizes(N, L, n_alpha):
     torch = torch_cuda()
     announce(f"update ragged N={N} L={L} n_alpha={n_alpha}")
