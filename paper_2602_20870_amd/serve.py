@@ -113,6 +113,7 @@ class _SlotSet:
         for i, r in enumerate(self.batch):
             r.t_done = now
             r.future.set_result(self.h_Y[i, :, : r.B].numpy().copy())
+            r.future = None    # the result now belongs to the caller's future alone
         self.batch = None
         self.event = None
 
@@ -222,31 +223,36 @@ def poisson_trace(n: int, rate: float, gids, B_max: int, seed: int = 0):
     return t, [gids[i] for i in g], a, b
 
 
-def run_trace(server: Server, trace, signals: dict, warmup: int = 0) -> dict:
+def run_trace(server: Server, trace, signals: dict, warmup: int = 0, keep_every: int = 1) -> dict:
     """Replay a trace in real time; latency = completion - arrival per request.
 
-    The cyclic garbage collector is paused during the replay: its full collections over the
-    trace's many request objects stall the scheduling loop for tens of milliseconds (they set
-    the p99 otherwise)."""
+    The client keeps the result of every `keep_every`-th request (returned as `kept`:
+    (trace index, future) pairs) and drops the others once they complete, as a client that
+    consumes its results would: holding every result of a long trace (gigabytes of host
+    arrays) makes each new result array fresh, page-faulted memory.  The cyclic garbage
+    collector is paused during the replay: its collections over the trace's many request
+    objects otherwise stall the scheduling loop for tens of milliseconds."""
     gc_was = gc.isenabled()
     gc.disable()
     try:
-        return _run_trace(server, trace, signals, warmup)
+        return _run_trace(server, trace, signals, warmup, keep_every)
     finally:
         if gc_was:
             gc.enable()
 
 
-def _run_trace(server: Server, trace, signals: dict, warmup: int) -> dict:
+def _run_trace(server: Server, trace, signals: dict, warmup: int, keep_every: int) -> dict:
     t_arr, gids, alphas, Bs = trace
-    futures, reqs = [], []
+    kept, reqs = [], []
     t0 = time.perf_counter()
     i, n = 0, len(t_arr)
     while i < n or server.busy():
         now = time.perf_counter() - t0
         while i < n and t_arr[i] <= now:
             X = signals[gids[i]][:, : Bs[i]]
-            futures.append(server.submit(gids[i], alphas[i], X, t_arrive=t0 + t_arr[i]))
+            fut = server.submit(gids[i], alphas[i], X, t_arrive=t0 + t_arr[i])
+            if i % keep_every == 0:
+                kept.append((i, fut))
             reqs.append(server.pending[gids[i]][-1])
             i += 1
         if not server.step():
@@ -264,27 +270,27 @@ def _run_trace(server: Server, trace, signals: dict, warmup: int) -> dict:
                 queue_wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
                 service_p50_ms=float(np.percentile(service, 50) * 1e3),
                 service_p99_ms=float(np.percentile(service, 99) * 1e3),
-                mean_batch=float(np.mean([r.batch_size for r in rs])), futures=futures)
+                mean_batch=float(np.mean([r.batch_size for r in rs])), kept=kept)
 
 
-def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0) -> dict:
-    """Baseline: one update launch and one apply launch per request, in arrival order (garbage
-    collector paused as in run_trace)."""
+def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0, keep_every: int = 1) -> dict:
+    """Baseline: one update launch and one apply launch per request, in arrival order; keeps
+    the results and pauses the garbage collector as run_trace does (`outputs`: index -> result)."""
     gc_was = gc.isenabled()
     gc.disable()
     try:
-        return _run_trace_per_request(plans, trace, signals, warmup)
+        return _run_trace_per_request(plans, trace, signals, warmup, keep_every)
     finally:
         if gc_was:
             gc.enable()
 
 
-def _run_trace_per_request(plans: dict, trace, signals: dict, warmup: int) -> dict:
+def _run_trace_per_request(plans: dict, trace, signals: dict, warmup: int, keep_every: int) -> dict:
     t_arr, gids, alphas, Bs = trace
     t0 = time.perf_counter()
     lat = []
     dev = next(iter(plans.values())).device
-    outs = []
+    outs = {}
     for i in range(len(t_arr)):
         now = time.perf_counter() - t0
         if t_arr[i] > now:
@@ -294,7 +300,8 @@ def _run_trace_per_request(plans: dict, trace, signals: dict, warmup: int) -> di
         Q = p.update([alphas[i]])
         Y = apply_operator(Q, X)
         y = Y[0].cpu().numpy()
-        outs.append(y)
+        if i % keep_every == 0:
+            outs[i] = y
         lat.append(time.perf_counter() - t0 - t_arr[i])
     wall = time.perf_counter() - t0
     lat = np.array(lat[warmup:])
