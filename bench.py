@@ -186,6 +186,67 @@ def table4_bench(sizes=(1000, 2000, 3000, 4000, 5000, 6000, 7000, 8000), L=10, a
 SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
 
 
+def direct_algorithmic_bytes(N, L, ncols):
+    # the stack and P streamed once per 64-column block: (2L + 1) 4 N^2, plus x read (4 N) and y written (8 N)
+    return -(-ncols // 64) * (2 * L + 1) * 4.0 * N * N + 12.0 * N * ncols
+
+
+def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16))):
+    """Direct route (no operator formed) vs update + apply for small signal batches of one plan.
+
+    Each case is (orders, signals per order); both routes produce the same Y (complex64 [N, B] per
+    order).  Times are per call, HIP events on the current stream, inputs resident."""
+    import torch
+    import synth
+    from paper_2602_20870_amd import apply_operator
+
+    N, L = plan.N, plan.L
+    stream = torch.cuda.current_stream()
+    rng = synth.streams(5, 1)[0]
+    out = []
+    for n, B in sizes:
+        al = np.ascontiguousarray(alphas[:n])
+        X = torch.from_numpy(synth.real_signals((n, N, B), rng).astype(np.float32)).to(dev)
+        Xd = X.permute(1, 0, 2).reshape(N, n * B).contiguous()
+        cols = torch.arange(n, dtype=torch.int32, device=dev).repeat_interleave(B)
+        al_dev = torch.from_numpy(al).to(dev)
+        Yd = torch.empty((N, n * B), dtype=torch.complex64, device=dev)
+        ws = torch.empty(max(256, plan.direct_workspace_bytes(n * B, n * B)), dtype=torch.uint8, device=dev)
+        Q = torch.empty((n, N, N), dtype=torch.complex64, device=dev)
+
+        def direct():
+            plan.apply_direct(al_dev, cols, Xd, out=Yd, ws=ws)
+
+        def two_step():
+            plan.update(al, out=Q)
+            return apply_operator(Q, X)
+
+        res = {}
+        for name, fn in (("direct", direct), ("update_apply", two_step)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / reps
+        Y2 = two_step().permute(1, 0, 2).reshape(N, n * B)
+        diff = float(torch.linalg.norm(Yd - Y2) / torch.linalg.norm(Y2))
+        alg = direct_algorithmic_bytes(N, L, n * B)
+        out.append({"orders": n, "signals_per_order": B, "ncols": n * B, "direct_ms": res["direct"],
+                    "update_apply_ms": res["update_apply"], "speedup": res["update_apply"] / res["direct"],
+                    "direct_algorithmic_GB": alg / 1e9,
+                    "direct_GBps": alg / (res["direct"] * 1e-3) / 1e9, "rel_diff_between_routes": diff})
+        log(f"direct n={n} B={B}: {res['direct']:.3f} ms vs update+apply {res['update_apply']:.3f} ms "
+            f"({alg / (res['direct'] * 1e-3) / 1e9:.0f} GB/s algorithmic, rel diff {diff:.1e})")
+        del X, Xd, Yd, ws, Q, Y2
+        torch.cuda.empty_cache()
+    return {"workload": f"knn4096 plan (N={N}, L={L}), real signals, orders from the main workload", "cases": out}
+
+
 def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_sets=1, per_request=True,
                   warm_trace=4000, keep_every=16):
     """p50/p99 latency of the continuous-batching server vs one launch per request.
@@ -244,6 +305,7 @@ def main():
     ap.add_argument("--stacktype", default="fp32", choices=["fp32", "bf16x2"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-route comparison")
     ap.add_argument("--table4", action="store_true",
                     help="only the Table IV workload (FGFRFT vs exact GFRFT online time, N = 1000..8000)")
     args = ap.parse_args()
@@ -335,6 +397,8 @@ def main():
     }
     del Q, X
     torch.cuda.empty_cache()
+    if not args.no_direct:
+        out["direct"] = direct_bench(plan, alphas, dev)
     out["copy_reference"] = copy_bandwidth(dev)
     log(f"plain copy {out['copy_reference']['GBps']:.0f} GB/s")
     if not args.no_grad:

@@ -183,6 +183,36 @@ FGFRFT_API fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, 
                                       void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Direct route: apply without forming any operator (Definition 2 with the
+ * expansion of Definition 1 and Proposition 2)
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for fgfrft_apply_direct (column scales, coefficient table,
+ * per-term-group partial sums). */
+FGFRFT_API size_t fgfrft_apply_direct_workspace_bytes(fgfrft_plan_t plan, int ncols, int ldx);
+
+/* Y[:, c] = Q_L^{alpha(c)} X[:, c] for c = 0..ncols-1, where column c has the order
+ * alpha(c) = alphas_dev[col_order_dev[c]], computed from the resident stack as
+ *   Y = c_0 X + (e^{j pi alpha} - c_0) P X + sum_{n=1}^{L} ( c_n M_n X + c_{-n} M_n^H X )
+ * (P_c = I - P folded into the first two terms; the standard form has P = 0).  No N x N
+ * operator is written or read: the stack is streamed once per 64 columns, so this route
+ * wins when the signals of a batch are few compared with its orders (it moves
+ * (2L+1) N^2 stack elements instead of 16 N^2 operator bytes per order).
+ *   alphas_dev: float64 [n_alpha] device; col_order_dev: int32 [ncols] device, each in
+ *   [0, n_alpha); X_dev: [N][ldx] row-major, float32 (x_complex = 0) or complex64
+ *   (x_complex = 1); Y_dev: complex64 [N][ldy].  ncols <= ldx, ncols <= ldy.
+ * Orders are device data and are not range-checked on the host: a column whose order
+ * index is out of range, or whose order has |alpha| >= L or is not finite, is filled
+ * with NaN.  Real F with an FP32 stack, real X and N % 32 == 0 take the matrix-core
+ * kernel (split fp16 operands, FP32 products folded into FP64 sums per 32-wide k
+ * chunk); every other case takes a plain FP64-accumulating kernel.  The call only
+ * enqueues work on `stream` (no host synchronisation; capturable). */
+FGFRFT_API fgfrft_status fgfrft_apply_direct(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha,
+                                             const int* col_order_dev, const void* X_dev, int x_complex,
+                                             int ncols, int ldx, void* Y_dev, int ldy, void* ws_dev,
+                                             size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Gradients (Proposition 4)
  * ------------------------------------------------------------------------- */
 

@@ -29,6 +29,9 @@ SIGNATURES = {
     "fgfrft_apply_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int]),
     "fgfrft_apply": (c_int, [c_void_p, P_double, c_int, c_void_p, c_int, c_int, c_int, c_void_p, c_int,
                              c_void_p, c_size_t, c_void_p]),
+    "fgfrft_apply_direct_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int]),
+    "fgfrft_apply_direct": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
+                                    c_int, c_void_p, c_size_t, c_void_p]),
     "fgfrft_grad_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "fgfrft_grad": (c_int, [c_void_p, P_double, c_int, c_void_p, c_int, c_int, c_int, c_void_p, P_double,
                             c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -214,6 +214,34 @@ fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha
   return FGFRFT_OK;
 }
 
+size_t fgfrft_apply_direct_workspace_bytes(fgfrft_plan_t plan, int ncols, int ldx) {
+  if (!plan || ncols < 0 || ldx < 1 || ldx > (1 << 20)) return 0;
+  return direct_ws_bytes((const Plan*)plan, ncols, ldx);
+}
+
+fgfrft_status fgfrft_apply_direct(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha, const int* col_order_dev,
+                                  const void* X_dev, int x_complex, int ncols, int ldx, void* Y_dev, int ldy,
+                                  void* ws_dev, size_t ws_bytes, void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  if (n_alpha < 1 || ncols < 0 || ldx < 1 || ldy < 1 || ncols > ldx || ncols > ldy || ldx > (1 << 20) ||
+      ldy > (1 << 20)) {
+    set_error("bad sizes n_alpha=%d ncols=%d ldx=%d ldy=%d", n_alpha, ncols, ldx, ldy);
+    return FGFRFT_EINVAL;
+  }
+  if (ncols == 0) return FGFRFT_OK;
+  if (!alphas_dev || !col_order_dev || !X_dev || !Y_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if ((uintptr_t)X_dev % (x_complex ? 8 : 4) || (uintptr_t)Y_dev % 8 || (uintptr_t)ws_dev % 256 ||
+      (uintptr_t)alphas_dev % 8 || (uintptr_t)col_order_dev % 4) {
+    set_error("misaligned device pointer (X: element, Y: 8 bytes, ws: 256 bytes)");
+    return FGFRFT_EINVAL;
+  }
+  const size_t need = direct_ws_bytes(p, ncols, ldx);
+  if (ws_bytes < need) { set_error("direct workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  return direct_launch(p, alphas_dev, n_alpha, col_order_dev, X_dev, x_complex ? 1 : 0, ncols, ldx, Y_dev, ldy, ws_dev,
+                       (hipStream_t)stream);
+}
+
 size_t fgfrft_grad_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared) {
   if (!plan || n_alpha < 1 || B < 1) return 0;
   return grad_ws_bytes((const Plan*)plan, n_alpha, B, x_shared);

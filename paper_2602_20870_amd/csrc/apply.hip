@@ -395,9 +395,20 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
   }
 }
 
+size_t colscale_partial_bytes(int N, int nx, int B) { return align_up((size_t)nx * ceil_div(N, CR) * B * sizeof(float), 256); }
+
+fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx, float2* scale, float* partial,
+                              hipStream_t s) {
+  const int nch = ceil_div(N, CR);
+  k_colmax<<<dim3(ceil_div(B, 64) * nx, nch), 256, 0, s>>>(X, x_complex, N, B, partial);
+  k_colscale<<<ceil_div(nx * B, 256), 256, 0, s>>>(partial, nch, B, nx, scale);
+  FG_LAUNCHED("colscale");
+  return FGFRFT_OK;
+}
+
 size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared) {
   const size_t nx = x_shared ? 1 : n_alpha;
-  return align_up(nx * B * sizeof(float2), 256) + align_up(nx * ceil_div(N, CR) * B * sizeof(float), 256);
+  return align_up(nx * B * sizeof(float2), 256) + colscale_partial_bytes(N, (int)nx, B);
 }
 
 template <bool ADJ, bool XC, bool YR>
@@ -423,11 +434,9 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
                            int B, void* Y, int y_real, void* ws, hipStream_t s) {
   float2* sc = (float2*)ws;
   const int nx = x_shared ? 1 : n_alpha;
-  const int nch = ceil_div(N, CR);
   float* partial = (float*)((char*)ws + align_up((size_t)nx * B * sizeof(float2), 256));
-  k_colmax<<<dim3(ceil_div(B, 64) * nx, nch), 256, 0, s>>>(X, x_complex, N, B, partial);
-  k_colscale<<<ceil_div(nx * B, 256), 256, 0, s>>>(partial, nch, B, nx, sc);
-  FG_LAUNCHED("colscale");
+  fgfrft_status rc = colscale_launch(X, x_complex, N, B, nx, sc, partial, s);
+  if (rc) return rc;
   // streaming kernel: k stages of 32 (real signals, 2-stage ring) or 16 (complex, 3-stage ring)
   if (!adjoint && N % (x_complex ? 16 : 32) == 0 && B % 64 == 0) {
     const int nrb = ceil_div(N, M2), ncb = B / 64;

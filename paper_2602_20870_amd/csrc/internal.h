@@ -26,6 +26,10 @@ constexpr float kCoefScale = 4096.0f;
 constexpr float kUnscale = 1.0f / (4096.0f * 4096.0f);
 
 // ---------------------------------------------------------------- device helpers
+// Fourier coefficient of Sec. III-A: c_n(alpha) = sinc(alpha - n) = sin(pi x) / (pi x), limit 1 at x = 0
+// (FP64, sinpi is exact at integers so integer orders give Kronecker deltas).
+__device__ __forceinline__ double sinc_pi(double x) { return x == 0.0 ? 1.0 : sinpi(x) / (M_PI * x); }
+
 typedef __attribute__((address_space(3))) char lds_char;
 __device__ __forceinline__ uint32_t lds_addr(const char* p) { return (uint32_t)(size_t)(const lds_char*)p; }
 
@@ -100,6 +104,17 @@ fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, 
 
 // Apply (apply.hip)
 size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared);
+// per-column power-of-two scales of X [nx][N][B] (max |x| s in [2^13, 2^14)), scale[(a, b)] = (s, 1/s);
+// partial: nx * ceil(N / 256) * B floats of scratch
+size_t colscale_partial_bytes(int N, int nx, int B);
+fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx, float2* scale, float* partial,
+                              hipStream_t s);
+
+// Direct route (direct.hip)
+size_t direct_ws_bytes(const Plan* p, int ncols, int ldx);
+fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha, const int* col_order_dev,
+                            const void* X, int x_complex, int ncols, int ldx, void* Y, int ldy, void* ws,
+                            hipStream_t s);
 fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex,
                            int x_shared, int B, void* Y, int y_real, void* ws, hipStream_t s);
 

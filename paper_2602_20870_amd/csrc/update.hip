@@ -25,8 +25,6 @@ namespace fgfrft {
 constexpr int TCOLS = 64;  // columns per strip
 
 // ------------------------------------------------------------ coefficients (a-1)
-__device__ __forceinline__ double sinc_pi(double x) { return x == 0.0 ? 1.0 : sinpi(x) / (M_PI * x); }
-
 template <bool BF>
 __device__ __forceinline__ void split16(double v, uint16_t& hi, uint16_t& lo) {
   if (BF) {

@@ -4,6 +4,7 @@ PyTorch, every computation in the HIP library (argument marshalling only).
     plan = Plan(F_cuda, L)                 # offline stage, Algorithm 1
     Q = plan.update(alphas)                # Q_L^alpha for many orders (Definition 1)
     Y = plan.apply(alphas, X)              # Q_L^alpha X (Definition 2)
+    Y = plan.apply_direct(alphas, cols, X) # the same without forming Q (one order per column)
     da, dX = plan.grad(alphas, X, GY)      # Proposition 4
 """
 from __future__ import annotations
@@ -165,6 +166,51 @@ class Plan:
         check(L_.fgfrft_apply(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(Y), chunk,
                               _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply")
         return Y
+
+    def apply_direct(self, alphas, col_order, X: torch.Tensor, ncols: int | None = None, out: torch.Tensor | None = None,
+                     ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Y[:, c] = Q(alphas[col_order[c]]) X[:, c] straight from the resident stack (no operator formed).
+
+        alphas: float64 cuda tensor (capturable) or host sequence; col_order: int32 cuda tensor or
+        host sequence; X: cuda [N, ldx] float32 or complex64 (the first `ncols` columns are
+        transformed); out: complex64 [N, ldy] with ldy >= ncols.  Columns with a bad order are NaN.
+        """
+        dev = self.device
+        if not isinstance(alphas, torch.Tensor) or not alphas.is_cuda:
+            alphas = torch.from_numpy(_alphas(alphas)).to(dev)
+        if not isinstance(col_order, torch.Tensor) or not col_order.is_cuda:
+            col_order = torch.as_tensor(np.asarray(col_order, dtype=np.int32)).to(dev)
+        if alphas.dtype != torch.float64 or not alphas.is_contiguous():
+            raise ValueError("alphas must be a contiguous float64 tensor")
+        if col_order.dtype != torch.int32 or not col_order.is_contiguous():
+            raise ValueError("col_order must be a contiguous int32 tensor")
+        if X.dim() != 2 or X.shape[0] != self.N or not X.is_cuda or not X.is_contiguous():
+            raise ValueError(f"X must be a contiguous cuda tensor of shape [{self.N}, ldx]")
+        if X.dtype == torch.float32:
+            xc = 0
+        elif X.dtype == torch.complex64:
+            xc = 1
+        else:
+            raise TypeError("X must be float32 or complex64")
+        ldx = X.shape[1]
+        ncols = ldx if ncols is None else int(ncols)
+        if col_order.numel() < ncols:
+            raise ValueError("col_order must have at least ncols entries")
+        if out is None:
+            out = torch.empty((self.N, max(ncols, 1)), dtype=torch.complex64, device=dev)
+        if out.dim() != 2 or out.shape[0] != self.N or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex64 tensor of shape [{self.N}, ldy]")
+        L_ = lib()
+        need = L_.fgfrft_apply_direct_workspace_bytes(self._h, ncols, ldx)
+        if ws is None or ws.numel() < need:
+            ws = _workspace(need, dev)
+        check(L_.fgfrft_apply_direct(self._h, _ptr(alphas), alphas.numel(), _ptr(col_order), _ptr(X), xc, ncols, ldx,
+                                     _ptr(out), out.shape[1], _ptr(ws), ws.numel(), _stream(stream)),
+              "fgfrft_apply_direct")
+        return out
+
+    def direct_workspace_bytes(self, ncols: int, ldx: int) -> int:
+        return int(lib().fgfrft_apply_direct_workspace_bytes(self._h, ncols, ldx))
 
     def grad(self, alphas, X: torch.Tensor, GY: torch.Tensor, want_dX: bool = True, stream=None):
         """(dl/dalpha as float64 numpy array, dl/dX or None) for GY = dl/dRe Y + j dl/dIm Y."""

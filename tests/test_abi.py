@@ -76,6 +76,10 @@ def test_null_and_small_arguments_are_rejected_on_host(L):
     assert L.fgfrft_apply_operator(None, 16, 1, 0, None, 0, 0, 4, None, 0, None, 0, None) == -1
     assert L.fgfrft_apply_operator(None, 0, 1, 0, None, 0, 0, 4, None, 0, None, 0, None) == -1
     assert L.fgfrft_update_workspace_bytes(None, 4) == 0
+    # direct route: NULL plan, then no workspace size for a NULL plan
+    assert L.fgfrft_apply_direct(None, None, 1, None, None, 0, 4, 4, None, 4, None, 0, None) == -1
+    assert b"NULL plan" in L.fgfrft_last_error()
+    assert L.fgfrft_apply_direct_workspace_bytes(None, 4, 4) == 0
 
 
 def test_strerror_names(L):
