@@ -248,7 +248,7 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
 
 
 def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_sets=1, per_request=True,
-                  warm_trace=4000, keep_every=16):
+                  warm_trace=4000, keep_every=16, route="auto"):
     """p50/p99 latency of the continuous-batching server vs one launch per request.
 
     8 resident plans from kNN graphs (k=10, Gaussian weights) on 3-D GMM points with
@@ -267,7 +267,7 @@ def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_s
           for g, N in enumerate(SERVE_NS)}
     rng = np.random.default_rng(7)
     sig = {g: rng.standard_normal((F.shape[0], 64)).astype(np.float32) for g, F in Fs.items()}
-    srv = serve.Server(hbm_budget=120 << 30, K=K, bmax=64, slot_sets=slot_sets, use_graphs=True)
+    srv = serve.Server(hbm_budget=120 << 30, K=K, bmax=64, slot_sets=slot_sets, use_graphs=True, route=route)
     for g, F in Fs.items():
         srv.add_plan(g, F, L)
     torch.cuda.synchronize()
@@ -277,7 +277,7 @@ def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_s
     trace = serve.poisson_trace(n_requests, rate, list(Fs), 64, seed=11)
     batched = serve.run_trace(srv, trace, sig, warmup=warmup, keep_every=keep_every)
     out = {"batched": batched, "rate_req_s": rate, "requests": n_requests, "warmup": warmup,
-           "plans_N": list(SERVE_NS), "L": L, "K": K, "slot_sets": slot_sets}
+           "plans_N": list(SERVE_NS), "L": L, "K": K, "slot_sets": slot_sets, "route": route}
     kept = batched.pop("kept")
     if per_request:
         per_req = serve.run_trace_per_request(srv.plans, trace, sig, warmup=warmup, keep_every=keep_every)

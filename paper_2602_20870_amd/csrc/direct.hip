@@ -9,11 +9,11 @@
 // fp16 hi/lo (after a power-of-two scale per column) in the order the matrix cores read them.  A
 // workgroup owns 128 output rows x 64 columns and a contiguous run of the (2L + 1) x N/32 stages
 // (term, 32-wide k chunk) of that tile; the runs are balanced so the whole grid is one round of
-// two workgroups per CU when the tile count allows.  Stack and signal tiles stream from HBM into
-// an LDS ring with direct loads; each stage's products (stack split into fp16 hi/lo when a wave
-// reads its fragments, hi*hi + hi*lo + lo*hi) land in a fresh FP32 accumulator that is folded into
-// an FP64 sum with the column's coefficient, so no long FP32 chain forms over the (2L + 1) N
-// products of an output.  The P term's products fold twice: into the real part with
+// resident workgroups (three per CU) when the tile count allows.  Stack and signal tiles stream from HBM into
+// an LDS ring with direct loads; the products of one term (stack split into fp16 hi/lo when a
+// wave reads its fragments, hi*hi + hi*lo + lo*hi) accumulate in FP32 and are folded into an FP64
+// sum with the column's coefficient when the term ends, so no FP32 chain runs over more than the
+// N products of one term.  The P term's products fold twice: into the real part with
 // cos(pi alpha) - c_0 and into the imaginary part with sin(pi alpha).  Runs write partial sums
 // that a second kernel adds in a fixed order (deterministic), with the identity term c_0 X.
 //
@@ -26,14 +26,18 @@ namespace fgfrft {
 
 constexpr int DM = 128;                          // output rows per workgroup (4 waves x 32)
 constexpr int DK = 32;                           // k per ring stage
-constexpr int DNS = 3;                           // ring stages
 constexpr int DAB = DM * DK * 4;                 // stack tile bytes per stage (16 KB)
 constexpr int DXB = DK * 64 * 4;                 // signal tile bytes per stage (8 KB: fp16 hi + lo)
 constexpr int DSB = DAB + DXB;
 constexpr int DLW = DAB / 4096 + DXB / 4096;     // direct loads per wave per stage
-constexpr int DTG = 24;                          // terms one workgroup's run may touch
-constexpr int DLDS = DNS * DSB + (DTG + 1) * 64 * 4;
-static_assert(DLDS <= 80 * 1024, "two workgroups per CU");
+// Ring of NS stages.  NS = 3: 80 KB of LDS, two workgroups per CU, runs touch up to 24 terms;
+// NS = 2: 53 KB, three workgroups per CU, up to 16 terms.
+template <int NS> struct DirectCfg {
+  static constexpr int TG = NS == 3 ? 24 : 16;              // terms one run may touch
+  static constexpr int LDS = NS * DSB + (TG + 1) * 64 * 4;
+  static constexpr int WPC = NS == 3 ? 2 : 3;               // workgroups per CU
+  static_assert(LDS * WPC <= 160 * 1024, "LDS budget");
+};
 
 // ---------------------------------------------------------------- coefficient table
 // Rows of ncp floats; for column c with order alpha and signal scale s (1 on the plain path):
@@ -113,7 +117,8 @@ __global__ __launch_bounds__(256) void k_xsplit(const float* __restrict__ X, int
 // st % nch).  Ids are dealt round-robin over the 8 XCDs; the column blocks of one (row block,
 // run) get consecutive ids on one XCD, so a stack tile read for one column block is an L2 hit for
 // the others.  part_re, part_im: [G][N][ncp]; part_im is written only by runs that reach P.
-__global__ __launch_bounds__(256, 2) void k_direct(const float* __restrict__ stack, const float* __restrict__ P, int N,
+template <int DNS>
+__global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float* __restrict__ stack, const float* __restrict__ P, int N,
                                                    int L, const short* __restrict__ Xs, int ncp,
                                                    const float* __restrict__ gam, int SPW, int G, int nIB, int ncb,
                                                    float* __restrict__ part_re, float* __restrict__ part_im) {
@@ -169,9 +174,12 @@ __global__ __launch_bounds__(256, 2) void k_direct(const float* __restrict__ sta
     }
   };
 
-  // FP64 sums of the real part; the imaginary part is the P term alone (one FP32 sum)
+  // acc: FP32 products of the current term; at the end of each term (or of the run) they are
+  // folded with the column's coefficient into FP64 sums of the real part, so an output sees one
+  // FP32 chain of at most N products per term.  The imaginary part is the P term alone.
   double sum_re[2][16] = {};
   float sum_im[2][16] = {};
+  floatx16 acc[2] = {};
   const int r = 32 * wave + l32;
   for (int it = 0; it < DNS - 1 && it < nst; ++it) issue(it);
   for (int it = 0; it < nst; ++it) {
@@ -182,9 +190,6 @@ __global__ __launch_bounds__(256, 2) void k_direct(const float* __restrict__ sta
     barrier_nofence();
     if (it + DNS - 1 < nst) issue(it + DNS - 1);   // refills the slot of stage it - 1
     const char* st = sm + (it % DNS) * DSB;
-    const int tl = (s0 + it) / nch - tfirst;
-    const bool isP = tfirst + tl == 2 * L;
-    floatx16 acc[2] = {};
 #pragma unroll
     for (int ks = 0; ks < DK / 16; ++ks) {
       // A: S_t[i0 + r][k0 + 16 ks + 8 lh .. + 7], two 16-byte chunks, split after the 2^12 scale
@@ -208,15 +213,21 @@ __global__ __launch_bounds__(256, 2) void k_direct(const float* __restrict__ sta
         acc[c] = dmma(al, bh, acc[c]);
       }
     }
+    const int gs = s0 + it;
+    if ((gs + 1) % nch == 0 || it == nst - 1) {     // the term ends here (or the run does)
+      const int tl = gs / nch - tfirst;
+      const bool isP = tfirst + tl == 2 * L;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const double gr = (double)gl[tl * 64 + 32 * c + l32];
+      for (int c = 0; c < 2; ++c) {
+        const double gr = (double)gl[tl * 64 + 32 * c + l32];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) sum_re[c][e] = fma(gr, (double)acc[c][e], sum_re[c][e]);
-      if (isP) {
-        const float gi = gl[nterm * 64 + 32 * c + l32];
+        for (int e = 0; e < 16; ++e) sum_re[c][e] = fma(gr, (double)acc[c][e], sum_re[c][e]);
+        if (isP) {
+          const float gi = gl[nterm * 64 + 32 * c + l32];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) sum_im[c][e] = fmaf(gi, acc[c][e], sum_im[c][e]);
+          for (int e = 0; e < 16; ++e) sum_im[c][e] = fmaf(gi, acc[c][e], sum_im[c][e]);
+        }
+        acc[c] = floatx16{};
       }
     }
   }
@@ -322,22 +333,30 @@ __global__ __launch_bounds__(256) void k_direct_plain(const void* __restrict__ s
 }
 
 // ---------------------------------------------------------------- host side
-// Runs per tile: enough for one round of two workgroups per CU when the tiles allow, and at most
-// DTG - 1 terms of stages per run (the coefficient rows a run keeps in LDS).
+// Runs per tile: enough for one round of the resident workgroups per CU when the tiles allow,
+// and at most TG - 1 terms of stages per run (the coefficient rows a run keeps in LDS).
 struct DirectGrid {
   int nIB, ncb, ncp, nch, G, SPW, gP;
 };
 
+// Two ring stages with three workgroups per CU measured a few percent faster than three stages
+// with two workgroups per CU at N = 4096, L = 32 (64 and 256 columns).
+constexpr int kDirectNS = 2;
+using DCfg = DirectCfg<kDirectNS>;
+
 static DirectGrid direct_grid(int N, int L, int ncols) {
+  const int TG = DCfg::TG, WPC = DCfg::WPC;
   DirectGrid d;
   d.nIB = ceil_div(N, DM);
   d.ncb = ceil_div(ncols, 64);
   d.ncp = d.ncb * 64;
   d.nch = N / DK > 0 ? N / DK : 1;
   const int T = 2 * L + 1, total = T * d.nch;
-  const long units = (long)d.nIB * d.ncb;
-  int G = (int)(512 / units);
-  const int gmin = ceil_div(T, DTG - 1);
+  // the runs depend on N and L only, so a column's result (its FP64 fold and reduction order)
+  // does not depend on how many other columns share the call
+  const long units = d.nIB;
+  int G = (int)(256 * WPC / units);
+  const int gmin = ceil_div(T, TG - 1);
   if (G < gmin) G = gmin;
   if (G > total) G = total;
   d.SPW = ceil_div(total, G);
@@ -426,11 +445,12 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
   }
   static bool attr_set = false;
   if (!attr_set) {
-    FG_HIP(hipFuncSetAttribute((const void*)k_direct, hipFuncAttributeMaxDynamicSharedMemorySize, DLDS));
+    FG_HIP(hipFuncSetAttribute((const void*)k_direct<kDirectNS>, hipFuncAttributeMaxDynamicSharedMemorySize, DCfg::LDS));
     attr_set = true;
   }
-  k_direct<<<(unsigned)nblocks, 256, DLDS, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs, d.ncp, w.gam,
-                                                d.SPW, d.G, d.nIB, d.ncb, w.part_re, w.part_im);
+  k_direct<kDirectNS><<<(unsigned)nblocks, 256, DCfg::LDS, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs,
+                                                                d.ncp, w.gam, d.SPW, d.G, d.nIB, d.ncb, w.part_re,
+                                                                w.part_im);
   FG_LAUNCHED("direct");
   const size_t n = (size_t)N * ncols;
   k_direct_reduce<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.part_re, w.part_im, d.G, d.gP, N, d.ncp, ncols, L,

@@ -8,14 +8,19 @@ operators, outputs, workspaces) plus pinned host staging.  Each scheduling step
   * retires finished batches (event query), hands results to their futures and
     frees their slot set,
   * for every plan with pending requests and a free slot set, coalesces up to K of
-    its requests into one batch: one fused operator-update launch for all their
-    orders followed by one apply launch, replayed from a captured hipGraph for the
-    batch-size bucket, on the slot set's own stream (batches of different plans
-    overlap on the device).
+    its requests into one batch and runs it on the slot set's own stream (batches of
+    different plans overlap on the device), replayed from a captured hipGraph for the
+    batch's size bucket, by one of two routes:
+      - operator route: one fused operator-update launch for all the batch's orders
+        followed by one apply launch (moves 16 N^2 bytes of operator per order);
+      - direct route: the signals of the batch side by side, one column per signal
+        with its own order, transformed straight from the resident stack (moves the
+        (2L+1) N^2 stack elements once per 64 columns, no operator formed).
+    The route is chosen per batch from the number of orders and of signal columns.
 Requests that arrive while batches run wait only until a slot set of their plan is
-free, not until the whole device drains.  Each order's plane is computed
-independently of the other orders of its batch, so a result is the same alone and
-in any mix (tested).
+free, not until the whole device drains.  Within one route a request's result does
+not depend on the other requests of its batch (bitwise, tested); the two routes agree
+to the parity bound.
 """
 from __future__ import annotations
 
@@ -30,6 +35,17 @@ import torch
 from .ops import Plan, apply_operator
 
 BUCKETS = (1, 2, 4, 8, 16, 32)
+DIRECT_BLOCKS = 4          # the direct route takes batches of up to 4 x 64 signal columns
+ROUTES = ("auto", "operator", "direct")
+
+
+def prefer_direct(n_orders: int, n_blocks: int, L: int) -> bool:
+    """Route choice for one batch from HBM traffic: the direct route streams the (2L+1) N^2 stack
+    elements once per 64-column block (blocks after the first partly hit in L2: measured about
+    0.6 of a stream each at N = 4096, L = 32), the operator route streams them once and adds
+    16 N^2 bytes (write and read of one complex64 operator) per order, i.e. 4 / (2L+1) of a
+    stream per order.  Direct iff 0.6 (blocks - 1) < 4 n_orders / (2L+1)."""
+    return n_blocks <= DIRECT_BLOCKS and 0.15 * (n_blocks - 1) * (2 * L + 1) < n_orders
 
 
 class AdmissionError(RuntimeError):
@@ -37,9 +53,9 @@ class AdmissionError(RuntimeError):
 
 
 class _SlotSet:
-    def __init__(self, plan: Plan, K: int, bmax: int, device, use_graphs: bool):
+    def __init__(self, plan: Plan, K: int, bmax: int, device, use_graphs: bool, route: str = "auto"):
         N = plan.N
-        self.K, self.bmax = K, bmax
+        self.K, self.bmax, self.route = K, bmax, route
         self.stream = torch.cuda.Stream(device=device)
         self.alphas = torch.zeros(K, dtype=torch.float64, device=device)
         self.X = torch.zeros((K, N, bmax), dtype=torch.float32, device=device)
@@ -52,6 +68,17 @@ class _SlotSet:
         self.h_alphas = torch.zeros(K, dtype=torch.float64).pin_memory()
         self.h_X = torch.zeros((K, N, bmax), dtype=torch.float32).pin_memory()
         self.h_Y = torch.empty((K, N, bmax), dtype=torch.complex64).pin_memory()
+        # direct route: per block count nb, signals [N, 64 nb] side by side, column -> order index
+        self.dblocks = range(1, DIRECT_BLOCKS + 1) if route != "operator" else range(0)
+        self.dX = {nb: torch.zeros((N, 64 * nb), dtype=torch.float32, device=device) for nb in self.dblocks}
+        self.dcols = {nb: torch.zeros(64 * nb, dtype=torch.int32, device=device) for nb in self.dblocks}
+        self.dY = {nb: torch.empty((N, 64 * nb), dtype=torch.complex64, device=device) for nb in self.dblocks}
+        self.dws = torch.empty(max([256] + [plan.direct_workspace_bytes(64 * nb, 64 * nb) for nb in self.dblocks]),
+                               dtype=torch.uint8, device=device)
+        self.h_dX = {nb: torch.zeros((N, 64 * nb), dtype=torch.float32).pin_memory() for nb in self.dblocks}
+        self.h_dcols = {nb: torch.zeros(64 * nb, dtype=torch.int32).pin_memory() for nb in self.dblocks}
+        self.h_dY = {nb: torch.empty((N, 64 * nb), dtype=torch.complex64).pin_memory() for nb in self.dblocks}
+        self.taken = None          # (route, bucket, column offsets) of the batch in flight
         self.plan = plan
         self.graphs = {}
         self.batch = None
@@ -59,74 +86,111 @@ class _SlotSet:
         if use_graphs:
             self._capture()
 
-    def _run(self, k: int):
-        self.plan.update_dev(self.alphas[:k], out=self.Q[:k], ws=self.uws)
-        apply_operator(self.Q[:k], self.X[:k], out=self.Y[:k], ws=self.aws)
+    def _run(self, key):
+        route, k = key
+        if route == "direct":
+            self.plan.apply_direct(self.alphas, self.dcols[k], self.dX[k], out=self.dY[k], ws=self.dws)
+        else:
+            self.plan.update_dev(self.alphas[:k], out=self.Q[:k], ws=self.uws)
+            apply_operator(self.Q[:k], self.X[:k], out=self.Y[:k], ws=self.aws)
+
+    def _keys(self):
+        return [("operator", k) for k in BUCKETS if k <= self.K] + [("direct", nb) for nb in self.dblocks]
 
     def _capture(self):
         with torch.cuda.stream(self.stream):
-            for k in BUCKETS:
-                if k <= self.K:
-                    self._run(k)     # eager warm-up (kernel attributes, code objects)
+            for key in self._keys():
+                self._run(key)       # eager warm-up (kernel attributes, code objects)
         self.stream.synchronize()
-        for k in BUCKETS:
-            if k > self.K:
-                continue
+        for key in self._keys():
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=self.stream):
-                self._run(k)
-            self.graphs[k] = g
+                self._run(key)
+            self.graphs[key] = g
         self.stream.synchronize()
 
     def nbytes(self) -> int:
-        return sum(t.numel() * t.element_size() for t in (self.alphas, self.X, self.Q, self.Y, self.uws, self.aws))
+        ts = [self.alphas, self.X, self.Q, self.Y, self.uws, self.aws, self.dws]
+        ts += list(self.dX.values()) + list(self.dcols.values()) + list(self.dY.values())
+        return sum(t.numel() * t.element_size() for t in ts)
+
+    def choose(self, batch) -> tuple:
+        ncols = sum(r.B for r in batch)
+        nb = -(-ncols // 64)
+        if self.dblocks and nb <= DIRECT_BLOCKS and (
+                self.route == "direct" or prefer_direct(len(batch), nb, self.plan.L)):
+            return ("direct", nb)
+        k = next(b for b in BUCKETS if b >= len(batch)) if self.graphs else len(batch)
+        return ("operator", k)
 
     def launch(self, batch):
         n = len(batch)
         t = time.perf_counter()
         for r in batch:
             r.t_launch, r.batch_size = t, n
-        k = next(b for b in BUCKETS if b >= n) if self.graphs else n
-        # padding orders get alpha = 0 (a valid order); padding rows and signal columns of X
-        # are left as they are: every order's plane and every signal column is computed
-        # independently (per-column scales in the apply), and padded outputs are never returned
-        self.h_alphas[n:k] = 0.0
-        for i, r in enumerate(batch):
-            self.h_alphas[i] = r.alpha
-            self.h_X[i, :, : r.B] = r.X
+        route, k = key = self.choose(batch)
+        # padding orders get alpha = 0 (a valid order); padding rows and signal columns are left
+        # as they are: every order's plane and every signal column is computed independently
+        # (per-column scales), and padded outputs are never returned
+        self.h_alphas[n:] = 0.0
+        offs = []
+        if route == "direct":
+            hx, hc, off = self.h_dX[k], self.h_dcols[k], 0
+            hc.zero_()
+            for i, r in enumerate(batch):
+                self.h_alphas[i] = r.alpha
+                hx[:, off: off + r.B] = r.X
+                hc[off: off + r.B] = i
+                offs.append(off)
+                off += r.B
+        else:
+            for i, r in enumerate(batch):
+                self.h_alphas[i] = r.alpha
+                self.h_X[i, :, : r.B] = r.X
         with torch.cuda.stream(self.stream):
             self.alphas.copy_(self.h_alphas, non_blocking=True)
-            self.X[:k].copy_(self.h_X[:k], non_blocking=True)
-            if self.graphs:
-                self.graphs[k].replay()
+            if route == "direct":
+                self.dcols[k].copy_(self.h_dcols[k], non_blocking=True)
+                self.dX[k].copy_(self.h_dX[k], non_blocking=True)
             else:
-                self._run(k)
-            self.h_Y[:n].copy_(self.Y[:n], non_blocking=True)
+                self.X[:k].copy_(self.h_X[:k], non_blocking=True)
+            if self.graphs:
+                self.graphs[key].replay()
+            else:
+                self._run(key)
+            if route == "direct":
+                self.h_dY[k].copy_(self.dY[k], non_blocking=True)
+            else:
+                self.h_Y[:n].copy_(self.Y[:n], non_blocking=True)
             self.event = torch.cuda.Event()
             self.event.record(self.stream)
-        self.batch = batch
+        self.batch, self.taken = batch, (route, k, offs)
 
     def done(self) -> bool:
         return self.batch is not None and self.event.query()
 
     def retire(self, now: float):
+        route, k, offs = self.taken
         for i, r in enumerate(self.batch):
-            r.t_done = now
-            r.future.set_result(self.h_Y[i, :, : r.B].numpy().copy())
+            r.t_done, r.route = now, route
+            if route == "direct":
+                y = self.h_dY[k][:, offs[i]: offs[i] + r.B].numpy().copy()
+            else:
+                y = self.h_Y[i, :, : r.B].numpy().copy()
+            r.future.set_result(y)
             r.future = None    # the result now belongs to the caller's future alone
-        self.batch = None
-        self.event = None
+        self.batch = self.event = self.taken = None
 
 
 class _Request:
-    __slots__ = ("gid", "alpha", "X", "B", "t_arrive", "t_launch", "t_done", "batch_size", "future")
+    __slots__ = ("gid", "alpha", "X", "B", "t_arrive", "t_launch", "t_done", "batch_size", "future", "route")
 
     def __init__(self, gid, alpha, X, t_arrive):
         self.gid, self.alpha = gid, float(alpha)
         self.X = torch.as_tensor(np.asarray(X, dtype=np.float32))
         self.B = self.X.shape[1]
         self.t_arrive, self.t_launch, self.t_done, self.batch_size = t_arrive, None, None, 0
-        self.future = Future()
+        self.future, self.route = Future(), None
 
 
 class Server:
@@ -134,13 +198,17 @@ class Server:
 
     hbm_budget: bytes of device memory the server may hold (plans + slot sets).
     K: orders per batch (one fused update launch); bmax: largest signal block;
-    slot_sets: batches of one plan that may be in flight at once.
+    slot_sets: batches of one plan that may be in flight at once;
+    route: "auto" (per batch, prefer_direct), "operator" or "direct" (when the batch's
+    signals fit DIRECT_BLOCKS x 64 columns, else the operator route).
     """
 
     def __init__(self, hbm_budget: int, K: int = 16, bmax: int = 64, slot_sets: int = 2, use_graphs: bool = True,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", route: str = "auto"):
+        if route not in ROUTES:
+            raise ValueError(f"route must be one of {ROUTES}")
         self.budget, self.used = int(hbm_budget), 0
-        self.K, self.bmax, self.S = K, bmax, slot_sets
+        self.K, self.bmax, self.S, self.route = K, bmax, slot_sets, route
         self.use_graphs = use_graphs
         self.device = torch.device(device)
         self.plans = {}
@@ -155,6 +223,8 @@ class Server:
         pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
         lib().fgfrft_plan_bytes(N, L, 1, 0, ctypes.byref(pb), ctypes.byref(sb))
         per_set = self.K * N * N * 8 + self.K * N * self.bmax * (4 + 8)
+        if self.route != "operator":      # direct-route signal and result blocks (1..4 x 64 columns)
+            per_set += 10 * 64 * N * (4 + 8)
         return int(pb.value) + self.S * per_set
 
     def add_plan(self, gid, F: np.ndarray, L: int) -> None:
@@ -165,7 +235,7 @@ class Server:
             raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {need / 1e9:.2f} GB; "
                                  f"{(self.budget - self.used) / 1e9:.2f} GB left")
         plan = Plan(torch.from_numpy(np.ascontiguousarray(F)).to(self.device), L)
-        sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs) for _ in range(self.S)]
+        sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs, self.route) for _ in range(self.S)]
         self.plans[gid] = plan
         self.slots[gid] = sets
         self.used += need
@@ -260,6 +330,7 @@ def _run_trace(server: Server, trace, signals: dict, warmup: int, keep_every: in
             time.sleep(max(0.0, min(nxt, 200e-6)))
     wall = time.perf_counter() - t0
     rs = reqs[warmup:]
+    direct_share = float(np.mean([r.route == "direct" for r in rs]))
     lat = np.array([r.t_done - r.t_arrive for r in rs])
     wait = np.array([r.t_launch - r.t_arrive for r in rs])
     service = np.array([r.t_done - r.t_launch for r in rs])
@@ -270,7 +341,7 @@ def _run_trace(server: Server, trace, signals: dict, warmup: int, keep_every: in
                 queue_wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
                 service_p50_ms=float(np.percentile(service, 50) * 1e3),
                 service_p99_ms=float(np.percentile(service, 99) * 1e3),
-                mean_batch=float(np.mean([r.batch_size for r in rs])), kept=kept)
+                mean_batch=float(np.mean([r.batch_size for r in rs])), direct_share=direct_share, kept=kept)
 
 
 def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0, keep_every: int = 1) -> dict:

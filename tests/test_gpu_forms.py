@@ -147,9 +147,9 @@ def test_update_dev_matches_host_orders_and_flags_out_of_range():
 # ----------------------------------------------------------------------------
 # serving loop
 # ----------------------------------------------------------------------------
-def _server(torch, use_graphs, Ns=(64, 100, 256), L=10):
+def _server(torch, use_graphs, Ns=(64, 100, 256), L=10, route="auto"):
     from paper_2602_20870_amd.serve import Server
-    srv = Server(hbm_budget=8 << 30, K=8, bmax=16, slot_sets=2, use_graphs=use_graphs)
+    srv = Server(hbm_budget=8 << 30, K=8, bmax=16, slot_sets=2, use_graphs=use_graphs, route=route)
     Fs = {}
     for i, N in enumerate(Ns):
         F = _orth(N, i, 20 + i)
@@ -158,10 +158,11 @@ def _server(torch, use_graphs, Ns=(64, 100, 256), L=10):
     return srv, Fs
 
 
-def test_serving_result_alone_equals_result_in_mix_and_oracle():
+@pytest.mark.parametrize("route", ["auto", "operator", "direct"])
+def test_serving_result_alone_equals_result_in_mix_and_oracle(route):
     torch = torch_cuda()
-    announce("serving alone vs mix")
-    srv, Fs = _server(torch, use_graphs=True)
+    announce(f"serving alone vs mix, route={route}")
+    srv, Fs = _server(torch, use_graphs=True, route=route)
     rng = np.random.default_rng(2)
     reqs = [(int(rng.integers(0, 3)), float(rng.uniform(-2, 2)), int(rng.integers(1, 17))) for _ in range(40)]
     sig = {g: rng.standard_normal((F.shape[0], 16)).astype(np.float32) for g, F in Fs.items()}
@@ -182,7 +183,7 @@ def test_serving_result_alone_equals_result_in_mix_and_oracle():
         yr = refs[g].combine(a) @ sig[g][:, :b].astype(np.float64)
         assert rel_fro(y, yr) <= TOL_FP32
     # graph replays equal eager launches (several replays, eager work in between)
-    eager, _ = _server(torch, use_graphs=False)
+    eager, _ = _server(torch, use_graphs=False, route=route)
     fut_e = [eager.submit(g, a, sig[g][:, :b]) for g, a, b in reqs]
     eager.drain()
     for fe, y in zip(fut_e, mixed):
