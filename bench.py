@@ -31,8 +31,11 @@ COPY_BYTES = 1 << 31          # plain device copy used as the counter and bandwi
 # then WRITE_SIZE, KiB per dispatch), each scaled by the same counter's reading for the plain
 # copy of COPY_BYTES that this script runs.  Valid only for the kernel sources with this digest:
 # once update.hip or internal.h change, the figure is reported as null until re-measured.
-UPDATE_TRAFFIC = {"fetch_bytes": 4363863126, "write_bytes": 34392583146,
-                  "source_sha256": "bf923680ba52071387085d6e304c7847e3a69451098a9068fd5a9ac4156769d8"}
+UPDATE_TRAFFIC = {"fetch_bytes": 4363906859, "write_bytes": 34392347840,
+                  "source_sha256": "d0338217b0c127152606813075f1c1faaa26f8bbcd07713db03d12cdbd247c3d"}
+# The same for one k_direct launch over 64 signal columns of the knn4096 plan (direct.hip + internal.h).
+DIRECT_TRAFFIC = {"fetch_bytes": 4743810464, "write_bytes": 26214400, "ncols": 64,
+                  "source_sha256": "e464e89210b6b7dc9b01ab1fbbb9efb7d5c5d05269a9cd2139c959199db6bdb4"}
 
 
 def log(msg):
@@ -49,13 +52,17 @@ def apply_algorithmic_bytes(N, B, n_alpha):
     return n_alpha * (8.0 * N * N + 12.0 * N * B)
 
 
-def update_source_digest():
+def source_digest(main):
     import hashlib
     h = hashlib.sha256()
-    for f in ("update.hip", "internal.h"):
+    for f in (main, "internal.h"):
         with open(os.path.join(ROOT, "paper_2602_20870_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def update_source_digest():
+    return source_digest("update.hip")
 
 
 def update_traffic():
@@ -187,8 +194,9 @@ SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
 
 
 def direct_algorithmic_bytes(N, L, ncols):
-    # the stack and P streamed once per 64-column block: (2L + 1) 4 N^2, plus x read (4 N) and y written (8 N)
-    return -(-ncols // 64) * (2 * L + 1) * 4.0 * N * N + 12.0 * N * ncols
+    # the 2L resident stack matrices and P read once, (2L + 1) 4 N^2, plus x read (4 N) and y written
+    # (8 N) per column; wider calls stream the stack once per 64-column block (L2 catches part of it)
+    return (2 * L + 1) * 4.0 * N * N + 12.0 * N * ncols
 
 
 def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16))):
@@ -244,7 +252,46 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
             f"({alg / (res['direct'] * 1e-3) / 1e9:.0f} GB/s algorithmic, rel diff {diff:.1e})")
         del X, Xd, Yd, ws, Q, Y2
         torch.cuda.empty_cache()
-    return {"workload": f"knn4096 plan (N={N}, L={L}), real signals, orders from the main workload", "cases": out}
+    res = {"workload": f"knn4096 plan (N={N}, L={L}), real signals, orders from the main workload", "cases": out}
+    # roofline of the direct route on the 64-column case: HIP events on this stream around the
+    # whole call, i.e. k_direct plus its set-up kernels (column scales, coefficient table, signal
+    # split) and the final reduction, about 50 us together; an upper bound on k_direct's time
+    n, B = 32, 2
+    ms = direct_call_ms(plan, alphas[:n], B, dev)
+    alg = direct_algorithmic_bytes(N, L, n * B)
+    traffic = None
+    if source_digest("direct.hip") == DIRECT_TRAFFIC["source_sha256"] and N == 4096 and L == 32:
+        traffic = DIRECT_TRAFFIC["fetch_bytes"] + DIRECT_TRAFFIC["write_bytes"]
+    res["roofline"] = {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                       "kernel": "k_direct (timed call includes its set-up and reduction kernels)",
+                       "ms": ms, "ncols": n * B}
+    log(f"direct call (64 columns): {ms:.3f} ms, {alg / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+    return res
+
+
+def direct_call_ms(plan, alphas, B, dev, reps=10):
+    """Median duration of one direct-route call (HIP events on the current stream)."""
+    import torch
+    import synth
+    N, n = plan.N, len(alphas)
+    rng = synth.streams(6, 1)[0]
+    Xd = torch.from_numpy(synth.real_signals((N, n * B), rng).astype(np.float32)).to(dev)
+    cols = torch.arange(n, dtype=torch.int32, device=dev).repeat_interleave(B)
+    al = torch.from_numpy(np.ascontiguousarray(alphas)).to(dev)
+    Yd = torch.empty((N, n * B), dtype=torch.complex64, device=dev)
+    ws = torch.empty(plan.direct_workspace_bytes(n * B, n * B), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    times = []
+    for i in range(reps + 2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.apply_direct(al, cols, Xd, out=Yd, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i >= 2:
+            times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
 
 
 def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_sets=1, per_request=True,
