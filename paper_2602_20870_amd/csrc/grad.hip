@@ -8,7 +8,7 @@
 // {M_1..M_L, M_1^H..M_L^H, P, I}; the host combines them with c_n'(alpha) in FP64.
 //
 // Steps per chunk of orders:
-//   k_outer      G_a = GY[a] X[a]^H                     (FP32, LDS-tiled)
+//   k_outer      G_a = GY[a] X[a]^H                     (FP32 on the matrix cores, LDS-tiled)
 //   k_inner      per 16x16 tile: the tile's 2L stack matrices staged in LDS once,
 //                partial sums of T over the tile's positions for every order of the chunk
 //   k_inner_sum  fixed-order sum of the partials over all tiles in FP64 (deterministic)
@@ -21,68 +21,75 @@ namespace fgfrft {
 constexpr int GT = 16, GPOS = 256;
 
 // ---------------------------------------------------------------- G = GY X^H
-// 64x64 output tile, 256 threads with 4x4 outputs each, k (signals) in chunks of 16.
+// 64x64 output tile per workgroup, one 32x32 block per wave, on the matrix cores in FP32
+// (v_mfma_f32_32x32x2_f32: FP32 products and sums, the accuracy of the plain FMA form); the
+// signals advance in chunks of 32 staged through LDS as separate real / imaginary planes
+// (zero outside N x B).  G = GY conj(X): Re = gr xr + gi xi, Im = gi xr - gr xi.
+constexpr int OKC = 32, OPITCH = OKC + 1;
+
+__device__ __forceinline__ floatx16 mfma_f32(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
 template <bool XC>
 __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, const void* __restrict__ X, int x_shared,
                                                int N, int B, int a_first, cplx64* __restrict__ G,
                                                float* __restrict__ gmax) {
-  __shared__ float Ar[16][65], Ai[16][65], Br[16][65], Bi[16][65];
-  const int tid = threadIdx.x, a = a_first + blockIdx.z;
+  __shared__ float Ar[64][OPITCH], Ai[64][OPITCH], Br[64][OPITCH], Bi[XC ? 64 : 1][OPITCH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lk = lane >> 5;
+  const int a = a_first + blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const int ti = (tid / 16) * 4, tj = (tid % 16) * 4;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   const cplx64* gy = GY + (size_t)a * N * B;
   const size_t xoff = x_shared ? 0 : (size_t)a * N * B;
-  float accr[4][4] = {}, acci[4][4] = {};
-  for (int b0 = 0; b0 < B; b0 += 16) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int r = e / 16, c = e % 16;
+  floatx16 accr = {}, acci = {};
+  for (int b0 = 0; b0 < B; b0 += OKC) {
+    for (int e = tid; e < 64 * OKC; e += 256) {
+      const int r = e / OKC, c = e % OKC;
       const int gi = i0 + r, gj = j0 + r, gb = b0 + c;
       cplx64 g = {0.f, 0.f};
       if (gi < N && gb < B) g = gy[(size_t)gi * B + gb];
-      Ar[c][r] = g.re;
-      Ai[c][r] = g.im;
+      Ar[r][c] = g.re;
+      Ai[r][c] = g.im;
       float xr = 0.f, xi = 0.f;
       if (gj < N && gb < B) {
         if (XC) { const float2 v = ((const float2*)X)[xoff + (size_t)gj * B + gb]; xr = v.x; xi = v.y; }
         else xr = ((const float*)X)[xoff + (size_t)gj * B + gb];
       }
-      Br[c][r] = xr;
-      Bi[c][r] = xi;
+      Br[r][c] = xr;
+      if (XC) Bi[r][c] = xi;
     }
     __syncthreads();
+    // A: lane holds row wi + l32 at k = 2 ks + lk; B: column wj + l32 at the same k
 #pragma unroll 4
-    for (int c = 0; c < 16; ++c) {
-      float ar[4], ai[4], br[4], bi[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ar[q] = Ar[c][ti + q]; ai[q] = Ai[c][ti + q];
-        br[q] = Br[c][tj + q]; bi[q] = Bi[c][tj + q];
+    for (int ks = 0; ks < OKC / 2; ++ks) {
+      const int k = 2 * ks + lk;
+      const float ar = Ar[wi + l32][k], ai = Ai[wi + l32][k], br = Br[wj + l32][k];
+      accr = mfma_f32(ar, br, accr);
+      acci = mfma_f32(ai, br, acci);
+      if (XC) {
+        const float bi = Bi[wj + l32][k];
+        accr = mfma_f32(ai, bi, accr);
+        acci = mfma_f32(-ar, bi, acci);
       }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {  // g * conj(x)
-          accr[x][y] += ar[x] * br[y] + ai[x] * bi[y];
-          acci[x][y] += ai[x] * br[y] - ar[x] * bi[y];
-        }
     }
     __syncthreads();
   }
+  // lane holds column j0 + wj + l32, rows i0 + wi + 8 (e / 4) + 4 lk + e % 4
   cplx64* g = G + (size_t)blockIdx.z * N * N;
+  const int gj = j0 + wj + l32;
   float m = 0.f;
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int gi = i0 + ti + x, gj = j0 + tj + y;
-      if (gi < N && gj < N) {
-        g[(size_t)gi * N + gj] = cplx64{accr[x][y], acci[x][y]};
-        m = fmaxf(m, fmaxf(fabsf(accr[x][y]), fabsf(acci[x][y])));
-      }
+  for (int e = 0; e < 16; ++e) {
+    const int gi = i0 + wi + 8 * (e >> 2) + 4 * lk + (e & 3);
+    if (gi < N && gj < N) {
+      g[(size_t)gi * N + gj] = cplx64{accr[e], acci[e]};
+      m = fmaxf(m, fmaxf(fabsf(accr[e]), fabsf(acci[e])));
     }
+  }
   // largest |Re|, |Im| of this tile -> gmax[order][tile] (the scale of the split operands)
   if (gmax) {
-    __syncthreads();
     float* red = &Ar[0][0];
     red[tid] = m;
     __syncthreads();
