@@ -31,7 +31,8 @@ __device__ __forceinline__ floatx16 mfma_f32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-template <bool XC>
+// VEC: B % 4 == 0 and 16-byte aligned GY and X, so the staging moves 16 bytes per load.
+template <bool XC, bool VEC>
 __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, const void* __restrict__ X, int x_shared,
                                                int N, int B, int a_first, cplx64* __restrict__ G,
                                                float* __restrict__ gmax) {
@@ -45,6 +46,32 @@ __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, co
   const size_t xoff = x_shared ? 0 : (size_t)a * N * B;
   floatx16 accr = {}, acci = {};
   for (int b0 = 0; b0 < B; b0 += OKC) {
+    if (VEC) {
+      for (int e = tid; e < 64 * (OKC / 2); e += 256) {       // GY: two complex values per load
+        const int r = e / (OKC / 2), q = e % (OKC / 2);
+        const int gi = i0 + r, gb = b0 + 2 * q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gi < N && gb < B) v = *(const float4*)(gy + (size_t)gi * B + gb);
+        Ar[r][2 * q] = v.x; Ai[r][2 * q] = v.y; Ar[r][2 * q + 1] = v.z; Ai[r][2 * q + 1] = v.w;
+      }
+      if (XC) {
+        for (int e = tid; e < 64 * (OKC / 2); e += 256) {
+          const int r = e / (OKC / 2), q = e % (OKC / 2);
+          const int gj = j0 + r, gb = b0 + 2 * q;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (gj < N && gb < B) v = *(const float4*)((const float2*)X + xoff + (size_t)gj * B + gb);
+          Br[r][2 * q] = v.x; Bi[r][2 * q] = v.y; Br[r][2 * q + 1] = v.z; Bi[r][2 * q + 1] = v.w;
+        }
+      } else {
+        for (int e = tid; e < 64 * (OKC / 4); e += 256) {      // X: four real values per load
+          const int r = e / (OKC / 4), q = e % (OKC / 4);
+          const int gj = j0 + r, gb = b0 + 4 * q;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (gj < N && gb < B) v = *(const float4*)((const float*)X + xoff + (size_t)gj * B + gb);
+          Br[r][4 * q] = v.x; Br[r][4 * q + 1] = v.y; Br[r][4 * q + 2] = v.z; Br[r][4 * q + 3] = v.w;
+        }
+      }
+    } else
     for (int e = tid; e < 64 * OKC; e += 256) {
       const int r = e / OKC, c = e % OKC;
       const int gi = i0 + r, gj = j0 + r, gb = b0 + c;
@@ -633,8 +660,15 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
       dim3 g(ceil_div(N, 64), ceil_div(N, 64), nc);
       const void* xa = x_shared ? X : (const void*)((const char*)X + (size_t)a0 * NB * (x_complex ? 8 : 4));
       float* gm = use_mfma ? gmax : nullptr;
-      if (x_complex) k_outer<true><<<g, 256, 0, s>>>(gy + (size_t)a0 * NB, xa, x_shared, N, B, 0, Gbuf, gm);
-      else k_outer<false><<<g, 256, 0, s>>>(gy + (size_t)a0 * NB, xa, x_shared, N, B, 0, Gbuf, gm);
+      const cplx64* gya = gy + (size_t)a0 * NB;
+      const bool vec = B % 4 == 0 && (uintptr_t)gya % 16 == 0 && (uintptr_t)xa % 16 == 0;
+      if (x_complex) {
+        if (vec) k_outer<true, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
+        else k_outer<true, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
+      } else {
+        if (vec) k_outer<false, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
+        else k_outer<false, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
+      }
       FG_LAUNCHED("outer");
     }
     if (use_mfma) {
