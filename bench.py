@@ -190,6 +190,66 @@ def table4_bench(sizes=(1000, 2000, 3000, 4000, 5000, 6000, 7000, 8000), L=10, a
     return {"workload": f"Haar eigenvectors, uniform phases, L={L}, alpha={alpha}", "rows": rows}
 
 
+def precision_form_bench(chunks=(32, 128), reps=3):
+    """Precision-form workload (grid8192: 128x64 grid, lognormal weights, N = 8192, L = 64): one
+    update launch per order chunk on the FP32 stack and on the BF16 hi/lo stack (both 4 bytes per
+    real value), and the apply of a 32-order chunk to one shared block of 1024 real signals."""
+    import torch
+    import synth
+    from paper_2602_20870_amd import Plan, apply_operator
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    cfg = synth.make_config("grid8192", seed=0, with_signals=False)
+    F, L, N = cfg["F"], cfg["L"], cfg["N"]
+    alphas = cfg["alphas"]
+    log(f"grid8192 built in {time.time() - t0:.0f}s")
+    Ft = torch.from_numpy(F).to(dev)
+    rng = synth.streams(0, 3)[2]
+    X = torch.from_numpy(synth.real_signals((N, 1024), rng).astype(np.float32)).to(dev)
+    out = {"workload": "grid8192: 128x64 grid, lognormal(0, 0.5) weights, N=8192, L=64, orders in [-2, 2]",
+           "forms": []}
+    for st in ("fp32", "bf16x2"):
+        t0 = time.perf_counter()
+        plan = Plan(Ft, L, stacktype=st)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        for n in chunks:
+            Q = torch.empty((n, N, N), dtype=torch.complex64, device=dev)
+            al = alphas[:n]
+            plan.update(al, out=Q)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                plan.update(al, out=Q)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            alg = update_algorithmic_bytes(N, L, n)
+            row = {"stacktype": st, "orders": n, "update_ms": ms, "updates_per_s": n / (ms * 1e-3),
+                   "algorithmic_GB": alg / 1e9, "algorithmic_GBps": alg / (ms * 1e-3) / 1e9, "plan_s": plan_s}
+            if n == 32:
+                Y = apply_operator(Q, X)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    apply_operator(Q, X, out=Y)
+                e1.record()
+                e1.synchronize()
+                ams = e0.elapsed_time(e1) / reps
+                flops = 32 * 4.0 * N * N * 1024      # complex Q times real X: 4 N^2 B flops per order
+                row.update(apply_ms=ams, apply_signals=1024, apply_TFLOPs=flops / (ams * 1e-3) / 1e12)
+                del Y
+            log(f"precision form {row}")
+            out["forms"].append(row)
+            del Q
+            torch.cuda.empty_cache()
+        del plan
+        torch.cuda.empty_cache()
+    return out
+
+
 SERVE_NS = (256, 512, 1024, 1024, 2048, 2048, 4096, 4096)
 
 
@@ -353,6 +413,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-route comparison")
+    ap.add_argument("--precision-form", action="store_true",
+                    help="only the precision-form workload (grid8192, N = 8192, L = 64, FP32 and BF16X2 stacks)")
     ap.add_argument("--table4", action="store_true",
                     help="only the Table IV workload (FGFRFT vs exact GFRFT online time, N = 1000..8000)")
     args = ap.parse_args()
@@ -367,6 +429,9 @@ def main():
     lib()  # fail loudly if the HIP library is missing
     if args.table4:
         print(json.dumps({"table4": table4_bench()}), flush=True)
+        return
+    if args.precision_form:
+        print(json.dumps({"precision_form": precision_form_bench()}), flush=True)
         return
     dev = torch.device("cuda:0")
     t0 = time.time()
