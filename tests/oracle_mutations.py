@@ -1,0 +1,143 @@
+"""Plausible mistakes planted in the CPU oracle, to check that the pins catch each of them.
+
+Each entry replaces one oracle routine by a variant with a single slip (a dropped term, a
+wrong sign or index, a missing conjugate, a transposed operand).  ``apply(name)`` installs
+it in both the module and the package namespace, in this process only; the mutation test
+runs the pin suite in a child process with the variable FGFRFT_ORACLE_MUTATION set, and the
+test configuration installs the named mutation before collection.  Nothing here touches the
+GPU library.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _coefficients_index_flip(alpha, L):
+    n = np.arange(-L, L + 1, dtype=np.float64)
+    x = alpha + n                                   # slip: c_n(alpha) = sinc(alpha + n)
+    out = np.ones_like(x)
+    nz = x != 0.0
+    out[nz] = np.sin(np.pi * x[nz]) / (np.pi * x[nz])
+    return out
+
+
+def _coefficients_unnormalised(alpha, L):
+    n = np.arange(-L, L + 1, dtype=np.float64)
+    x = alpha - n
+    out = np.ones_like(x)
+    nz = x != 0.0
+    out[nz] = np.sin(np.pi * x[nz]) / x[nz]         # slip: the 1/pi of the sinc dropped
+    return out
+
+
+def _derivatives_sign(alpha, L):
+    from oracle import fgfrft as m
+    return -_ORIG["coefficient_derivatives"](alpha, L)  # slip: sign of dc_n/dalpha
+
+
+def _combine(variant):
+    def f(P, M, alpha):
+        from oracle import fgfrft as m
+        L = len(M) - 1
+        c = m.coefficients(alpha, L)
+        ph = np.exp(-1j * np.pi * alpha) if variant == "phase_sign" else np.exp(1j * np.pi * alpha)
+        Q = (0.0 if variant == "drop_P" else ph) * P
+        Q = Q + c[L] * (np.eye(P.shape[0]) if variant == "c0_identity" else M[0])
+        for n in range(1, L + 1):
+            neg = M[n] if variant == "no_adjoint" else (M[n].T if variant == "transpose_only" else M[n].conj().T)
+            Q = Q + c[L + n] * M[n] + c[L - n] * neg
+        return Q
+    return f
+
+
+def _power_stack_off_by_one(F, Pc, L):
+    M = [np.array(Pc, dtype=np.result_type(F, Pc))]
+    for _ in range(L):
+        M.append(F @ M[-1])
+    return [M[0]] + [F @ m_ for m_ in M[1:]]        # slip: M_n = F^{n+1} P_c for n >= 1
+
+
+def _split_projectors_transpose(F, tau=1e-6, decomposition=None):
+    from oracle import fgfrft as m
+    Z, theta, m1 = decomposition if decomposition is not None else m.spectral_decomposition(F, tau)
+    W = Z[:, m1]
+    P = W @ W.T                                     # slip: transpose instead of conjugate transpose
+    return P, np.eye(F.shape[0]) - P, int(m1.sum())
+
+
+def _spectral_snap_minus_pi(F, tau=1e-6):
+    Z, theta, m1 = _ORIG["spectral_decomposition"](F, tau)
+    theta = theta.copy()
+    theta[m1] = -np.pi                              # slip: the -1 phase on the other branch end
+    return Z, theta, m1
+
+
+def _dQ_drop_P(P, M, alpha):
+    from oracle import fgfrft as m
+    L = len(M) - 1
+    d = m.coefficient_derivatives(alpha, L)
+    D = d[L] * M[0]                                 # slip: the j pi e^{j pi alpha} P term dropped
+    for n in range(1, L + 1):
+        D = D + d[L + n] * M[n] + d[L - n] * M[n].conj().T
+    return D
+
+
+def _grad_no_conj(P, M, alphas, X, GY, x_real=None):
+    from oracle import fgfrft as m
+    X = np.asarray(X)
+    if x_real is None:
+        x_real = np.isrealobj(X)
+    dal = np.empty(len(alphas))
+    dX = np.empty(X.shape, dtype=np.float64 if x_real else np.complex128)
+    for a, al in enumerate(alphas):
+        Q = m.fgfrft_combine(P, M, al)
+        D = m.dQ_dalpha(P, M, al)
+        GQ = GY[a] @ X[a].T                         # slip: X^T instead of X^H
+        dal[a] = float(np.real(np.sum(GQ.conj() * D)))
+        g = Q.T @ GY[a]                             # slip: Q^T instead of Q^H
+        dX[a] = g.real if x_real else g
+    return dal, dX
+
+
+def _residual_sign(theta, alpha, L):
+    from oracle import fgfrft as m
+    theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    c = m.coefficients(alpha, L)
+    n = np.arange(-L, L + 1)
+    return np.exp(1j * alpha * theta) - np.exp(-1j * np.outer(theta, n)) @ c   # slip: e^{-j n theta}
+
+
+def _exact_conj(F, alpha, decomposition=None):
+    from oracle import fgfrft as m
+    Z, theta, _ = decomposition if decomposition is not None else m.spectral_decomposition(F)
+    return (Z * np.exp(-1j * alpha * theta)[None, :]) @ Z.conj().T   # slip: e^{-j alpha theta}
+
+
+MUTATIONS = {
+    "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
+    "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
+    "derivatives_sign": ("coefficient_derivatives", _derivatives_sign),
+    "combine_drop_P": ("fgfrft_combine", _combine("drop_P")),
+    "combine_phase_sign": ("fgfrft_combine", _combine("phase_sign")),
+    "combine_c0_identity": ("fgfrft_combine", _combine("c0_identity")),
+    "combine_no_adjoint": ("fgfrft_combine", _combine("no_adjoint")),
+    "combine_transpose_only": ("fgfrft_combine", _combine("transpose_only")),
+    "power_stack_off_by_one": ("power_stack", _power_stack_off_by_one),
+    "projector_transpose": ("split_projectors", _split_projectors_transpose),
+    "snap_minus_pi": ("spectral_decomposition", _spectral_snap_minus_pi),
+    "dQ_drop_P": ("dQ_dalpha", _dQ_drop_P),
+    "grad_no_conj": ("grad", _grad_no_conj),
+    "residual_sign": ("truncation_residual", _residual_sign),
+    "exact_conj": ("gfrft_exact", _exact_conj),
+}
+
+_ORIG: dict = {}
+
+
+def apply(name: str) -> None:
+    import oracle
+    from oracle import fgfrft as m
+    target, fn = MUTATIONS[name]
+    _ORIG[target] = getattr(m, target)
+    setattr(m, target, fn)
+    setattr(oracle, target, fn)
