@@ -78,11 +78,17 @@ class _SlotSet:
         self.h_dX = {nb: torch.zeros((N, 64 * nb), dtype=torch.float32).pin_memory() for nb in self.dblocks}
         self.h_dcols = {nb: torch.zeros(64 * nb, dtype=torch.int32).pin_memory() for nb in self.dblocks}
         self.h_dY = {nb: torch.empty((N, 64 * nb), dtype=torch.complex64).pin_memory() for nb in self.dblocks}
+        # NumPy views of the pinned staging: the scheduling loop packs and unpacks with single-threaded
+        # NumPy copies (torch's host copies fan out to its thread pool, whose wake-ups stall the loop)
+        self.n_alphas, self.n_X, self.n_Y = self.h_alphas.numpy(), self.h_X.numpy(), self.h_Y.numpy()
+        self.n_dX = {nb: t.numpy() for nb, t in self.h_dX.items()}
+        self.n_dcols = {nb: t.numpy() for nb, t in self.h_dcols.items()}
+        self.n_dY = {nb: t.numpy() for nb, t in self.h_dY.items()}
+        self.event = torch.cuda.Event()   # recorded after each batch (one event reused)
         self.taken = None          # (route, bucket, column offsets) of the batch in flight
         self.plan = plan
         self.graphs = {}
         self.batch = None
-        self.event = None
         if use_graphs:
             self._capture()
 
@@ -132,21 +138,21 @@ class _SlotSet:
         # padding orders get alpha = 0 (a valid order); padding rows and signal columns are left
         # as they are: every order's plane and every signal column is computed independently
         # (per-column scales), and padded outputs are never returned
-        self.h_alphas[n:] = 0.0
+        self.n_alphas[n:] = 0.0
         offs = []
         if route == "direct":
-            hx, hc, off = self.h_dX[k], self.h_dcols[k], 0
-            hc.zero_()
+            hx, hc, off = self.n_dX[k], self.n_dcols[k], 0
+            hc[:] = 0
             for i, r in enumerate(batch):
-                self.h_alphas[i] = r.alpha
+                self.n_alphas[i] = r.alpha
                 hx[:, off: off + r.B] = r.X
                 hc[off: off + r.B] = i
                 offs.append(off)
                 off += r.B
         else:
             for i, r in enumerate(batch):
-                self.h_alphas[i] = r.alpha
-                self.h_X[i, :, : r.B] = r.X
+                self.n_alphas[i] = r.alpha
+                self.n_X[i, :, : r.B] = r.X
         with torch.cuda.stream(self.stream):
             self.alphas.copy_(self.h_alphas, non_blocking=True)
             if route == "direct":
@@ -162,7 +168,6 @@ class _SlotSet:
                 self.h_dY[k].copy_(self.dY[k], non_blocking=True)
             else:
                 self.h_Y[:n].copy_(self.Y[:n], non_blocking=True)
-            self.event = torch.cuda.Event()
             self.event.record(self.stream)
         self.batch, self.taken = batch, (route, k, offs)
 
@@ -174,12 +179,12 @@ class _SlotSet:
         for i, r in enumerate(self.batch):
             r.t_done, r.route = now, route
             if route == "direct":
-                y = self.h_dY[k][:, offs[i]: offs[i] + r.B].numpy().copy()
+                y = self.n_dY[k][:, offs[i]: offs[i] + r.B].copy()
             else:
-                y = self.h_Y[i, :, : r.B].numpy().copy()
+                y = self.n_Y[i, :, : r.B].copy()
             r.future.set_result(y)
             r.future = None    # the result now belongs to the caller's future alone
-        self.batch = self.event = self.taken = None
+        self.batch = self.taken = None
 
 
 class _Request:
@@ -187,7 +192,7 @@ class _Request:
 
     def __init__(self, gid, alpha, X, t_arrive):
         self.gid, self.alpha = gid, float(alpha)
-        self.X = torch.as_tensor(np.asarray(X, dtype=np.float32))
+        self.X = np.asarray(X, dtype=np.float32)
         self.B = self.X.shape[1]
         self.t_arrive, self.t_launch, self.t_done, self.batch_size = t_arrive, None, None, 0
         self.future, self.route = Future(), None
