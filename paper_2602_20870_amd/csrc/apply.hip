@@ -254,11 +254,14 @@ struct Apply2Layout {
   static_assert((RPI * 4) % CPR == 0, "row swizzle constant per wave");
 };
 
-template <bool XC, bool YREAL, int NS, int K2>
+// PRE (real signals, K2 = 32): X is the pre-split signal block of xsplit_launch, so a stage's
+// B fragments are plain 16-byte LDS reads (no per-wave split of the same signals).
+template <bool XC, bool YREAL, int NS, int K2, bool PRE = false>
 __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q, int N, int n_alpha,
                                                    const void* __restrict__ X, int x_shared, int B,
                                                    const float2* __restrict__ xscale, void* __restrict__ Y, int nrb,
                                                    int ncb) {
+  static_assert(!PRE || (!XC && K2 == 32), "pre-split signals: real, 32-wide k stages");
   using LY = Apply2Layout<XC, K2>;
   constexpr int XE = XC ? 8 : 4, CPR = LY::CPR, RPI = LY::RPI;
   extern __shared__ __align__(16) char sm[];
@@ -301,8 +304,13 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
 #pragma unroll
     for (int q = 0; q < LY::XB / 4096; ++q) {
       const int i = wv + 4 * q;
-      const char* gb = Xa + ((size_t)(k0 + (XC ? 2 * i : 4 * i)) * B + b0) * XE;
-      lds_dma16(gb + xoff_l, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
+      if (PRE) {
+        const char* gb = (const char*)X + (((size_t)(x_shared ? 0 : a) * ncb + cb) * nch + it) * LY::XB + i * 1024;
+        lds_dma16(gb + 16 * lane, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
+      } else {
+        const char* gb = Xa + ((size_t)(k0 + (XC ? 2 * i : 4 * i)) * B + b0) * XE;
+        lds_dma16(gb + xoff_l, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
+      }
     }
   };
 
@@ -339,6 +347,14 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
       split_h(v.w * kStackScale, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
     }
     shortx8 bxrh[2], bxrl[2], bxih[2], bxil[2];
+    if (PRE) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const char* xb = st + LY::QB + ((ks * 2 + c) * 2) * 1024 + 16 * lane;
+        bxrh[c] = *(const shortx8*)xb;
+        bxrl[c] = *(const shortx8*)(xb + 1024);
+      }
+    } else
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int col = 32 * c + l32;
@@ -395,6 +411,50 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
   }
 }
 
+// ---------------------------------------------------------------- signals split once
+// One thread per (order, column block, k chunk, ks, c, lane): 8 values of column
+// 64 cb + 32 c + l32 at k = 32 chunk + 16 ks + 8 lh .. + 7, scaled by the column's power of two
+// (exact) and split into fp16 hi / lo; 2 KB per (ks, c) pair of one k chunk (hi then lo).
+__global__ __launch_bounds__(256) void k_xsplit(const float* __restrict__ X, int ldx, int ncols, int N, int ncb,
+                                                size_t xstride, const float2* __restrict__ xs, int xs_stride,
+                                                short* __restrict__ Xs) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int nch = N / 32, a = blockIdx.y;
+  if (idx >= (size_t)ncb * nch * 256) return;
+  const int lane = (int)(idx & 63), c = (int)((idx >> 6) & 1), ks = (int)((idx >> 7) & 1);
+  const size_t bc = idx >> 8;                        // cb * nch + chunk
+  const int chunk = (int)(bc % nch), cb = (int)(bc / nch);
+  const int col = cb * 64 + 32 * c + (lane & 31);
+  const int k0 = chunk * 32 + 16 * ks + 8 * (lane >> 5);
+  const float* Xa = X + (size_t)a * xstride;
+  const float sc = col < ncols ? xs[(size_t)a * xs_stride + col].x : 0.f;
+  shortx8 h, l;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float v = col < ncols ? Xa[(size_t)(k0 + j) * ldx + col] * sc : 0.f;
+    short hh, ll;
+    split_h(v, hh, ll);
+    h[j] = hh;
+    l[j] = ll;
+  }
+  shortx8* dst = (shortx8*)(Xs + ((((size_t)a * ncb * nch + bc) * 2 + ks) * 2 + c) * 2 * 64 * 8);
+  dst[lane] = h;
+  dst[64 + lane] = l;
+}
+
+size_t xsplit_bytes(int N, int nx, int ncols) {
+  return align_up((size_t)nx * ceil_div(ncols, 64) * (N / 32) * 8192, 256);
+}
+
+fgfrft_status xsplit_launch(const float* X, int ldx, int ncols, int N, int nx, size_t xstride, const float2* xs,
+                            int xs_stride, short* Xs, hipStream_t s) {
+  const size_t n = (size_t)ceil_div(ncols, 64) * (N / 32) * 256;
+  k_xsplit<<<dim3((unsigned)((n + 255) / 256), nx), 256, 0, s>>>(X, ldx, ncols, N, ceil_div(ncols, 64), xstride, xs,
+                                                                  xs_stride, Xs);
+  FG_LAUNCHED("signal split");
+  return FGFRFT_OK;
+}
+
 size_t colscale_partial_bytes(int N, int nx, int B) { return align_up((size_t)nx * ceil_div(N, CR) * B * sizeof(float), 256); }
 
 fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx, float2* scale, float* partial,
@@ -406,9 +466,17 @@ fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx
   return FGFRFT_OK;
 }
 
+// Pre-split signals pay when the same signals are split by many workgroups: a block shared by
+// every order, or many signals per order (each Q row block re-splits them once per 64 columns).
+static bool apply_presplit(int N, int B, int x_complex, int x_shared) {
+  return !x_complex && N % 32 == 0 && B % 64 == 0 && (x_shared || B >= 256);
+}
+
 size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared) {
   const size_t nx = x_shared ? 1 : n_alpha;
-  return align_up(nx * B * sizeof(float2), 256) + colscale_partial_bytes(N, (int)nx, B);
+  size_t b = align_up(nx * B * sizeof(float2), 256) + colscale_partial_bytes(N, (int)nx, B);
+  if (apply_presplit(N, B, 0, x_shared)) b += xsplit_bytes(N, (int)nx, B);   // real signals only
+  return b;
 }
 
 template <bool ADJ, bool XC, bool YR>
@@ -417,18 +485,20 @@ static void launch_apply_t(dim3 g, hipStream_t s, const cplx64* Q, int N, int n_
   k_apply<ADJ, XC, YR><<<g, 256, 0, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
-template <bool XC, bool YR, int NS, int K2>
+template <bool XC, bool YR, int NS, int K2, bool PRE = false>
 static void launch_apply2_t(unsigned g, hipStream_t s, const cplx64* Q, int N, int n_alpha, const void* X, int x_shared,
                             int B, const float2* sc, void* Y, int nrb, int ncb) {
   constexpr int lds = NS * Apply2Layout<XC, K2>::SB;
   static_assert(lds <= 80 * 1024, "two workgroups per CU");
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_apply2<XC, YR, NS, K2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_apply2<XC, YR, NS, K2, PRE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds);
     attr_set = true;
   }
-  k_apply2<XC, YR, NS, K2><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
+  k_apply2<XC, YR, NS, K2, PRE><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
+
 
 fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex, int x_shared,
                            int B, void* Y, int y_real, void* ws, hipStream_t s) {
@@ -437,6 +507,12 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
   float* partial = (float*)((char*)ws + align_up((size_t)nx * B * sizeof(float2), 256));
   fgfrft_status rc = colscale_launch(X, x_complex, N, B, nx, sc, partial, s);
   if (rc) return rc;
+  const bool pre = !adjoint && apply_presplit(N, B, x_complex, x_shared);
+  short* Xs = (short*)((char*)partial + colscale_partial_bytes(N, nx, B));
+  if (pre) {
+    rc = xsplit_launch((const float*)X, B, B, N, nx, x_shared ? 0 : (size_t)N * B, sc, B, Xs, s);
+    if (rc) return rc;
+  }
   // streaming kernel: k stages of 32 (real signals, 2-stage ring) or 16 (complex, 3-stage ring)
   if (!adjoint && N % (x_complex ? 16 : 32) == 0 && B % 64 == 0) {
     const int nrb = ceil_div(N, M2), ncb = B / 64;
@@ -447,6 +523,12 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
     }
     const cplx64* q = (const cplx64*)Q;
     const int key = (x_complex ? 2 : 0) | (y_real ? 1 : 0);
+    if (pre) {
+      if (y_real) launch_apply2_t<false, true, 2, 32, true>((unsigned)nblocks, s, q, N, n_alpha, Xs, x_shared, B, sc, Y, nrb, ncb);
+      else launch_apply2_t<false, false, 2, 32, true>((unsigned)nblocks, s, q, N, n_alpha, Xs, x_shared, B, sc, Y, nrb, ncb);
+      FG_LAUNCHED("apply");
+      return FGFRFT_OK;
+    }
     switch (key) {
       case 0: launch_apply2_t<false, false, 2, 32>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
       case 1: launch_apply2_t<false, true, 2, 32>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;

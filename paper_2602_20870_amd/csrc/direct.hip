@@ -6,7 +6,8 @@
 // term is a per-column scalar.
 //
 // Matrix-core kernel (real F, FP32 stack, real X, N % 32 == 0): the signals are split once into
-// fp16 hi/lo (after a power-of-two scale per column) in the order the matrix cores read them.  A
+// fp16 hi/lo (after a power-of-two scale per column) in the order the matrix cores read them
+// (xsplit_launch, shared with the apply).  A
 // workgroup owns 128 output rows x 64 columns and a contiguous run of the (2L + 1) x N/32 stages
 // (term, 32-wide k chunk) of that tile; the runs are balanced so the whole grid is one round of
 // resident workgroups (three per CU) when the tile count allows.  Stack and signal tiles stream from HBM into
@@ -80,36 +81,6 @@ __device__ __forceinline__ void dsplit(float v, short& hi, short& lo) {
 }
 __device__ __forceinline__ floatx16 dmma(shortx8 a, shortx8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0, 0, 0);
-}
-
-// Signals split once: Xs[cb][chunk][ks][c][part][lane][8] halves for column block cb (64 columns),
-// k chunk of 32, k step ks of 16, column half c, part hi / lo: lane (l32, lh) of the matrix-core
-// B operand holds column 64 cb + 32 c + l32, k = 32 chunk + 16 ks + 8 lh .. + 7.  Each column is
-// scaled by its power of two s first (exact), so hi + lo keeps ~22 bits of every entry.
-// Columns >= ncols are zero.  One thread per (cb, chunk, ks, c, lane).
-__global__ __launch_bounds__(256) void k_xsplit(const float* __restrict__ X, int ldx, int ncols, int N, int ncb,
-                                                const float2* __restrict__ xs, short* __restrict__ Xs) {
-  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const int nch = N / DK;
-  if (idx >= (size_t)ncb * nch * 4 * 64) return;
-  const int lane = (int)(idx & 63), c = (int)((idx >> 6) & 1), ks = (int)((idx >> 7) & 1);
-  const size_t bc = idx >> 8;                        // cb * nch + chunk
-  const int chunk = (int)(bc % nch), cb = (int)(bc / nch);
-  const int col = cb * 64 + 32 * c + (lane & 31);
-  const int k0 = chunk * DK + 16 * ks + 8 * (lane >> 5);
-  shortx8 h, l;
-  const float sc = col < ncols ? xs[col].x : 0.f;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float v = col < ncols ? X[(size_t)(k0 + j) * ldx + col] * sc : 0.f;
-    short a, b;
-    dsplit(v, a, b);
-    h[j] = a;
-    l[j] = b;
-  }
-  shortx8* dst = (shortx8*)(Xs + ((((bc * 2 + ks) * 2 + c) * 2) * 64) * 8);
-  dst[lane] = h;
-  dst[64 + lane] = l;
 }
 
 // Grid: 8 * ceil(nIB * G / 8) * ncb workgroups; workgroup (row block ib, run g, column block cb)
@@ -435,9 +406,9 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
   if (rc) return rc;
   k_dcoef<<<ceil_div(nrow * d.ncp, 256), 256, 0, s>>>(alphas_dev, n_alpha, col_order_dev, ncols, d.ncp, L, w.xs,
                                                         kStackScale, w.gam);
-  const size_t nsplit = (size_t)d.ncb * d.nch * 256;
-  k_xsplit<<<(unsigned)((nsplit + 255) / 256), 256, 0, s>>>((const float*)X, ldx, ncols, N, d.ncb, w.xs, w.Xs);
-  FG_LAUNCHED("direct coefficients / signal split");
+  FG_LAUNCHED("direct coefficients");
+  rc = xsplit_launch((const float*)X, ldx, ncols, N, 1, 0, w.xs, 0, w.Xs, s);
+  if (rc) return rc;
   const size_t nblocks = (size_t)8 * ceil_div(d.nIB * d.G, 8) * d.ncb;
   if (nblocks > 0x7fffffff) {
     set_error("direct grid too large");

@@ -4,8 +4,9 @@ on sampled outputs the FP64 oracle computes row by row.
 * knn4096: N = 4096, L = 32, one update launch of 256 orders (34 GB of Q), then one apply
   launch to 64 real signals per order, as in the benchmark step.
 * grid8192 (precision form): N = 8192, L = 64, one update launch of a 32-order chunk for the
-  FP32 stack and for the BF16 hi/lo stack; per-order errors against the oracle are printed
-  (and written as JSON to $FGFRFT_REPORT_DIR when that is set).
+  FP32 stack and for the BF16 hi/lo stack, and the apply of the FP32 operators to one shared
+  block of 1024 real signals; per-order errors against the oracle are printed (and written as
+  JSON to $FGFRFT_REPORT_DIR when that is set).
 
 The oracle's rows come from the row/column power recurrences of the stack (no N x N FP64
 stack is formed) and its projector from the symmetric-part route for real orthogonal F.
@@ -103,7 +104,7 @@ def test_knn4096_bench_launch_sampled_rows():
 @pytest.mark.timeout(900)
 def test_grid8192_precision_forms_sampled_rows():
     torch = torch_cuda()
-    from paper_2602_20870_amd import Plan
+    from paper_2602_20870_amd import Plan, apply_operator
     t0 = time.time()
     announce("grid8192: building F (128x64 grid, lognormal weights, N=8192)")
     cfg = synth.make_config("grid8192", seed=0, with_signals=False)
@@ -112,6 +113,7 @@ def test_grid8192_precision_forms_sampled_rows():
     chunk[:4] = [0.0, 1.0, -1.0, 0.5]
     rows = _rows(N, 2)
     Ft = torch.from_numpy(F).cuda()
+    Xs = synth.real_signals((N, 1024), synth.streams(0, 3)[2]).astype(np.float32)   # one shared block
     got = {}
     for st in ("fp32", "bf16x2"):
         announce(f"grid8192: GPU plan ({st}) + one 32-order update launch [{time.time() - t0:.0f}s]")
@@ -119,6 +121,10 @@ def test_grid8192_precision_forms_sampled_rows():
         Q = plan.update(chunk)
         torch.cuda.synchronize()
         got[st] = (_sample_rows(torch, Q, range(32), rows), plan.r_minus1)
+        if st == "fp32":   # the apply of the 32 operators to 1024 shared signals (pre-split signals)
+            Y = apply_operator(Q, torch.from_numpy(Xs).cuda())
+            Yrows = _sample_rows(torch, Y, range(32), rows)
+            del Y
         del Q, plan
         torch.cuda.empty_cache()
     del Ft
@@ -134,4 +140,9 @@ def test_grid8192_precision_forms_sampled_rows():
         report[st] = errs
         announce(f"grid8192 {st}: worst row error {max(errs):.2e}, median {np.median(errs):.2e}")
         assert max(errs) <= tol, (st, errs)
+    X64 = Xs.astype(np.float64)
+    errs_y = [rel_fro(Yrows[i], ref[i] @ X64) for i in range(32)]
+    report["apply_1024_shared_fp32"] = errs_y
+    announce(f"grid8192 apply to 1024 shared signals: worst row error {max(errs_y):.2e}")
+    assert max(errs_y) <= TOL_FP32, errs_y
     _report("grid8192_precision.json", report)

@@ -170,7 +170,9 @@ def test_update_rejects_out_of_range_orders():
 # apply (a-3)
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("xc,shared,N,B", [(False, False, 64, 32), (True, False, 80, 37), (False, True, 50, 5),
-                                           (True, True, 130, 70)])
+                                           (True, True, 130, 70),
+                                           (False, True, 96, 128),      # pre-split signals: shared block
+                                           (False, False, 160, 256)])   # pre-split signals: wide blocks
 def test_apply_against_oracle(xc, shared, N, B):
     torch = torch_cuda()
     announce(f"apply xc={xc} shared={shared} N={N} B={B}")
