@@ -245,6 +245,13 @@ def precision_form_bench(chunks=(32, 128), reps=3):
             out["forms"].append(row)
             del Q
             torch.cuda.empty_cache()
+        # the direct route on the same plan: 32 orders x 2 signals (64 columns, no operator formed)
+        ms = direct_call_ms(plan, alphas[:32], 2, dev)
+        alg = direct_algorithmic_bytes(N, L, 64)
+        row = {"stacktype": st, "direct_orders": 32, "direct_columns": 64, "direct_ms": ms,
+               "direct_algorithmic_GBps": alg / (ms * 1e-3) / 1e9}
+        log(f"precision form {row}")
+        out["forms"].append(row)
         del plan
         torch.cuda.empty_cache()
     return out

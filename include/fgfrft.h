@@ -203,10 +203,11 @@ FGFRFT_API size_t fgfrft_apply_direct_workspace_bytes(fgfrft_plan_t plan, int nc
  *   (x_complex = 1); Y_dev: complex64 [N][ldy].  ncols <= ldx, ncols <= ldy.
  * Orders are device data and are not range-checked on the host: a column whose order
  * index is out of range, or whose order has |alpha| >= L or is not finite, is filled
- * with NaN.  Real F with an FP32 stack, real X and N % 32 == 0 take the matrix-core
- * kernel (split fp16 operands, FP32 products folded into FP64 sums per 32-wide k
- * chunk); every other case takes a plain FP64-accumulating kernel.  The call only
- * enqueues work on `stream` (no host synchronisation; capturable). */
+ * with NaN.  Real F, real X and N % 32 == 0 take the matrix-core kernel (FP32 stack:
+ * split fp16 operands; BF16X2 stack: its bf16 pairs with bf16-split signals; FP32
+ * products of each term folded into FP64 sums); every other case takes a plain
+ * FP64-accumulating kernel.  The call only enqueues work on `stream` (no host
+ * synchronisation; capturable). */
 FGFRFT_API fgfrft_status fgfrft_apply_direct(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha,
                                              const int* col_order_dev, const void* X_dev, int x_complex,
                                              int ncols, int ldx, void* Y_dev, int ldy, void* ws_dev,

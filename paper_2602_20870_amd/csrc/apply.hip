@@ -414,7 +414,9 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
 // ---------------------------------------------------------------- signals split once
 // One thread per (order, column block, k chunk, ks, c, lane): 8 values of column
 // 64 cb + 32 c + l32 at k = 32 chunk + 16 ks + 8 lh .. + 7, scaled by the column's power of two
-// (exact) and split into fp16 hi / lo; 2 KB per (ks, c) pair of one k chunk (hi then lo).
+// (exact) and split into fp16 hi / lo (or bf16 hi / lo); 2 KB per (ks, c) pair of one k chunk
+// (hi then lo).
+template <bool BF>
 __global__ __launch_bounds__(256) void k_xsplit(const float* __restrict__ X, int ldx, int ncols, int N, int ncb,
                                                 size_t xstride, const float2* __restrict__ xs, int xs_stride,
                                                 short* __restrict__ Xs) {
@@ -433,7 +435,14 @@ __global__ __launch_bounds__(256) void k_xsplit(const float* __restrict__ X, int
   for (int j = 0; j < 8; ++j) {
     const float v = col < ncols ? Xa[(size_t)(k0 + j) * ldx + col] * sc : 0.f;
     short hh, ll;
-    split_h(v, hh, ll);
+    if (BF) {
+      const __bf16 bh = (__bf16)v;
+      const __bf16 bl = (__bf16)(v - (float)bh);
+      hh = __builtin_bit_cast(short, bh);
+      ll = __builtin_bit_cast(short, bl);
+    } else {
+      split_h(v, hh, ll);
+    }
     h[j] = hh;
     l[j] = ll;
   }
@@ -447,10 +456,11 @@ size_t xsplit_bytes(int N, int nx, int ncols) {
 }
 
 fgfrft_status xsplit_launch(const float* X, int ldx, int ncols, int N, int nx, size_t xstride, const float2* xs,
-                            int xs_stride, short* Xs, hipStream_t s) {
+                            int xs_stride, short* Xs, hipStream_t s, bool bf16) {
   const size_t n = (size_t)ceil_div(ncols, 64) * (N / 32) * 256;
-  k_xsplit<<<dim3((unsigned)((n + 255) / 256), nx), 256, 0, s>>>(X, ldx, ncols, N, ceil_div(ncols, 64), xstride, xs,
-                                                                  xs_stride, Xs);
+  const dim3 g((unsigned)((n + 255) / 256), nx);
+  if (bf16) k_xsplit<true><<<g, 256, 0, s>>>(X, ldx, ncols, N, ceil_div(ncols, 64), xstride, xs, xs_stride, Xs);
+  else k_xsplit<false><<<g, 256, 0, s>>>(X, ldx, ncols, N, ceil_div(ncols, 64), xstride, xs, xs_stride, Xs);
   FG_LAUNCHED("signal split");
   return FGFRFT_OK;
 }

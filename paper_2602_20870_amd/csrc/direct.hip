@@ -18,7 +18,8 @@
 // cos(pi alpha) - c_0 and into the imaginary part with sin(pi alpha).  Runs write partial sums
 // that a second kernel adds in a fixed order (deterministic), with the identity term c_0 X.
 //
-// Every other configuration (complex F, BF16X2 stack, complex X, N % 32 != 0) takes a plain
+// A BF16X2 stack (a packed bf16 hi / lo pair per entry) feeds the bf16 matrix cores directly with
+// bf16-split signals.  Every other configuration (complex F, complex X, N % 32 != 0) takes a plain
 // kernel with one thread per output and FP64 accumulation.
 #include "internal.h"
 #include <math.h>
@@ -79,8 +80,19 @@ __device__ __forceinline__ void dsplit(float v, short& hi, short& lo) {
   hi = __builtin_bit_cast(short, h);
   lo = __builtin_bit_cast(short, l);
 }
+template <bool BF>
 __device__ __forceinline__ floatx16 dmma(shortx8 a, shortx8 b, floatx16 c) {
+  if (BF)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0, 0, 0);
+}
+
+// bf16 hi / lo of an FP32 value (the projector of a BF16X2 plan is kept in FP32)
+__device__ __forceinline__ void bsplit(float v, short& hi, short& lo) {
+  const __bf16 h = (__bf16)v;
+  const __bf16 l = (__bf16)(v - (float)h);
+  hi = __builtin_bit_cast(short, h);
+  lo = __builtin_bit_cast(short, l);
 }
 
 // Grid: 8 * ceil(nIB * G / 8) * ncb workgroups; workgroup (row block ib, run g, column block cb)
@@ -88,7 +100,9 @@ __device__ __forceinline__ floatx16 dmma(shortx8 a, shortx8 b, floatx16 c) {
 // st % nch).  Ids are dealt round-robin over the 8 XCDs; the column blocks of one (row block,
 // run) get consecutive ids on one XCD, so a stack tile read for one column block is an L2 hit for
 // the others.  part_re, part_im: [G][N][ncp]; part_im is written only by runs that reach P.
-template <int DNS>
+// BF: BF16X2 stack (each real entry a packed bf16 pair, hi in the low half), bf16 matrix cores,
+// unscaled operands; the P stages split their FP32 tiles into bf16 hi / lo.
+template <int DNS, bool BF>
 __global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float* __restrict__ stack, const float* __restrict__ P, int N,
                                                    int L, const short* __restrict__ Xs, int ncp,
                                                    const float* __restrict__ gam, int SPW, int G, int nIB, int ncb,
@@ -165,23 +179,37 @@ __global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float
     for (int ks = 0; ks < DK / 16; ++ks) {
       // A: S_t[i0 + r][k0 + 16 ks + 8 lh .. + 7], two 16-byte chunks, split after the 2^12 scale
       shortx8 ah, al;
+      const bool pstage = BF && (s0 + it) / nch == 2 * L;      // wave-uniform
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int ch = (4 * ks + 2 * lh + q) ^ (r & 7);
         const float4 v = *(const float4*)(st + r * (DK * 4) + ch * 16);
         short h, l;
-        dsplit(v.x * kStackScale, h, l); ah[4 * q + 0] = h; al[4 * q + 0] = l;
-        dsplit(v.y * kStackScale, h, l); ah[4 * q + 1] = h; al[4 * q + 1] = l;
-        dsplit(v.z * kStackScale, h, l); ah[4 * q + 2] = h; al[4 * q + 2] = l;
-        dsplit(v.w * kStackScale, h, l); ah[4 * q + 3] = h; al[4 * q + 3] = l;
+        if (BF && !pstage) {
+          const uint4 w = __builtin_bit_cast(uint4, v);
+          ah[4 * q + 0] = (short)(w.x & 0xffff); al[4 * q + 0] = (short)(w.x >> 16);
+          ah[4 * q + 1] = (short)(w.y & 0xffff); al[4 * q + 1] = (short)(w.y >> 16);
+          ah[4 * q + 2] = (short)(w.z & 0xffff); al[4 * q + 2] = (short)(w.z >> 16);
+          ah[4 * q + 3] = (short)(w.w & 0xffff); al[4 * q + 3] = (short)(w.w >> 16);
+        } else if (BF) {
+          bsplit(v.x, h, l); ah[4 * q + 0] = h; al[4 * q + 0] = l;
+          bsplit(v.y, h, l); ah[4 * q + 1] = h; al[4 * q + 1] = l;
+          bsplit(v.z, h, l); ah[4 * q + 2] = h; al[4 * q + 2] = l;
+          bsplit(v.w, h, l); ah[4 * q + 3] = h; al[4 * q + 3] = l;
+        } else {
+          dsplit(v.x * kStackScale, h, l); ah[4 * q + 0] = h; al[4 * q + 0] = l;
+          dsplit(v.y * kStackScale, h, l); ah[4 * q + 1] = h; al[4 * q + 1] = l;
+          dsplit(v.z * kStackScale, h, l); ah[4 * q + 2] = h; al[4 * q + 2] = l;
+          dsplit(v.w * kStackScale, h, l); ah[4 * q + 3] = h; al[4 * q + 3] = l;
+        }
       }
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const char* xb = st + DAB + ((ks * 2 + c) * 2) * 1024 + 16 * lane;
         const shortx8 bh = *(const shortx8*)xb, bl = *(const shortx8*)(xb + 1024);
-        acc[c] = dmma(ah, bh, acc[c]);
-        acc[c] = dmma(ah, bl, acc[c]);
-        acc[c] = dmma(al, bh, acc[c]);
+        acc[c] = dmma<BF>(ah, bh, acc[c]);
+        acc[c] = dmma<BF>(ah, bl, acc[c]);
+        acc[c] = dmma<BF>(al, bh, acc[c]);
       }
     }
     const int gs = s0 + it;
@@ -382,7 +410,8 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
   const int N = p->N, L = p->L;
   const DirectGrid d = direct_grid(N, L, ncols);
   const DirectWs w = direct_ws(p, ncols, ldx, ws);
-  const bool fast = !p->cplx && p->stacktype == FGFRFT_STACK_FP32 && !x_complex && N % DK == 0;
+  const bool bf = p->stacktype == FGFRFT_STACK_BF16X2;
+  const bool fast = !p->cplx && !x_complex && N % DK == 0;
   const int nrow = 2 * L + 4;
   if (!fast) {
     k_dcoef<<<ceil_div(nrow * d.ncp, 256), 256, 0, s>>>(alphas_dev, n_alpha, col_order_dev, ncols, d.ncp, L, nullptr,
@@ -405,9 +434,9 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
   fgfrft_status rc = colscale_launch(X, 0, N, ldx, 1, w.xs, w.colpart, s);
   if (rc) return rc;
   k_dcoef<<<ceil_div(nrow * d.ncp, 256), 256, 0, s>>>(alphas_dev, n_alpha, col_order_dev, ncols, d.ncp, L, w.xs,
-                                                        kStackScale, w.gam);
+                                                        bf ? 1.0f : kStackScale, w.gam);
   FG_LAUNCHED("direct coefficients");
-  rc = xsplit_launch((const float*)X, ldx, ncols, N, 1, 0, w.xs, 0, w.Xs, s);
+  rc = xsplit_launch((const float*)X, ldx, ncols, N, 1, 0, w.xs, 0, w.Xs, s, bf);
   if (rc) return rc;
   const size_t nblocks = (size_t)8 * ceil_div(d.nIB * d.G, 8) * d.ncb;
   if (nblocks > 0x7fffffff) {
@@ -416,12 +445,15 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
   }
   static bool attr_set = false;
   if (!attr_set) {
-    FG_HIP(hipFuncSetAttribute((const void*)k_direct<kDirectNS>, hipFuncAttributeMaxDynamicSharedMemorySize, DCfg::LDS));
+    FG_HIP(hipFuncSetAttribute((const void*)k_direct<kDirectNS, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               DCfg::LDS));
+    FG_HIP(hipFuncSetAttribute((const void*)k_direct<kDirectNS, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               DCfg::LDS));
     attr_set = true;
   }
-  k_direct<kDirectNS><<<(unsigned)nblocks, 256, DCfg::LDS, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs,
-                                                                d.ncp, w.gam, d.SPW, d.G, d.nIB, d.ncb, w.part_re,
-                                                                w.part_im);
+  auto kern = bf ? k_direct<kDirectNS, true> : k_direct<kDirectNS, false>;
+  kern<<<(unsigned)nblocks, 256, DCfg::LDS, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs, d.ncp, w.gam,
+                                                 d.SPW, d.G, d.nIB, d.ncb, w.part_re, w.part_im);
   FG_LAUNCHED("direct");
   const size_t n = (size_t)N * ncols;
   k_direct_reduce<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.part_re, w.part_im, d.G, d.gP, N, d.ncp, ncols, L,

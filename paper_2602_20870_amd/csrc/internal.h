@@ -113,10 +113,10 @@ fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx
 // Signals split once for the matrix cores (apply.hip): real X [nx][N][ldx] (order stride xstride
 // floats, 0 = one block for all), columns scaled by xs[a * xs_stride + col].x, written as
 // Xs[a][cb][chunk][ks][c][part][lane][8] fp16 (64-column blocks, 32-wide k chunks, N % 32 == 0;
-// columns >= ncols are zero): xsplit_bytes(N, nx, ncols) bytes.
+// columns >= ncols are zero; bf16 = true: bf16 hi / lo parts): xsplit_bytes(N, nx, ncols) bytes.
 size_t xsplit_bytes(int N, int nx, int ncols);
 fgfrft_status xsplit_launch(const float* X, int ldx, int ncols, int N, int nx, size_t xstride, const float2* xs,
-                            int xs_stride, short* Xs, hipStream_t s);
+                            int xs_stride, short* Xs, hipStream_t s, bool bf16 = false);
 
 // Direct route (direct.hip)
 size_t direct_ws_bytes(const Plan* p, int ncols, int ldx);

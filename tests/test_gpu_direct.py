@@ -94,11 +94,15 @@ def test_direct_agrees_with_update_then_apply():
         assert rel_fro(Y2[a], Y1[a]) <= 2 * TOL_FP32, a
 
 
-@pytest.mark.parametrize("case", ["dft64_complex_x", "haar96_real_x", "real_n70", "real_f_complex_x", "bf16x2"])
-def test_direct_plain_paths(case):
+@pytest.mark.parametrize("case", ["dft64_complex_x", "haar96_real_x", "real_n70", "real_f_complex_x", "bf16x2",
+                                  "bf16x2_n70"])
+def test_direct_other_configurations(case):
+    """Complex F, complex signals and N % 32 != 0 take the plain kernel; a BF16X2 stack with
+    N % 32 == 0 takes the bf16 matrix-core kernel, with N = 70 the plain one."""
     torch = torch_cuda()
     announce(f"direct plain kernel: {case}")
-    seeds = {"dft64_complex_x": 21, "haar96_real_x": 22, "real_n70": 23, "real_f_complex_x": 24, "bf16x2": 25}
+    seeds = {"dft64_complex_x": 21, "haar96_real_x": 22, "real_n70": 23, "real_f_complex_x": 24, "bf16x2": 25,
+             "bf16x2_n70": 26}
     rng = np.random.default_rng(seeds[case])
     stacktype, tol, L = "fp32", TOL_FP32, 10
     if case == "dft64_complex_x":
@@ -114,8 +118,10 @@ def test_direct_plain_paths(case):
         F = synth.make_config("knn4096", seed=6, N=96, with_signals=False)["F"]
         X = synth.complex_signals((96, 11), rng)
     else:
-        F = synth.make_config("knn4096", seed=7, N=128, with_signals=False)["F"]
-        X = synth.real_signals((128, 40), rng)
+        n = 128 if case == "bf16x2" else 70
+        F = synth.make_config("knn4096", seed=7, N=n, with_signals=False)["F"]
+        X = synth.real_signals((n, 40), rng)
+        X[:, ::4] *= 1e3
         stacktype, tol, L = "bf16x2", TOL_BF16X2, 16
     alphas = rng.uniform(-2, 2, 4)
     cols = _columns(rng, 4, [1, 2, 3, X.shape[1] - 6])

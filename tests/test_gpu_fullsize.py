@@ -4,8 +4,8 @@ on sampled outputs the FP64 oracle computes row by row.
 * knn4096: N = 4096, L = 32, one update launch of 256 orders (34 GB of Q), then one apply
   launch to 64 real signals per order, as in the benchmark step.
 * grid8192 (precision form): N = 8192, L = 64, one update launch of a 32-order chunk for the
-  FP32 stack and for the BF16 hi/lo stack, and the apply of the FP32 operators to one shared
-  block of 1024 real signals; per-order errors against the oracle are printed (and written as
+  FP32 stack and for the BF16 hi/lo stack, the direct route on both (32 orders x 2 signals),
+  and the apply of the FP32 operators to one shared block of 1024 real signals; per-order errors against the oracle are printed (and written as
   JSON to $FGFRFT_REPORT_DIR when that is set).
 
 The oracle's rows come from the row/column power recurrences of the stack (no N x N FP64
@@ -121,6 +121,11 @@ def test_grid8192_precision_forms_sampled_rows():
         Q = plan.update(chunk)
         torch.cuda.synchronize()
         got[st] = (_sample_rows(torch, Q, range(32), rows), plan.r_minus1)
+        # the direct route on the same plan: the 32 orders with two of the shared signals each
+        Yd = plan.apply_direct(chunk, np.repeat(np.arange(32, dtype=np.int32), 2),
+                               torch.from_numpy(np.ascontiguousarray(Xs[:, :64])).cuda())
+        got[st + "_direct"] = Yd[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        del Yd
         if st == "fp32":   # the apply of the 32 operators to 1024 shared signals (pre-split signals)
             Y = apply_operator(Q, torch.from_numpy(Xs).cuda())
             Yrows = _sample_rows(torch, Y, range(32), rows)
@@ -141,6 +146,12 @@ def test_grid8192_precision_forms_sampled_rows():
         announce(f"grid8192 {st}: worst row error {max(errs):.2e}, median {np.median(errs):.2e}")
         assert max(errs) <= tol, (st, errs)
     X64 = Xs.astype(np.float64)
+    for st, tol in (("fp32", TOL_FP32), ("bf16x2", TOL_BF16X2)):
+        Yd = got[st + "_direct"]
+        errs_d = [rel_fro(Yd[:, 2 * i: 2 * i + 2], ref[i] @ X64[:, 2 * i: 2 * i + 2]) for i in range(32)]
+        report[st + "_direct"] = errs_d
+        announce(f"grid8192 {st} direct route: worst row error {max(errs_d):.2e}")
+        assert max(errs_d) <= tol, (st, errs_d)
     errs_y = [rel_fro(Yrows[i], ref[i] @ X64) for i in range(32)]
     report["apply_1024_shared_fp32"] = errs_y
     announce(f"grid8192 apply to 1024 shared signals: worst row error {max(errs_y):.2e}")
