@@ -68,8 +68,11 @@ class _SlotSet:
         self.h_alphas = torch.zeros(K, dtype=torch.float64).pin_memory()
         self.h_X = torch.zeros((K, N, bmax), dtype=torch.float32).pin_memory()
         self.h_Y = torch.empty((K, N, bmax), dtype=torch.complex64).pin_memory()
-        # direct route: per block count nb, signals [N, 64 nb] side by side, column -> order index
-        self.dblocks = range(1, DIRECT_BLOCKS + 1) if route != "operator" else range(0)
+        # direct route: per block count nb, signals [N, 64 nb] side by side, column -> order index.
+        # Only plans the matrix-core direct kernel takes (real F, N % 32 == 0) offer it; the plain
+        # kernel of the other configurations is far slower than the operator route.
+        direct_ok = route != "operator" and not plan.complex and N % 32 == 0
+        self.dblocks = range(1, DIRECT_BLOCKS + 1) if direct_ok else range(0)
         self.dX = {nb: torch.zeros((N, 64 * nb), dtype=torch.float32, device=device) for nb in self.dblocks}
         self.dcols = {nb: torch.zeros(64 * nb, dtype=torch.int32, device=device) for nb in self.dblocks}
         self.dY = {nb: torch.empty((N, 64 * nb), dtype=torch.complex64, device=device) for nb in self.dblocks}
@@ -205,7 +208,8 @@ class Server:
     K: orders per batch (one fused update launch); bmax: largest signal block;
     slot_sets: batches of one plan that may be in flight at once;
     route: "auto" (per batch, prefer_direct), "operator" or "direct" (when the batch's
-    signals fit DIRECT_BLOCKS x 64 columns, else the operator route).
+    signals fit DIRECT_BLOCKS x 64 columns, else the operator route).  The direct route is
+    offered for plans of real F with N % 32 == 0 (the matrix-core direct kernel).
     """
 
     def __init__(self, hbm_budget: int, K: int = 16, bmax: int = 64, slot_sets: int = 2, use_graphs: bool = True,
@@ -228,7 +232,7 @@ class Server:
         pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
         lib().fgfrft_plan_bytes(N, L, 1, 0, ctypes.byref(pb), ctypes.byref(sb))
         per_set = self.K * N * N * 8 + self.K * N * self.bmax * (4 + 8)
-        if self.route != "operator":      # direct-route signal and result blocks (1..4 x 64 columns)
+        if self.route != "operator" and N % 32 == 0:      # direct-route blocks (1..4 x 64 columns)
             per_set += 10 * 64 * N * (4 + 8)
         return int(pb.value) + self.S * per_set
 
