@@ -22,7 +22,7 @@ constexpr int RS = 40;   // LDS row stride in 16-bit values (32 + 8 pad)
 // scale[(a, b)] = 2^e with max_i |X[a][i][b]| * 2^e in [2^13, 2^14); stored (s, 1/s).
 // Two passes: column maxima over chunks of CR rows (grid: (order, column block) x chunks),
 // then the maximum over chunks and the power of two (fixed order, no atomics).
-constexpr int CR = 256;
+constexpr int CR = 64;
 
 __global__ __launch_bounds__(256) void k_colmax(const void* __restrict__ X, int x_complex, int N, int B,
                                                 float* __restrict__ partial) {

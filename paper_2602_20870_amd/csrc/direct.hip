@@ -5,18 +5,11 @@
 // c_{-(t-L+1)} (t >= L).  Every signal column carries its own order, so the coefficient of a
 // term is a per-column scalar.
 //
-// Matrix-core kernel (real F, FP32 stack, real X, N % 32 == 0): the signals are split once into
-// fp16 hi/lo (after a power-of-two scale per column) in the order the matrix cores read them
-// (xsplit_launch, shared with the apply).  A
-// workgroup owns 128 output rows x 64 columns and a contiguous run of the (2L + 1) x N/32 stages
-// (term, 32-wide k chunk) of that tile; the runs are balanced so the whole grid is one round of
-// resident workgroups (three per CU) when the tile count allows.  Stack and signal tiles stream from HBM into
-// an LDS ring with direct loads; the products of one term (stack split into fp16 hi/lo when a
-// wave reads its fragments, hi*hi + hi*lo + lo*hi) accumulate in FP32 and are folded into an FP64
-// sum with the column's coefficient when the term ends, so no FP32 chain runs over more than the
-// N products of one term.  The P term's products fold twice: into the real part with
-// cos(pi alpha) - c_0 and into the imaginary part with sin(pi alpha).  Runs write partial sums
-// that a second kernel adds in a fixed order (deterministic), with the identity term c_0 X.
+// Matrix-core kernel (real F, real X, N % 32 == 0; `k_direct_pair` below): the signals are split
+// once into fp16 hi/lo (after a power-of-two scale per column) in the order the matrix cores read
+// them (xsplit_launch, shared with the apply); every resident tile M_n[I, J] feeds both M_n X
+// (rows I) and M_n^T X (rows J), so the stored adjoints are not read; partial sums of row blocks,
+// runs and waves are added in a fixed order by a second kernel, with the identity term c_0 X.
 //
 // A BF16X2 stack (a packed bf16 hi / lo pair per entry) feeds the bf16 matrix cores directly with
 // bf16-split signals.  Every other configuration (complex F, complex X, N % 32 != 0) takes a plain
@@ -31,15 +24,6 @@ constexpr int DK = 32;                           // k per ring stage
 constexpr int DAB = DM * DK * 4;                 // stack tile bytes per stage (16 KB)
 constexpr int DXB = DK * 64 * 4;                 // signal tile bytes per stage (8 KB: fp16 hi + lo)
 constexpr int DSB = DAB + DXB;
-constexpr int DLW = DAB / 4096 + DXB / 4096;     // direct loads per wave per stage
-// Ring of NS stages.  NS = 3: 80 KB of LDS, two workgroups per CU, runs touch up to 24 terms;
-// NS = 2: 53 KB, three workgroups per CU, up to 16 terms.
-template <int NS> struct DirectCfg {
-  static constexpr int TG = NS == 3 ? 24 : 16;              // terms one run may touch
-  static constexpr int LDS = NS * DSB + (TG + 1) * 64 * 4;
-  static constexpr int WPC = NS == 3 ? 2 : 3;               // workgroups per CU
-  static_assert(LDS * WPC <= 160 * 1024, "LDS budget");
-};
 
 // ---------------------------------------------------------------- coefficient table
 // Rows of ncp floats; for column c with order alpha and signal scale s (1 on the plain path):
@@ -95,18 +79,26 @@ __device__ __forceinline__ void bsplit(float v, short& hi, short& lo) {
   lo = __builtin_bit_cast(short, l);
 }
 
-// Grid: 8 * ceil(nIB * G / 8) * ncb workgroups; workgroup (row block ib, run g, column block cb)
-// takes stages [g SPW, min((g + 1) SPW, T nch)) of its tile, stage st = (term st / nch, k chunk
-// st % nch).  Ids are dealt round-robin over the 8 XCDs; the column blocks of one (row block,
-// run) get consecutive ids on one XCD, so a stack tile read for one column block is an L2 hit for
-// the others.  part_re, part_im: [G][N][ncp]; part_im is written only by runs that reach P.
-// BF: BF16X2 stack (each real entry a packed bf16 pair, hi in the low half), bf16 matrix cores,
-// unscaled operands; the P stages split their FP32 tiles into bf16 hi / lo.
-template <int DNS, bool BF>
-__global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float* __restrict__ stack, const float* __restrict__ P, int N,
-                                                   int L, const short* __restrict__ Xs, int ncp,
-                                                   const float* __restrict__ gam, int SPW, int G, int nIB, int ncb,
-                                                   float* __restrict__ part_re, float* __restrict__ part_im) {
+// ---------------------------------------------------------------- paired matrix-core kernel
+// Each resident tile M_n[I, J] serves both products that need it: M_n X for the output rows I and
+// M_n^T X (= M_n^H X, real F) for the output rows J, so the stored adjoint copies are never read
+// and the call streams L + 1 matrices (M_1..M_L, P) instead of 2L + 1.  A workgroup owns 128
+// output rows I (4 waves x 32), 64 columns and a run of CPR 32-wide chunks J; per chunk it walks
+// the L + 1 terms (stage = (chunk, term)).  Wave w's negative products sum over its own 32 rows
+// of I, with the signals of those rows held in registers (pre-split, loaded once).  Per stage:
+//   positive: acc = S_t[I, J] X[J]   -> FP32 sum over the run, coefficient c_{t+1} (P: cos - c_0,
+//             and sin for the imaginary part);
+//   negative: acc = S_t[I_w, J]^T X[I_w] -> FP32 sum over the chunk's terms, coefficient
+//             c_{-(t+1)}; written as a partial of rows J when the chunk's terms are done.
+// Partials: pos / im [G][N][ncp] (runs), neg [nIB][N][ncp] (row blocks; the waves' parts are
+// added in LDS first).
+template <bool BF>
+__global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict__ stack, const float* __restrict__ P,
+                                                        int N, int L, const short* __restrict__ Xs, int ncp,
+                                                        const float* __restrict__ gam, int CPR, int G, int nIB,
+                                                        int ncb, float* __restrict__ part_pos,
+                                                        float* __restrict__ part_im, float* __restrict__ part_neg) {
+  constexpr int NS = 2;
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
@@ -115,82 +107,87 @@ __global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float
   if (w >= nIB * G) return;
   const int ib = w % nIB, g = w / nIB;
   const int i0 = ib * DM, b0 = cb * 64;
-  const int T = 2 * L + 1, nch = N / DK;
-  const int s0 = g * SPW;
-  const int s1 = s0 + SPW < T * nch ? s0 + SPW : T * nch;
-  const int nst = s1 - s0;
-  const int tfirst = s0 / nch, nterm = (s1 - 1) / nch - tfirst + 1;
-  const bool hasP = s1 > 2 * L * nch;
+  const int nch = N / DK, T1 = L + 1;
+  const int cfirst = g * CPR, clast = cfirst + CPR < nch ? cfirst + CPR : nch;
+  const int nst = (clast - cfirst) * T1;
 
-  // coefficients of the terms this run touches for the 64 columns (row nterm: the sin row of P)
-  float* gl = (float*)(sm + DNS * DSB);
-  for (int e = tid; e < (nterm + 1) * 64; e += 256) {
-    const int tl = e >> 6, col = e & 63;
-    const int row = tl < nterm ? tfirst + tl : (hasP ? T : -1);
-    gl[e] = row >= 0 ? gam[(size_t)row * ncp + b0 + col] : 0.f;
-  }
+  // all coefficient rows (2L + 2) for the 64 columns
+  float* gl = (float*)(sm + NS * DSB);
+  for (int e = tid; e < (2 * L + 2) * 64; e += 256) gl[e] = gam[(size_t)(e >> 6) * ncp + b0 + (e & 63)];
+
+  // signals of this wave's 32 rows of I (the k range of its negative products), pre-split: chunk
+  // i0 / 32 + wave of the column block; zero past N
+  const char* xsb = (const char*)Xs + (size_t)cb * nch * DXB;
+  const int ich = i0 / DK + wave;
+  shortx8 xih[2][2], xil[2][2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (ich < nch) {
+        const shortx8* src = (const shortx8*)(xsb + (size_t)ich * DXB + ((ks * 2 + c) * 2) * 1024);
+        xih[ks][c] = src[lane];
+        xil[ks][c] = src[64 + lane];
+      } else {
+        xih[ks][c] = shortx8{};
+        xil[ks][c] = shortx8{};
+      }
+    }
+  // settle these loads before the ring starts: a wait for them inside the loop would also wait for
+  // every direct load issued after them
+  asm volatile("" ::"v"(xih[0][0]), "v"(xih[0][1]), "v"(xih[1][0]), "v"(xih[1][1]));
+  asm volatile("" ::"v"(xil[0][0]), "v"(xil[0][1]), "v"(xil[1][0]), "v"(xil[1][1]));
   __syncthreads();
 
-  // Direct loads: a wave-uniform base plus a fixed per-lane 32-bit offset.  Stack instruction
-  // i (i = wave + 4q) moves tile rows 8i .. 8i + 7 (a row group past N: the last valid group,
-  // never written back); lane: row 8i + lane / 8, stored chunk lane % 8 holds the row's 16-byte
-  // chunk (lane % 8) ^ (lane / 8), so chunk c of tile row r sits at c ^ (r % 8).  Signal
-  // instruction i moves the i-th kilobyte of the stage's pre-split signal block.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   const uint32_t aoff = (uint32_t)((((size_t)(lane >> 3)) * N + 4 * ((lane & 7) ^ (lane >> 3))) * 4);
-  const char* xsb = (const char*)Xs + (size_t)cb * nch * DXB;
   auto issue = [&](int it) {
-    char* st = sm + (it % DNS) * DSB;
-    const int gs = s0 + it, t = gs / nch, chunk = gs - t * nch;
-    const int k0 = chunk * DK;
-    const float* A = t < 2 * L ? stack + (size_t)t * N * N : P;
+    char* st = sm + (it % NS) * DSB;
+    const int jc = cfirst + it / T1, t = it % T1;
+    const float* A = t < L ? stack + (size_t)t * N * N : P;
 #pragma unroll
     for (int q = 0; q < DAB / 4096; ++q) {
       const int i = wv + 4 * q;
       const int row0 = i0 + 8 * i <= N - 8 ? i0 + 8 * i : N - 8;
-      const char* gb = (const char*)(A + (size_t)row0 * N + k0);
+      const char* gb = (const char*)(A + (size_t)row0 * N + jc * DK);
       lds_dma16(gb + aoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
     }
 #pragma unroll
     for (int q = 0; q < DXB / 4096; ++q) {
       const int i = wv + 4 * q;
-      const char* gb = xsb + (size_t)chunk * DXB + i * 1024;
+      const char* gb = xsb + (size_t)jc * DXB + i * 1024;
       lds_dma16(gb + 16 * lane, __builtin_amdgcn_readfirstlane(lds_addr(st + DAB + i * 1024)));
     }
   };
 
-  // acc: FP32 products of the current term; at the end of each term (or of the run) they are
-  // folded with the column's coefficient into FP64 sums of the real part, so an output sees one
-  // FP32 chain of at most N products per term.  The imaginary part is the P term alone.
-  double sum_re[2][16] = {};
-  float sum_im[2][16] = {};
-  floatx16 acc[2] = {};
+  float sum_pos[2][16] = {}, sum_im[2][16] = {}, sum_neg[2][16] = {};
   const int r = 32 * wave + l32;
-  for (int it = 0; it < DNS - 1 && it < nst; ++it) issue(it);
+  issue(0);
   for (int it = 0; it < nst; ++it) {
-    // this wave's loads of stage it have landed (only the DNS - 2 younger stages may still be in
-    // flight) and its LDS reads of stage it - 1 are done; after the barrier that holds for all waves
-    if (it + DNS - 1 <= nst) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((DNS - 2) * DLW));
-    else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    // this wave's loads of stage it have landed and its LDS reads of stage it - 1 are done; after the
+    // barrier that holds for every wave, so stage it + 1 may refill the other slot
+    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
     barrier_nofence();
-    if (it + DNS - 1 < nst) issue(it + DNS - 1);   // refills the slot of stage it - 1
-    const char* st = sm + (it % DNS) * DSB;
+    if (it + 1 < nst) issue(it + 1);
+    const char* st = sm + (it % NS) * DSB;
+    const int jc = cfirst + it / T1, t = it % T1;
+    const bool isP = t == L;
+    // ---- positive: S_t[I, J] X[J]
+    floatx16 acc[2] = {};
 #pragma unroll
     for (int ks = 0; ks < DK / 16; ++ks) {
-      // A: S_t[i0 + r][k0 + 16 ks + 8 lh .. + 7], two 16-byte chunks, split after the 2^12 scale
       shortx8 ah, al;
-      const bool pstage = BF && (s0 + it) / nch == 2 * L;      // wave-uniform
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int ch = (4 * ks + 2 * lh + q) ^ (r & 7);
         const float4 v = *(const float4*)(st + r * (DK * 4) + ch * 16);
         short h, l;
-        if (BF && !pstage) {
-          const uint4 w = __builtin_bit_cast(uint4, v);
-          ah[4 * q + 0] = (short)(w.x & 0xffff); al[4 * q + 0] = (short)(w.x >> 16);
-          ah[4 * q + 1] = (short)(w.y & 0xffff); al[4 * q + 1] = (short)(w.y >> 16);
-          ah[4 * q + 2] = (short)(w.z & 0xffff); al[4 * q + 2] = (short)(w.z >> 16);
-          ah[4 * q + 3] = (short)(w.w & 0xffff); al[4 * q + 3] = (short)(w.w >> 16);
+        if (BF && !isP) {
+          const uint4 u4 = __builtin_bit_cast(uint4, v);
+          ah[4 * q + 0] = (short)(u4.x & 0xffff); al[4 * q + 0] = (short)(u4.x >> 16);
+          ah[4 * q + 1] = (short)(u4.y & 0xffff); al[4 * q + 1] = (short)(u4.y >> 16);
+          ah[4 * q + 2] = (short)(u4.z & 0xffff); al[4 * q + 2] = (short)(u4.z >> 16);
+          ah[4 * q + 3] = (short)(u4.w & 0xffff); al[4 * q + 3] = (short)(u4.w >> 16);
         } else if (BF) {
           bsplit(v.x, h, l); ah[4 * q + 0] = h; al[4 * q + 0] = l;
           bsplit(v.y, h, l); ah[4 * q + 1] = h; al[4 * q + 1] = l;
@@ -212,25 +209,86 @@ __global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float
         acc[c] = dmma<BF>(al, bh, acc[c]);
       }
     }
-    const int gs = s0 + it;
-    if ((gs + 1) % nch == 0 || it == nst - 1) {     // the term ends here (or the run does)
-      const int tl = gs / nch - tfirst;
-      const bool isP = tfirst + tl == 2 * L;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const double gr = (double)gl[tl * 64 + 32 * c + l32];
+    for (int c = 0; c < 2; ++c) {
+      const float gp = gl[(isP ? 2 * L : t) * 64 + 32 * c + l32];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) sum_re[c][e] = fma(gr, (double)acc[c][e], sum_re[c][e]);
-        if (isP) {
-          const float gi = gl[nterm * 64 + 32 * c + l32];
+      for (int e = 0; e < 16; ++e) sum_pos[c][e] = fmaf(gp, acc[c][e], sum_pos[c][e]);
+      if (isP) {
+        const float gi = gl[(2 * L + 1) * 64 + 32 * c + l32];
 #pragma unroll
-          for (int e = 0; e < 16; ++e) sum_im[c][e] = fmaf(gi, acc[c][e], sum_im[c][e]);
-        }
-        acc[c] = floatx16{};
+        for (int e = 0; e < 16; ++e) sum_im[c][e] = fmaf(gi, acc[c][e], sum_im[c][e]);
       }
     }
+    if (!isP) {
+      // ---- negative: S_t[I_w, J]^T X[I_w]; lane (j = l32, lh) holds tile rows 32 w + 16 ks + 8 lh + e
+      // of column j (chunk j / 4 of those rows, swizzled by row)
+      floatx16 an[2] = {};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        shortx8 th, tl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int rr = 32 * wave + 16 * ks + 8 * lh + e;
+          const float v = *(const float*)(st + rr * (DK * 4) + (((l32 >> 2) ^ (rr & 7)) * 16) + (l32 & 3) * 4);
+          short h, l;
+          if (BF) {
+            const uint32_t u = __builtin_bit_cast(uint32_t, v);
+            h = (short)(u & 0xffff);
+            l = (short)(u >> 16);
+          } else {
+            dsplit(v * kStackScale, h, l);
+          }
+          th[e] = h;
+          tl[e] = l;
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          an[c] = dmma<BF>(th, xih[ks][c], an[c]);
+          an[c] = dmma<BF>(th, xil[ks][c], an[c]);
+          an[c] = dmma<BF>(tl, xih[ks][c], an[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float gn = gl[(L + t) * 64 + 32 * c + l32];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sum_neg[c][e] = fmaf(gn, an[c][e], sum_neg[c][e]);
+      }
+    } else {
+      // the chunk's terms are done: the four waves' negative partials (rows J of this chunk) are
+      // added through the stage's LDS slot (free once every wave has passed this barrier; the next
+      // refill of it comes after the next iteration's barrier) and wave 0 writes the sum
+      barrier_nofence();
+      float* red = (float*)(sm + (it % NS) * DSB);             // [wave 1..3][c][e][lane]: 24 KB
+      if (wave > 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) red[(((wave - 1) * 2 + c) * 16 + e) * 64 + lane] = sum_neg[c][e];
+      }
+      __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(63));              // LDS writes done (lgkmcnt 0)
+      barrier_nofence();
+      if (wave == 0) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int col = b0 + 32 * c + l32;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            float v = sum_neg[c][e];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v += red[((q * 2 + c) * 16 + e) * 64 + lane];
+            const int gj = jc * DK + 8 * (e >> 2) + 4 * lh + (e & 3);
+            part_neg[((size_t)ib * N + gj) * ncp + col] = v;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sum_neg[c][e] = 0.f;
+    }
   }
-  // lane holds column b0 + 32 c + l32, rows 32 wave + 8 (e / 4) + 4 lh + e % 4
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int col = b0 + 32 * c + l32;
@@ -239,26 +297,30 @@ __global__ __launch_bounds__(256, DirectCfg<DNS>::WPC) void k_direct(const float
       const int gi = i0 + 32 * wave + 8 * (e >> 2) + 4 * lh + (e & 3);
       if (gi < N) {
         const size_t o = ((size_t)g * N + gi) * ncp + col;
-        part_re[o] = (float)sum_re[c][e];
-        if (hasP) part_im[o] = sum_im[c][e];
+        part_pos[o] = sum_pos[c][e];
+        part_im[o] = sum_im[c][e];
       }
     }
   }
 }
 
-// Y[i][c] = (sum_g part_re[g][i][c]) u + c_0 X[i][c] + j (sum_{g >= gP} part_im[g][i][c]) u,
-// runs in a fixed order.
-__global__ __launch_bounds__(256) void k_direct_reduce(const float* __restrict__ part_re,
-                                                       const float* __restrict__ part_im, int G, int gP, int N,
-                                                       int ncp, int ncols, int L, const float* __restrict__ gam,
-                                                       const float* __restrict__ X, int ldx,
-                                                       cplx64* __restrict__ Y, int ldy) {
+// Y[i][c] = u (sum_g pos[g][i][c] + sum_q neg[q][i][c]) + c_0 X[i][c] + j u sum_g im[g][i][c],
+// partials in a fixed order.
+__global__ __launch_bounds__(256) void k_direct_pair_reduce(const float* __restrict__ part_pos,
+                                                            const float* __restrict__ part_im,
+                                                            const float* __restrict__ part_neg, int G, int NQ, int N,
+                                                            int ncp, int ncols, int L, const float* __restrict__ gam,
+                                                            const float* __restrict__ X, int ldx,
+                                                            cplx64* __restrict__ Y, int ldy) {
   const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (size_t)N * ncols) return;
   const int i = (int)(idx / ncols), c = (int)(idx % ncols);
   float re = 0.f, im = 0.f;
-  for (int g = 0; g < G; ++g) re += part_re[((size_t)g * N + i) * ncp + c];
-  for (int g = gP; g < G; ++g) im += part_im[((size_t)g * N + i) * ncp + c];
+  for (int g = 0; g < G; ++g) {
+    re += part_pos[((size_t)g * N + i) * ncp + c];
+    im += part_im[((size_t)g * N + i) * ncp + c];
+  }
+  for (int q = 0; q < NQ; ++q) re += part_neg[((size_t)q * N + i) * ncp + c];
   const float c0 = gam[(size_t)(2 * L + 2) * ncp + c], u = gam[(size_t)(2 * L + 3) * ncp + c];
   Y[(size_t)i * ldy + c] = cplx64{re * u + c0 * X[(size_t)i * ldx + c], im * u};
 }
@@ -332,35 +394,25 @@ __global__ __launch_bounds__(256) void k_direct_plain(const void* __restrict__ s
 }
 
 // ---------------------------------------------------------------- host side
-// Runs per tile: enough for one round of the resident workgroups per CU when the tiles allow,
-// and at most TG - 1 terms of stages per run (the coefficient rows a run keeps in LDS).
-struct DirectGrid {
-  int nIB, ncb, ncp, nch, G, SPW, gP;
+// Paired kernel grid: runs of CPR chunks J per row block, enough runs for one round of resident
+// workgroups; runs depend on N and L only.
+struct PairGrid {
+  int nIB, ncb, ncp, nch, G, CPR, lds;
 };
 
-// Two ring stages with three workgroups per CU measured a few percent faster than three stages
-// with two workgroups per CU at N = 4096, L = 32 (64 and 256 columns).
-constexpr int kDirectNS = 2;
-using DCfg = DirectCfg<kDirectNS>;
-
-static DirectGrid direct_grid(int N, int L, int ncols) {
-  const int TG = DCfg::TG, WPC = DCfg::WPC;
-  DirectGrid d;
+static PairGrid pair_grid(int N, int L, int ncols) {
+  PairGrid d;
   d.nIB = ceil_div(N, DM);
   d.ncb = ceil_div(ncols, 64);
   d.ncp = d.ncb * 64;
   d.nch = N / DK > 0 ? N / DK : 1;
-  const int T = 2 * L + 1, total = T * d.nch;
-  // the runs depend on N and L only, so a column's result (its FP64 fold and reduction order)
-  // does not depend on how many other columns share the call
-  const long units = d.nIB;
-  int G = (int)(256 * WPC / units);
-  const int gmin = ceil_div(T, TG - 1);
-  if (G < gmin) G = gmin;
-  if (G > total) G = total;
-  d.SPW = ceil_div(total, G);
-  d.G = ceil_div(total, d.SPW);
-  d.gP = (2 * L * d.nch) / d.SPW;
+  d.lds = 2 * DSB + (2 * L + 2) * 64 * 4;
+  const int wpc = d.lds <= 80 * 1024 ? 2 : 1;
+  int G = 256 * wpc / d.nIB;
+  if (G < 1) G = 1;
+  if (G > d.nch) G = d.nch;
+  d.CPR = ceil_div(d.nch, G);
+  d.G = ceil_div(d.nch, d.CPR);
   return d;
 }
 
@@ -371,12 +423,14 @@ struct DirectWs {
   short* Xs;
   float* part_re;
   float* part_im;
+  float* part_neg;
   size_t bytes;
 };
 
 static DirectWs direct_ws(const Plan* p, int ncols, int ldx, void* base) {
   const int N = p->N, L = p->L;
-  const DirectGrid d = direct_grid(N, L, ncols);
+  const PairGrid d = pair_grid(N, L, ncols);
+  const int G = d.G;
   DirectWs w;
   char* b = (char*)base;
   size_t off = 0;
@@ -384,11 +438,13 @@ static DirectWs direct_ws(const Plan* p, int ncols, int ldx, void* base) {
   w.colpart = (float*)(b + off); off += colscale_partial_bytes(N, 1, ldx);
   w.gam = (float*)(b + off); off += align_up((size_t)(2 * L + 4) * d.ncp * sizeof(float), 256);
   w.Xs = (short*)(b + off); off += align_up((size_t)d.ncb * d.nch * DXB, 256);
-  w.part_re = (float*)(b + off); off += align_up((size_t)d.G * N * d.ncp * sizeof(float), 256);
-  w.part_im = (float*)(b + off); off += align_up((size_t)d.G * N * d.ncp * sizeof(float), 256);
+  w.part_re = (float*)(b + off); off += align_up((size_t)G * N * d.ncp * sizeof(float), 256);
+  w.part_im = (float*)(b + off); off += align_up((size_t)G * N * d.ncp * sizeof(float), 256);
+  w.part_neg = (float*)(b + off); off += align_up((size_t)d.nIB * N * d.ncp * sizeof(float), 256);
   w.bytes = off;
   return w;
 }
+
 
 size_t direct_ws_bytes(const Plan* p, int ncols, int ldx) {
   if (ncols < 1) return 256;
@@ -408,7 +464,7 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
                             hipStream_t s) {
   if (ncols == 0) return FGFRFT_OK;
   const int N = p->N, L = p->L;
-  const DirectGrid d = direct_grid(N, L, ncols);
+  const PairGrid d = pair_grid(N, L, ncols);
   const DirectWs w = direct_ws(p, ncols, ldx, ws);
   const bool bf = p->stacktype == FGFRFT_STACK_BF16X2;
   const bool fast = !p->cplx && !x_complex && N % DK == 0;
@@ -438,26 +494,24 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
   FG_LAUNCHED("direct coefficients");
   rc = xsplit_launch((const float*)X, ldx, ncols, N, 1, 0, w.xs, 0, w.Xs, s, bf);
   if (rc) return rc;
-  const size_t nblocks = (size_t)8 * ceil_div(d.nIB * d.G, 8) * d.ncb;
-  if (nblocks > 0x7fffffff) {
+  const size_t nb = (size_t)8 * ceil_div(d.nIB * d.G, 8) * d.ncb;
+  if (nb > 0x7fffffff) {
     set_error("direct grid too large");
     return FGFRFT_EUNSUPPORTED;
   }
-  static bool attr_set = false;
-  if (!attr_set) {
-    FG_HIP(hipFuncSetAttribute((const void*)k_direct<kDirectNS, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               DCfg::LDS));
-    FG_HIP(hipFuncSetAttribute((const void*)k_direct<kDirectNS, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               DCfg::LDS));
-    attr_set = true;
+  static int attr_lds[2] = {0, 0};
+  auto kp = bf ? k_direct_pair<true> : k_direct_pair<false>;
+  if (attr_lds[bf] < d.lds) {
+    FG_HIP(hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds));
+    attr_lds[bf] = d.lds;
   }
-  auto kern = bf ? k_direct<kDirectNS, true> : k_direct<kDirectNS, false>;
-  kern<<<(unsigned)nblocks, 256, DCfg::LDS, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs, d.ncp, w.gam,
-                                                 d.SPW, d.G, d.nIB, d.ncb, w.part_re, w.part_im);
+  kp<<<(unsigned)nb, 256, d.lds, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs, d.ncp, w.gam, d.CPR,
+                                      d.G, d.nIB, d.ncb, w.part_re, w.part_im, w.part_neg);
   FG_LAUNCHED("direct");
   const size_t n = (size_t)N * ncols;
-  k_direct_reduce<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.part_re, w.part_im, d.G, d.gP, N, d.ncp, ncols, L,
-                                                              w.gam, (const float*)X, ldx, (cplx64*)Y, ldy);
+  k_direct_pair_reduce<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w.part_re, w.part_im, w.part_neg, d.G, d.nIB, N,
+                                                                   d.ncp, ncols, L, w.gam, (const float*)X, ldx,
+                                                                   (cplx64*)Y, ldy);
   FG_LAUNCHED("direct reduce");
   return FGFRFT_OK;
 }

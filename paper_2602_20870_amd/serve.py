@@ -40,11 +40,11 @@ ROUTES = ("auto", "operator", "direct")
 
 
 def prefer_direct(n_orders: int, n_blocks: int, L: int) -> bool:
-    """Route choice for one batch from HBM traffic: the direct route streams the (2L+1) N^2 stack
-    elements once per 64-column block (blocks after the first partly hit in L2: measured about
-    0.6 of a stream each at N = 4096, L = 32), the operator route streams them once and adds
-    16 N^2 bytes (write and read of one complex64 operator) per order, i.e. 4 / (2L+1) of a
-    stream per order.  Direct iff 0.6 (blocks - 1) < 4 n_orders / (2L+1)."""
+    """Route choice for one batch, in units of the operator route's stack stream S (its update
+    reads the 2L resident matrices): the operator route costs S plus 16 N^2 bytes (write and read
+    of one complex64 operator) per order, 4 / (2L+1) of S each; the direct route costs about 0.85 S
+    for the first 64-column block and about 0.6 S for each further one (measured at N = 4096,
+    L = 32).  Direct iff 0.6 (blocks - 1) < 4 n_orders / (2L+1), slightly conservative."""
     return n_blocks <= DIRECT_BLOCKS and 0.15 * (n_blocks - 1) * (2 * L + 1) < n_orders
 
 
