@@ -8,8 +8,8 @@
 // owns a strip of TR rows x 64 columns of positions: it stages the 2L stack tiles of the
 // strip in LDS once (direct HBM-to-LDS loads), then its 4 waves produce those positions of
 // Q for every order of the call (all waves on the same group of 32 orders at a time), so
-// each stack element is read from HBM once per call.  With paired blocks a lane holds two
-// neighbouring positions and each store writes 512-byte runs of a row.  The P and identity
+// each stack element is read from HBM once per call.  With paired blocks each store instruction
+// writes a 512-byte run of one row of one operator plane.  The P and identity
 // terms ride in one extra MFMA k-step whose B operand is built in registers, so the
 // epilogue is only the power-of-two unscale.
 //
@@ -22,7 +22,6 @@
 
 namespace fgfrft {
 
-constexpr int TCOLS = 64;  // columns per strip
 
 // ------------------------------------------------------------ coefficients (a-1)
 template <bool BF>
@@ -193,31 +192,31 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 // Interior strip whose rows start 16-byte aligned: every instruction moves 1 KB of R (64 lanes
 // x 16 bytes) from HBM straight into LDS; producer wave pw of NPW issues instructions pw, pw+NPW, ..
-template <bool CPLX, int TR, int NPW>
+template <bool CPLX, int TR, int TC, int NPW>
 __device__ __forceinline__ void stage_direct(const void* __restrict__ stack, int N, int L, int row0, int col0, char* R,
                                              int pw, int lane) {
-  constexpr int EB = CPLX ? 8 : 4, PT = TR * TCOLS;
+  constexpr int EB = CPLX ? 8 : 4, PT = TR * TC;
   const int ninst = 2 * L * PT * EB / 1024;      // 2L * PT * EB is a multiple of 1 KB (PT * EB >= 512)
   const size_t NN = (size_t)N * N;
   for (int i = pw; i < ninst; i += NPW) {
     const int e0 = (i * 1024 + 16 * lane) / EB;  // first element of this lane's 16 bytes in R
     const int k = e0 / PT, pos = e0 % PT;
-    const char* g = (const char*)stack + ((size_t)k * NN + (size_t)(row0 + pos / TCOLS) * N + col0 + pos % TCOLS) * EB;
+    const char* g = (const char*)stack + ((size_t)k * NN + (size_t)(row0 + pos / TC) * N + col0 + pos % TC) * EB;
     __builtin_amdgcn_global_load_lds(g, (lds_void*)(R + i * 1024), 16, 0, 0);
   }
 }
 
 // Any strip (edges, unaligned N): element by element through registers, zero outside the matrix.
-template <bool CPLX, int TR, int NTH>
+template <bool CPLX, int TR, int TC, int NTH>
 __device__ __forceinline__ void stage_generic(const void* __restrict__ stack, int N, int L, int row0, int col0,
                                               char* R, int t) {
-  constexpr int NPL = CPLX ? 2 : 1, PT = TR * TCOLS;
+  constexpr int NPL = CPLX ? 2 : 1, PT = TR * TC;
   const size_t NN = (size_t)N * N;
   uint32_t* dst = (uint32_t*)R;
   const uint32_t* src = (const uint32_t*)stack;
   for (int e = t; e < 2 * L * PT; e += NTH) {
     const int k = e / PT, pos = e % PT;
-    const int row = row0 + pos / TCOLS, col = col0 + pos % TCOLS;
+    const int row = row0 + pos / TC, col = col0 + pos % TC;
     const bool inb = row < N && col < N;
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl)
@@ -225,11 +224,11 @@ __device__ __forceinline__ void stage_generic(const void* __restrict__ stack, in
   }
 }
 
-template <bool CPLX, int TR, int NTH>
+template <bool CPLX, int TR, int TC, int NTH>
 __device__ __forceinline__ void stage_p(const void* __restrict__ Pm, int N, int row0, int col0, float* Pt, int t) {
-  constexpr int NPL = CPLX ? 2 : 1, PT = TR * TCOLS;
+  constexpr int NPL = CPLX ? 2 : 1, PT = TR * TC;
   for (int p = t; p < PT; p += NTH) {
-    const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
+    const int row = row0 + p / TC, col = col0 + p % TC;
     const bool inb = row < N && col < N;
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl) Pt[p * NPL + pl] = inb ? ((const float*)Pm)[((size_t)row * N + col) * NPL + pl] : 0.f;
@@ -238,12 +237,12 @@ __device__ __forceinline__ void stage_p(const void* __restrict__ Pm, int N, int 
 
 // B fragments for this lane's position p of the strip (all k, split into 16-bit parts) and the
 // extra k-step operand (P_re, P_im, identity at k = 0..2 for lanes lh == 0, zero elsewhere).
-template <bool CPLX, int KP, int TR, bool BF>
+template <bool CPLX, int KP, int TR, int TC, bool BF>
 __device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const float* Pt, int N, int row0, int col0,
                                                    int p, int lh, shortx8 (&bh)[CPLX ? 2 : 1][KP / 16],
                                                    shortx8 (&bl)[CPLX ? 2 : 1][KP / 16], shortx8& bxh, shortx8& bxl) {
   constexpr int NPL = CPLX ? 2 : 1;
-  constexpr int KS = KP / 16, PT = TR * TCOLS;
+  constexpr int KS = KP / 16, PT = TR * TC;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -262,7 +261,7 @@ __device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const floa
   bxh = shortx8{};
   bxl = shortx8{};
   if (lh == 0) {
-    const int row = row0 + p / TCOLS, col = col0 + p % TCOLS;
+    const int row = row0 + p / TC, col = col0 + p % TC;
     const float pr = CPLX ? Pt[2 * p] : Pt[p];
     const float pi = CPLX ? Pt[2 * p + 1] : 0.f;
     short h, l;
@@ -275,9 +274,9 @@ __device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const floa
   }
 }
 
-template <bool CPLX, int KP, int TR, int CAP_ = (KP <= 64 ? 256 : 128)>
+template <bool CPLX, int KP, int TR, int TC, int CAP_ = (KP <= 64 ? 256 : 128)>
 struct StripLayout {
-  static constexpr int NPL = CPLX ? 2 : 1, PT = TR * TCOLS, CH = KP / 4;
+  static constexpr int NPL = CPLX ? 2 : 1, PT = TR * TC, CH = KP / 4;
   static constexpr int CAP = CAP_;                                     // orders per LDS table chunk
   static constexpr size_t RB = (size_t)KP * PT * NPL * 4;              // raw stack tiles
   static constexpr size_t PB = ((size_t)PT * NPL * 4 + 15) / 16 * 16;  // P tile
@@ -285,11 +284,74 @@ struct StripLayout {
   static constexpr size_t bytes = RB + PB + TB + (size_t)CAP * 16;      // + epilogue table
 };
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// v_permlane32_swap: x's lanes 32..63 trade places with y's lanes 0..31.  The two results are
+// copied out of the returned vector before the bit casts: this compiler lowers a bit cast of a
+// vector element as a load from the vector's first element (both casts would read x's result).
+__device__ __forceinline__ void swap_halves(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                  false, false);
+  const unsigned rx = r[0], ry = r[1];
+  x = __builtin_bit_cast(float, rx);
+  y = __builtin_bit_cast(float, ry);
+}
+
+// Epilogue of one group of 32 orders for a lane's two neighbouring positions (col, col + 1 of
+// row; lane half lh holds orders a0 + 8(r/4) + 4 lh + r%4 of accumulator element r).
+template <bool OFF32>
+__device__ __forceinline__ void store_pair(const floatx16& re0, const floatx16& im0, const floatx16& re1,
+                                           const floatx16& im1, int a0, int n_alpha, bool fast, int row, int col,
+                                           int N, size_t NN, int lh, float unscale, cplx64* __restrict__ Q) {
+  if (fast) {   // interior, full group of orders, N even
+    // Exchange half-waves so that each store instruction writes one order's whole 64-position row
+    // run (512 contiguous bytes of one plane): after the swap, lane (l32, lh) holds position
+    // col + lh of order 8m + i in (a, c) and of order 8m + 4 + i in (b, d), r = 4m + i.  The plane
+    // offset advances by one plane per store and is pinned to scalar registers, so each store is
+    // a uniform base plus one per-lane offset (no per-store 64-bit addresses held in vector
+    // registers, which would leave too few for the fragments).
+    const size_t plane = NN * sizeof(cplx64);
+    size_t po = (size_t)a0 * plane;
+    const size_t vo = ((size_t)row * N + col + lh) * sizeof(cplx64);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float a[4], b[4], c[4], d[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = re0[4 * m + i] * unscale; b[i] = re1[4 * m + i] * unscale;
+        c[i] = im0[4 * m + i] * unscale; d[i] = im1[4 * m + i] * unscale;
+        swap_halves(a[i], b[i]);
+        swap_halves(c[i], d[i]);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const f32x2 v = h == 0 ? f32x2{a[i], c[i]} : f32x2{b[i], d[i]};
+          if (OFF32) __builtin_nontemporal_store(v, (f32x2*)((char*)Q + po + (uint32_t)vo));
+          else __builtin_nontemporal_store(v, (f32x2*)((char*)Q + po + vo));
+          po += plane;
+          asm volatile("" : "+s"(po));
+        }
+    }
+  } else if (row < N) {
+    cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha) {
+        cplx64* q = ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN;
+        if (col < N) q[0] = cplx64{re0[r] * unscale, im0[r] * unscale};
+        if (col + 1 < N) q[1] = cplx64{re1[r] * unscale, im1[r] * unscale};
+      }
+  }
+}
+
 // Two 32-position blocks whose lanes hold the even (block 0) and odd (block 1) position of one
-// column pair: the same MFMA sequence per block as order_group, then one 16-byte store per order
-// and lane (two neighbouring complex values), so each half-wave writes a 512-byte row run.  The
-// operator planes are streamed out with nontemporal stores (they are far larger than the caches).
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+// column pair: the same MFMA sequence per block as order_group; a half-wave exchange then gives each
+// lane one position of two orders, so every store instruction writes one order's 64-position row
+// run (512 contiguous bytes of a single plane; measured 7% faster than two 512-byte runs in planes
+// four orders apart).  The operator planes are streamed out with nontemporal stores (they are far
+// larger than the caches).
 template <bool CPLX, int KP, bool BF, bool OFF32>
 __device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, int g0, int a0, int n_alpha, bool fast,
                                            int row, int col, int N, size_t NN, int l32, int lh,
@@ -334,31 +396,7 @@ __device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, in
   im0 = mfma16<BF>(xiH, bxh0, im0); im1 = mfma16<BF>(xiH, bxh1, im1);
   im0 = mfma16<BF>(xiH, bxl0, im0); im1 = mfma16<BF>(xiH, bxl1, im1);
   im0 = mfma16<BF>(xiL, bxh0, im0); im1 = mfma16<BF>(xiL, bxh1, im1);
-  if (fast) {   // interior, full group of orders, N even: 16-byte aligned pairs
-    if (OFF32) {
-      const uint32_t voff = (uint32_t)(((size_t)4 * lh * NN + (size_t)row * N + col) * sizeof(cplx64));
-      char* qa = (char*)(Q + (size_t)a0 * NN);
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        __builtin_nontemporal_store(f32x4{re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale},
-                                    (f32x4*)(qa + (size_t)(8 * (r >> 2) + (r & 3)) * NN * sizeof(cplx64) + voff));
-    } else {
-      cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        __builtin_nontemporal_store(f32x4{re0[r] * unscale, im0[r] * unscale, re1[r] * unscale, im1[r] * unscale},
-                                    (f32x4*)(ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN));
-    }
-  } else if (row < N) {
-    cplx64* ql = Q + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha) {
-        cplx64* q = ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN;
-        if (col < N) q[0] = cplx64{re0[r] * unscale, im0[r] * unscale};
-        if (col + 1 < N) q[1] = cplx64{re1[r] * unscale, im1[r] * unscale};
-      }
-  }
+  store_pair<OFF32>(re0, im0, re1, im1, a0, n_alpha, fast, row, col, N, NN, lh, unscale, Q);
 }
 
 // Table chunk of ncap orders into LDS with direct HBM/L2-to-LDS loads: LDS 16-byte chunk m =
@@ -382,12 +420,12 @@ __device__ __forceinline__ void load_table_direct(const uint16_t* __restrict__ t
 // then reuses the LDS for the coefficient table, CAP orders at a time, and runs the order loop,
 // which touches only LDS, the matrix cores and stores: nothing in it waits on the memory counter
 // the stores also use, so the stores stream without drains.
-template <bool CPLX, int KP, int TR, bool BF, int NT, int MINW, bool OFF32, int CAPV, bool PAIR>
+template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, bool OFF32, int CAPV, bool PAIR>
 __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restrict__ stack, const void* __restrict__ Pm,
                                                            int N, int L, int nJ, const uint16_t* __restrict__ table,
                                                            const float4* __restrict__ epi, int n_alpha, int n_pad,
                                                            cplx64* __restrict__ Q) {
-  using LY = StripLayout<CPLX, KP, TR, CAPV>;
+  using LY = StripLayout<CPLX, KP, TR, TC, CAPV>;
   constexpr int NPL = LY::NPL, CH = LY::CH, KS = KP / 16, PT = LY::PT, CAP = LY::CAP;
   constexpr int NW = NT / 64, NBLK = PT / 32, BPW = NBLK >= NW ? NBLK / NW : 1;
   extern __shared__ __align__(16) shortx8 smem[];
@@ -398,28 +436,30 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
   const int I = blockIdx.x / nJ, J = blockIdx.x % nJ;
-  const int row0 = I * TR, col0 = J * TCOLS;
+  const int row0 = I * TR, col0 = J * TC;
   const size_t NN = (size_t)N * N;
-  const bool interior = row0 + TR <= N && col0 + TCOLS <= N;
+  const bool interior = row0 + TR <= N && col0 + TC <= N;
 
   for (int e = tid; e < (KP - 2 * L) * PT * NPL; e += NT) ((uint32_t*)R)[2 * L * PT * NPL + e] = 0u;
-  if (((size_t)N * (CPLX ? 8 : 4)) % 16 == 0 && interior) stage_direct<CPLX, TR, NW>(stack, N, L, row0, col0, R, wave, lane);
-  else stage_generic<CPLX, TR, NT>(stack, N, L, row0, col0, R, tid);
-  stage_p<CPLX, TR, NT>(Pm, N, row0, col0, Pt, tid);
+  if (((size_t)N * (CPLX ? 8 : 4)) % 16 == 0 && interior) stage_direct<CPLX, TR, TC, NW>(stack, N, L, row0, col0, R, wave, lane);
+  else stage_generic<CPLX, TR, TC, NT>(stack, N, L, row0, col0, R, tid);
+  stage_p<CPLX, TR, TC, NT>(Pm, N, row0, col0, Pt, tid);
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
-  // PAIR: wave w owns strip rows w * BPW/2 .. (BPW/2 per wave); block j holds the positions of row
-  // w * BPW/2 + j/2 with column parity j & 1.  Otherwise block j is positions (wave + NW j) * 32 + 0..31.
-  static_assert(!PAIR || (BPW % 2 == 0 && NW * BPW / 2 == TR), "paired blocks cover whole strip rows");
+  // PAIR: the strip is cut into 64-column row segments (TC / 64 per row); wave w owns segments
+  // w * BPW/2 .. (BPW/2 per wave), and block j holds the positions of segment w * BPW/2 + j/2 with
+  // column parity j & 1.  Otherwise block j is positions (wave + NW j) * 32 + 0..31.
+  static_assert(!PAIR || (BPW % 2 == 0 && NW * BPW / 2 * 64 == TR * TC && TC % 64 == 0),
+                "paired blocks cover the strip in 64-column row segments");
   auto pos_of = [&](int j) {
-    if (PAIR) return (wave * (BPW / 2) + j / 2) * TCOLS + 2 * l32 + (j & 1);
+    if (PAIR) return (wave * (BPW / 2) + j / 2) * 64 + 2 * l32 + (j & 1);
     const int blk = wave + NW * j < NBLK ? wave + NW * j : NBLK - 1;
     return blk * 32 + l32;
   };
   shortx8 bh[BPW][NPL][KS], bl[BPW][NPL][KS], bxh[BPW], bxl[BPW];
 #pragma unroll
   for (int j = 0; j < BPW; ++j)
-    load_fragments_raw<CPLX, KP, TR, BF>((const uint32_t*)R, Pt, N, row0, col0, pos_of(j), lh, bh[j], bl[j], bxh[j],
+    load_fragments_raw<CPLX, KP, TR, TC, BF>((const uint32_t*)R, Pt, N, row0, col0, pos_of(j), lh, bh[j], bl[j], bxh[j],
                                          bxl[j]);
   for (int c0 = 0; c0 < n_pad; c0 += CAP) {
     const int ncap = n_pad - c0 < CAP ? n_pad - c0 : CAP;
@@ -436,8 +476,8 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
 #pragma unroll
         for (int j = 0; j < BPW; j += 2) {
           const int p = pos_of(j);
-          order_pair<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast && (N % 2) == 0, row0 + p / TCOLS,
-                                          col0 + p % TCOLS, N, NN, l32, lh, bh[j], bl[j], bxh[j], bxl[j], bh[j + 1],
+          order_pair<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast && (N % 2) == 0, row0 + p / TC,
+                                          col0 + p % TC, N, NN, l32, lh, bh[j], bl[j], bxh[j], bxl[j], bh[j + 1],
                                           bl[j + 1], bxh[j + 1], bxl[j + 1], Q);
         }
       } else {
@@ -446,7 +486,7 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
           const int blk = wave + NW * j;
           if (blk >= NBLK) break;
           const int p = blk * 32 + l32;
-          order_group<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast, row0 + p / TCOLS, col0 + p % TCOLS, N, NN,
+          order_group<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast, row0 + p / TC, col0 + p % TC, N, NN,
                                            l32, lh, bh[j], bl[j], bxh[j], bxl[j], Q);
         }
       }
@@ -474,21 +514,21 @@ fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, 
   return FGFRFT_OK;
 }
 
-template <bool CPLX, int KP, int TR, bool BF, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false>
+template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false>
 static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha,
                                          int n_pad, void* Q, hipStream_t s) {
-  using LY = StripLayout<CPLX, KP, TR, CAPV>;
+  using LY = StripLayout<CPLX, KP, TR, TC, CAPV>;
   constexpr size_t lds = LY::RB + LY::PB > LY::TB + (size_t)LY::CAP * 16 ? LY::RB + LY::PB : LY::TB + (size_t)LY::CAP * 16;
   static_assert(lds <= 160 * 1024, "LDS budget");
   const bool off32 = (size_t)5 * p->N * p->N * sizeof(cplx64) < ((size_t)1 << 32);
-  auto kern = off32 ? k_update_strip<CPLX, KP, TR, BF, NT, MINW, true, CAPV, PAIR>
-                    : k_update_strip<CPLX, KP, TR, BF, NT, MINW, false, CAPV, PAIR>;
+  auto kern = off32 ? k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, true, CAPV, PAIR>
+                    : k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, false, CAPV, PAIR>;
   static bool attr_set[2] = {false, false};
   if (!attr_set[off32]) {
     FG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set[off32] = true;
   }
-  const int nI = ceil_div(p->N, TR), nJ = ceil_div(p->N, TCOLS);
+  const int nI = ceil_div(p->N, TR), nJ = ceil_div(p->N, TC);
   kern<<<nI * nJ, NT, lds, s>>>(p->stack, p->P, p->N, p->L, nJ, table, epi, n_alpha, n_pad, (cplx64*)Q);
   FG_LAUNCHED("update");
   return FGFRFT_OK;
@@ -502,15 +542,15 @@ static fgfrft_status dispatch(const Plan* p, const uint16_t* table, const float4
   const int KP = kp_of(p->L);
   if (!p->cplx) {
     switch (KP) {
-      case 32: return launch_update_strip<false, 32, 8, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_strip<false, 64, 4, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
-      case 96: return launch_update_strip<false, 96, 2, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
-      case 128: return launch_update_strip<false, 128, 2, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<false, 32, 8, 64, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<false, 64, 4, 64, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
+      case 96: return launch_update_strip<false, 96, 2, 64, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
+      case 128: return launch_update_strip<false, 128, 2, 64, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
     }
   } else {
     switch (KP) {
-      case 32: return launch_update_strip<true, 32, 4, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_strip<true, 64, 2, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<true, 32, 4, 64, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<true, 64, 2, 64, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
     }
   }
   set_error("unsupported L=%d for %s F", p->L, p->cplx ? "complex" : "real");

@@ -126,6 +126,46 @@ def test_update_ragged_and_edge_sizes(N, L, n_alpha):
     _check_update(torch, F, L, alphas)
 
 
+# The paired-block path (real F, 2L padded to 64 matrix rows) at whole-strip sizes: odd L (stack rows
+# 2L..63 zero), order counts off a multiple of 32 (a partial last group of stores), several strips per
+# CU (N >= 512), and more than 256 orders (the order table in two LDS chunks).
+@pytest.mark.parametrize("N,L,n_alpha,seed", [(128, 17, 33, 1), (512, 25, 64, 2), (192, 32, 300, 3),
+                                              (256, 31, 1, 4), (512, 32, 256, 5)])
+def test_update_paired_path_sizes(N, L, n_alpha, seed):
+    torch = torch_cuda()
+    announce(f"update paired path N={N} L={L} n_alpha={n_alpha}")
+    rng = np.random.default_rng(seed)
+    F = _real_orthogonal_with_minus1(N, 1 + N // 16, seed)
+    alphas = rng.uniform(-2, 2, n_alpha)
+    sample = None if N * n_alpha <= 256 * 128 else sorted(set(range(0, n_alpha, 7)) | {n_alpha - 1})
+    worst, *_ = _check_update(torch, F, L, alphas, sample=sample)
+    print("worst rel err", worst)
+
+
+def test_update_integer_and_near_integer_orders():
+    """Orders at and next to integers, where c_n(alpha) tends to a Kronecker delta (Definition 1 at
+    integer orders): |alpha - m| down to 1e-12."""
+    torch = torch_cuda()
+    announce("update: integer and near-integer orders")
+    F = _real_orthogonal_with_minus1(128, 9, 6)
+    alphas = np.array([0.0, 1.0, -1.0, 2.0, 1 + 1e-9, 1 - 1e-7, -2 + 3e-8, 1e-12, -1e-12, 0.5, -0.5, 1.999999,
+                       3 - 2e-6, -2.5, 0.25, 31.0 / 32.0])
+    worst, plan, ref, Q = _check_update(torch, F, 32, alphas)
+    print("worst rel err", worst)
+    assert np.max(np.abs(Q[0] - np.eye(128))) < 2e-6
+    assert np.max(np.abs(Q[1] - F)) < 2e-6
+    assert np.max(np.abs(Q[2] - F.T)) < 2e-6
+
+
+def test_update_paired_path_bf16x2():
+    torch = torch_cuda()
+    announce("update paired path: bf16x2 stack N=256 L=32 40 orders")
+    F = _real_orthogonal_with_minus1(256, 17, 7)
+    alphas = np.random.default_rng(7).uniform(-2, 2, 40)
+    worst, *_ = _check_update(torch, F, 32, alphas, tol=TOL_BF16X2, stacktype="bf16x2")
+    print("bf16x2 worst rel err", worst)
+
+
 def test_update_complex_haar_L10():
     torch = torch_cuda()
     announce("update haar N=96 L=10")
