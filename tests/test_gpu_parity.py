@@ -281,6 +281,32 @@ def test_grad_against_oracle(xc, shared, cplxF):
     assert rel_fro(dX, dX_ref) <= TOL_FP32
 
 
+@pytest.mark.parametrize("xc,B", [(False, 64), (True, 64), (False, 65), (True, 33)])
+def test_grad_outer_product_row_scales(xc, B):
+    """G = GY X^H over two and three 32-signal chunks (33, 64, 65 signals), ragged 64 x 64 tiles
+    (N = 200), and GY / X rows whose magnitudes span eight decades (the per-order scale of the
+    split inner products must follow G's range)."""
+    torch = torch_cuda()
+    announce(f"grad outer product xc={xc} B={B}")
+    rng = np.random.default_rng(100 + B + xc)
+    N, L, n = 200, 12, 3
+    F = _real_orthogonal_with_minus1(N, 7, 14)
+    alphas = np.array([0.37, -1.6, 2.05])
+    X = synth.complex_signals((n, N, B), rng) if xc else synth.real_signals((n, N, B), rng)
+    X = X * np.logspace(-4, 4, N)[rng.permutation(N)][None, :, None]
+    X = X.astype(np.complex64 if xc else np.float32)
+    GY = (rng.standard_normal((n, N, B)) + 1j * rng.standard_normal((n, N, B))) * np.logspace(-4, 4, N)[None, :, None]
+    GY = GY.astype(np.complex64)
+    plan = _gpu_plan(torch, F, L)
+    ref = O.Plan(F, L)
+    Xd = X.astype(np.complex128) if xc else X.astype(np.float64)
+    dal_ref, dX_ref = O.grad(ref.P, ref.M, alphas, Xd, GY.astype(np.complex128), x_real=not xc)
+    dal, dX = plan.grad(alphas, torch.from_numpy(X).cuda(), torch.from_numpy(GY).cuda())
+    scale = np.max(np.abs(dal_ref))
+    assert np.max(np.abs(dal - dal_ref)) <= TOL_FP32 * scale, (dal, dal_ref)
+    assert rel_fro(dX.cpu().numpy(), dX_ref) <= TOL_FP32
+
+
 @pytest.mark.parametrize("N,L,n,cplxF", [(50, 9, 5, False),    # N % 8 != 0: per-tile inner products
                                          (64, 64, 3, False),   # five k-blocks: two passes over the positions
                                          (40, 5, 70, False),   # two chunks of orders
