@@ -103,7 +103,9 @@ __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, co
     }
     __syncthreads();
   }
-  // lane holds column j0 + wj + l32, rows i0 + wi + 8 (e / 4) + 4 lk + e % 4
+  // lane holds column j0 + wj + l32, rows i0 + wi + 8 (e / 4) + 4 lk + e % 4; G is streamed out with
+  // nontemporal stores (the chunk's G is far larger than the caches; 4% faster than plain stores)
+  typedef float f2v __attribute__((ext_vector_type(2)));
   cplx64* g = G + (size_t)blockIdx.z * N * N;
   const int gj = j0 + wj + l32;
   float m = 0.f;
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, co
   for (int e = 0; e < 16; ++e) {
     const int gi = i0 + wi + 8 * (e >> 2) + 4 * lk + (e & 3);
     if (gi < N && gj < N) {
-      g[(size_t)gi * N + gj] = cplx64{accr[e], acci[e]};
+      __builtin_nontemporal_store(f2v{accr[e], acci[e]}, (f2v*)(g + (size_t)gi * N + gj));
       m = fmaxf(m, fmaxf(fabsf(accr[e]), fabsf(acci[e])));
     }
   }
