@@ -8,8 +8,9 @@ operators, outputs, workspaces) plus pinned host staging.  Each scheduling step
   * retires finished batches (event query), hands results to their futures and
     frees their slot set,
   * for every plan with pending requests and a free slot set, coalesces up to K of
-    its requests into one batch and runs it on the slot set's own stream (batches of
-    different plans overlap on the device), replayed from a captured hipGraph for the
+    its requests into one batch and runs it on the slot set's stream (one stream per hardware
+    queue; plans of similar size share one, so small plans do not queue behind large ones;
+    batches on different queues overlap on the device), replayed from a captured hipGraph for the
     batch's size bucket, by one of two routes:
       - operator route: one fused operator-update launch for all the batch's orders
         followed by one apply launch (moves 16 N^2 bytes of operator per order);
@@ -26,6 +27,7 @@ from __future__ import annotations
 
 import collections
 import gc
+import os
 import time
 from concurrent.futures import Future
 
@@ -53,10 +55,10 @@ class AdmissionError(RuntimeError):
 
 
 class _SlotSet:
-    def __init__(self, plan: Plan, K: int, bmax: int, device, use_graphs: bool, route: str = "auto"):
+    def __init__(self, plan: Plan, K: int, bmax: int, device, use_graphs: bool, route: str = "auto", stream=None):
         N = plan.N
         self.K, self.bmax, self.route = K, bmax, route
-        self.stream = torch.cuda.Stream(device=device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.alphas = torch.zeros(K, dtype=torch.float64, device=device)
         self.X = torch.zeros((K, N, bmax), dtype=torch.float32, device=device)
         self.Q = torch.empty((K, N, N), dtype=torch.complex64, device=device)
@@ -224,6 +226,10 @@ class Server:
         self.slots = {}
         self.pending = collections.defaultdict(collections.deque)
         self.inflight = 0
+        # one stream per hardware queue of the device (HIP deals the queues to streams round-robin in
+        # creation order, and a queue runs its commands in order): created together on first admission
+        self.n_queues = max(1, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")))
+        self.streams = []
 
     # ------------------------------------------------------------------ admission
     def footprint(self, N: int, L: int) -> int:
@@ -243,11 +249,37 @@ class Server:
         if self.used + need > self.budget:
             raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {need / 1e9:.2f} GB; "
                                  f"{(self.budget - self.used) / 1e9:.2f} GB left")
+        if not self.streams:
+            self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.n_queues)]
+            # a stream takes its hardware queue at its first command: touch them in order so that
+            # they take different queues
+            for st in self.streams:
+                with torch.cuda.stream(st):
+                    torch.zeros(1, device=self.device).add_(1)
+                st.synchronize()
         plan = Plan(torch.from_numpy(np.ascontiguousarray(F)).to(self.device), L)
-        sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs, self.route) for _ in range(self.S)]
+        sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs, self.route, self.streams[0])
+                for _ in range(self.S)]
         self.plans[gid] = plan
         self.slots[gid] = sets
         self.used += need
+        self._balance()
+
+    def _balance(self):
+        """Deal the slot sets to the hardware-queue streams by size class: sorted by the stack a
+        launch streams (N^2 (2L+1)), the slot sets are cut into as many consecutive groups of equal
+        count as there are streams, so plans of similar cost share a queue.  A queue runs its
+        commands in order, so a small plan's batch that shares a queue with a large plan waits
+        behind the large plan's launches (measured: N = 1024 requests at p50 2.0 ms behind N = 4096
+        batches for 0.1 ms of work of their own), while waiting behind a peer costs about its own
+        service time.  A slot set only launches after its previous batch has completed, so moving it
+        to another stream needs no synchronisation."""
+        units = [(p.N * p.N * (2 * p.L + 1), gid, j) for gid, p in self.plans.items()
+                 for j in range(len(self.slots[gid]))]
+        units.sort(key=lambda u: -u[0])
+        nq = len(self.streams)
+        for i, (_, gid, j) in enumerate(units):
+            self.slots[gid][j].stream = self.streams[min(nq - 1, i * nq // len(units))]
 
     # ------------------------------------------------------------------ requests
     def submit(self, gid, alpha: float, X, t_arrive: float | None = None) -> Future:

@@ -34,3 +34,20 @@ def test_poisson_trace_statistics():
     assert np.all(gaps > 0)
     assert set(g) == set(range(8)) and a.min() >= -2 and a.max() <= 2
     assert b.min() == 1 and b.max() == 64
+
+
+def test_slot_sets_grouped_by_size_on_hardware_queues(built):
+    """The trace's eight plans on four queues: the two N = 4096 plans share one, the two 2048, the
+    two 1024 and the 256 / 512 pair the others, so no small plan waits behind a large plan's batch."""
+    from types import SimpleNamespace
+    from paper_2602_20870_amd.serve import Server
+    srv = Server(hbm_budget=1 << 40, K=4, bmax=8, slot_sets=1, use_graphs=False, device="cpu")
+    srv.streams = [f"q{i}" for i in range(4)]
+    Ns = [256, 512, 1024, 1024, 2048, 2048, 4096, 4096]
+    for gid, N in enumerate(Ns):
+        srv.plans[gid] = SimpleNamespace(N=N, L=32)
+        srv.slots[gid] = [SimpleNamespace(stream=None)]
+    srv._balance()
+    q = {gid: srv.slots[gid][0].stream for gid in srv.plans}
+    assert q[6] == q[7] and q[4] == q[5] and q[2] == q[3] and q[0] == q[1]
+    assert len({q[0], q[2], q[4], q[6]}) == 4
