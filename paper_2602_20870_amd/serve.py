@@ -9,7 +9,7 @@ operators, outputs, workspaces) plus pinned host staging.  Each scheduling step
     frees their slot set,
   * for every plan with pending requests and a free slot set, coalesces up to K of
     its requests into one batch and runs it on the slot set's stream (one stream per hardware
-    queue; plans of similar size share one, so small plans do not queue behind large ones;
+    queue; plans are grouped on them by size, so small plans do not queue behind large ones;
     batches on different queues overlap on the device), replayed from a captured hipGraph for the
     batch's size bucket, by one of two routes:
       - operator route: one fused operator-update launch for all the batch's orders
@@ -48,6 +48,46 @@ def prefer_direct(n_orders: int, n_blocks: int, L: int) -> bool:
     for the first 64-column block and about 0.6 S for each further one (measured at N = 4096,
     L = 32).  Direct iff 0.6 (blocks - 1) < 4 n_orders / (2L+1), slightly conservative."""
     return n_blocks <= DIRECT_BLOCKS and 0.15 * (n_blocks - 1) * (2 * L + 1) < n_orders
+
+
+def _distinct_queue_streams(n: int, device) -> list:
+    """Up to n streams that run on different hardware queues.  Which queue a stream lands on is up
+    to the runtime (and to what the process did before), so candidates are tested: a candidate is
+    kept when a tiny command on it completes while a spin of about 10 ms on each stream kept so far
+    is still running.  If fewer than n pass, the rest are filled with untested candidates."""
+    cands = [torch.cuda.Stream(device=device) for _ in range(4 * n)]
+    t = torch.zeros(1, device=device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(cands[0]):          # calibrate the spin: cycles per millisecond
+        e0.record(cands[0])
+        torch.cuda._sleep(1 << 20)
+        e1.record(cands[0])
+    e1.synchronize()
+    per_ms = (1 << 20) / max(e0.elapsed_time(e1), 1e-3)
+    cycles = int(min(max(10.0 * per_ms, 1 << 16), 32 << 20))   # at most 32x the calibration spin
+
+    def apart(a, b) -> bool:
+        ea, eb = torch.cuda.Event(), torch.cuda.Event()
+        with torch.cuda.stream(a):
+            torch.cuda._sleep(cycles)
+            ea.record(a)
+        with torch.cuda.stream(b):
+            t.add_(1)
+            eb.record(b)
+        eb.synchronize()
+        ok = not ea.query()
+        ea.synchronize()
+        return ok
+
+    chosen = []
+    for c in cands:
+        if len(chosen) == n:
+            break
+        if all(apart(k, c) for k in chosen):
+            chosen.append(c)
+    rest = [c for c in cands if all(c is not k for k in chosen)]
+    torch.cuda.synchronize(device)
+    return chosen + rest[: n - len(chosen)]
 
 
 class AdmissionError(RuntimeError):
@@ -226,8 +266,8 @@ class Server:
         self.slots = {}
         self.pending = collections.defaultdict(collections.deque)
         self.inflight = 0
-        # one stream per hardware queue of the device (HIP deals the queues to streams round-robin in
-        # creation order, and a queue runs its commands in order): created together on first admission
+        # one stream per hardware queue of the device (a queue runs its commands in order), chosen by
+        # test on first admission
         self.n_queues = max(1, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")))
         self.streams = []
 
@@ -250,13 +290,7 @@ class Server:
             raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {need / 1e9:.2f} GB; "
                                  f"{(self.budget - self.used) / 1e9:.2f} GB left")
         if not self.streams:
-            self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.n_queues)]
-            # a stream takes its hardware queue at its first command: touch them in order so that
-            # they take different queues
-            for st in self.streams:
-                with torch.cuda.stream(st):
-                    torch.zeros(1, device=self.device).add_(1)
-                st.synchronize()
+            self.streams = _distinct_queue_streams(self.n_queues, self.device)
         plan = Plan(torch.from_numpy(np.ascontiguousarray(F)).to(self.device), L)
         sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs, self.route, self.streams[0])
                 for _ in range(self.S)]
@@ -268,12 +302,14 @@ class Server:
     def _balance(self):
         """Deal the slot sets to the hardware-queue streams by size class: sorted by the stack a
         launch streams (N^2 (2L+1)), the slot sets are cut into as many consecutive groups of equal
-        count as there are streams, so plans of similar cost share a queue.  A queue runs its
-        commands in order, so a small plan's batch that shares a queue with a large plan waits
-        behind the large plan's launches (measured: N = 1024 requests at p50 2.0 ms behind N = 4096
-        batches for 0.1 ms of work of their own), while waiting behind a peer costs about its own
-        service time.  A slot set only launches after its previous batch has completed, so moving it
-        to another stream needs no synchronisation."""
+        count as there are streams, one group per stream, so plans of similar cost share a queue.  A
+        queue runs its commands in order, so a small plan's batch that shares a queue with a large plan
+        waits behind the large plan's launches (measured: N = 1024 requests at p50 2.0 ms behind
+        N = 4096 batches for 0.1 ms of work of their own), while plans of similar size cost each other
+        about their own service time.  (Giving each large plan a queue of its own and packing the small
+        ones onto the rest measured worse: trace p50 1.5 against 1.1 ms.)  A slot set only launches
+        after its previous batch has completed, so moving it to another stream needs no
+        synchronisation."""
         units = [(p.N * p.N * (2 * p.L + 1), gid, j) for gid, p in self.plans.items()
                  for j in range(len(self.slots[gid]))]
         units.sort(key=lambda u: -u[0])

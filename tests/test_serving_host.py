@@ -51,3 +51,8 @@ def test_slot_sets_grouped_by_size_on_hardware_queues(built):
     q = {gid: srv.slots[gid][0].stream for gid in srv.plans}
     assert q[6] == q[7] and q[4] == q[5] and q[2] == q[3] and q[0] == q[1]
     assert len({q[0], q[2], q[4], q[6]}) == 4
+    # fewer slot sets than queues: one each
+    srv.plans = {0: SimpleNamespace(N=64, L=8), 1: SimpleNamespace(N=128, L=8)}
+    srv.slots = {0: [SimpleNamespace(stream=None)], 1: [SimpleNamespace(stream=None)]}
+    srv._balance()
+    assert srv.slots[0][0].stream != srv.slots[1][0].stream
