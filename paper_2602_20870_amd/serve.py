@@ -56,6 +56,8 @@ def _distinct_queue_streams(n: int, device) -> list:
     kept when a tiny command on it completes while a spin of about 10 ms on each stream kept so far
     is still running.  If fewer than n pass, the rest are filled with untested candidates."""
     cands = [torch.cuda.Stream(device=device) for _ in range(4 * n)]
+    if not hasattr(torch.cuda, "_sleep"):      # no spin kernel in this torch build: untested streams
+        return cands[:n]
     t = torch.zeros(1, device=device)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(cands[0]):          # calibrate the spin: cycles per millisecond
