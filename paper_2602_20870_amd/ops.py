@@ -51,6 +51,10 @@ class Plan:
                  form: str = "split"):
         if not F.is_cuda:
             raise ValueError("F must be a cuda tensor")
+        if stacktype not in STACK_TYPES:
+            raise ValueError(f"stacktype must be one of {sorted(STACK_TYPES)}")
+        if form not in FORMS:
+            raise ValueError(f"form must be one of {sorted(FORMS)}")
         if F.dtype == torch.float64:
             intype = 1
         elif F.dtype == torch.complex128:
@@ -69,8 +73,6 @@ class Plan:
         self.persistent = _workspace(pb.value, F.device)
         scratch = _workspace(sb.value, F.device)
         h = ctypes.c_void_p()
-        if form not in FORMS:
-            raise ValueError(f"form must be one of {sorted(FORMS)}")
         check(L_.fgfrft_plan(_ptr(F), N, L, intype, STACK_TYPES[stacktype], FORMS[form], float(tau),
                              _ptr(self.persistent),
                              pb.value, _ptr(scratch), sb.value, _stream(stream), ctypes.byref(h)), "fgfrft_plan")
