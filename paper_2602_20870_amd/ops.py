@@ -39,6 +39,15 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _keep(stream, *tensors) -> None:
+    """Temporaries allocated here on the current stream but used by work queued on `stream`: tell
+    the caching allocator, so their memory is not handed out again before that work has run."""
+    if stream is not None:
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
 class Plan:
     """Offline stage of Algorithm 1 on the GPU for a unitary F.
 
@@ -131,6 +140,7 @@ class Plan:
         ws = _workspace(L_.fgfrft_update_workspace_bytes(self._h, n), self.device)
         check(L_.fgfrft_update(self._h, a.ctypes.data_as(P_double), n, _ptr(out), _ptr(ws), ws.numel(),
                                _stream(stream)), "fgfrft_update")
+        _keep(stream, ws)
         return out
 
     def update_dev(self, alphas_dev: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
@@ -146,10 +156,12 @@ class Plan:
             raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*N elements")
         L_ = lib()
         need = L_.fgfrft_update_workspace_bytes(self._h, n)
+        tmp = None
         if ws is None or ws.numel() < need:
-            ws = _workspace(need, self.device)
+            ws = tmp = _workspace(need, self.device)
         check(L_.fgfrft_update_dev(self._h, _ptr(alphas_dev), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
               "fgfrft_update_dev")
+        _keep(stream, tmp)
         return out
 
     def update_workspace_bytes(self, n_alpha: int) -> int:
@@ -167,6 +179,7 @@ class Plan:
         ws = _workspace(L_.fgfrft_apply_workspace_bytes(self._h, n, B, int(x_shared), chunk), self.device)
         check(L_.fgfrft_apply(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(Y), chunk,
                               _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply")
+        _keep(stream, ws)
         return Y
 
     def apply_direct(self, alphas, col_order, X: torch.Tensor, ncols: int | None = None, out: torch.Tensor | None = None,
@@ -178,10 +191,13 @@ class Plan:
         transformed); out: complex64 [N, ldy] with ldy >= ncols.  Columns with a bad order are NaN.
         """
         dev = self.device
+        tmps = []
         if not isinstance(alphas, torch.Tensor) or not alphas.is_cuda:
             alphas = torch.from_numpy(_alphas(alphas)).to(dev)
+            tmps.append(alphas)
         if not isinstance(col_order, torch.Tensor) or not col_order.is_cuda:
             col_order = torch.as_tensor(np.asarray(col_order, dtype=np.int32)).to(dev)
+            tmps.append(col_order)
         if alphas.dtype != torch.float64 or not alphas.is_contiguous():
             raise ValueError("alphas must be a contiguous float64 tensor")
         if col_order.dtype != torch.int32 or not col_order.is_contiguous():
@@ -206,9 +222,11 @@ class Plan:
         need = L_.fgfrft_apply_direct_workspace_bytes(self._h, ncols, ldx)
         if ws is None or ws.numel() < need:
             ws = _workspace(need, dev)
+            tmps.append(ws)
         check(L_.fgfrft_apply_direct(self._h, _ptr(alphas), alphas.numel(), _ptr(col_order), _ptr(X), xc, ncols, ldx,
                                      _ptr(out), out.shape[1], _ptr(ws), ws.numel(), _stream(stream)),
               "fgfrft_apply_direct")
+        _keep(stream, *tmps)
         return out
 
     def direct_workspace_bytes(self, ncols: int, ldx: int) -> int:
@@ -230,6 +248,7 @@ class Plan:
         check(L_.fgfrft_grad(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(GY),
                              dal.ctypes.data_as(P_double), _ptr(dX) if dX is not None else None, _ptr(ws),
                              ws.numel(), _stream(stream)), "fgfrft_grad")
+        _keep(stream, ws)
         return dal, dX
 
 
@@ -268,10 +287,12 @@ def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_re
         Y = out
     L_ = lib()
     need = L_.fgfrft_apply_operator_workspace_bytes(N, n, B, int(x_shared))
+    tmp = None
     if ws is None or ws.numel() < need:
-        ws = _workspace(need, Q.device)
+        ws = tmp = _workspace(need, Q.device)
     check(L_.fgfrft_apply_operator(_ptr(Q), N, n, int(adjoint), _ptr(X), xc, int(x_shared), B, _ptr(Y), int(y_real),
                                    _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply_operator")
+    _keep(stream, tmp)
     return Y
 
 
@@ -282,12 +303,13 @@ def gfrft_exact(V: torch.Tensor, Vh: torch.Tensor, theta: torch.Tensor, alpha: f
         if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
             raise ValueError(f"{name} must be a contiguous complex128 cuda matrix")
     N = V.shape[0]
-    if theta.dtype != torch.float64 or not theta.is_cuda or theta.numel() != N:
-        raise ValueError("theta must be a float64 cuda vector of length N")
+    if theta.dtype != torch.float64 or not theta.is_cuda or theta.numel() != N or not theta.is_contiguous():
+        raise ValueError("theta must be a contiguous float64 cuda vector of length N")
     if out is None:
         out = torch.empty((N, N), dtype=torch.complex128, device=V.device)
     L_ = lib()
     ws = _workspace(L_.fgfrft_gfrft_exact_workspace_bytes(N), V.device)
-    check(L_.fgfrft_gfrft_exact(_ptr(V), _ptr(Vh), _ptr(theta.contiguous()), N, float(alpha), _ptr(out), _ptr(ws),
+    check(L_.fgfrft_gfrft_exact(_ptr(V), _ptr(Vh), _ptr(theta), N, float(alpha), _ptr(out), _ptr(ws),
                                 ws.numel(), _stream(stream)), "fgfrft_gfrft_exact")
+    _keep(stream, ws)
     return out

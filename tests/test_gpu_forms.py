@@ -324,3 +324,31 @@ def test_fractional_mask_denoiser_reduces_the_error():
              f"alpha {float(model.alpha.detach()):.3f}")
     assert hist[-1] < 0.5 * noisy
     assert np.isfinite(float(model.alpha.detach()))
+
+
+def test_calls_on_an_explicit_stream_match_the_current_stream():
+    """update, apply, the direct route and the gradient queued on a side stream (the binding's
+    temporaries are kept for that stream) give bitwise the results of the same calls on the
+    current stream."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan
+    announce("explicit stream")
+    rng = np.random.default_rng(41)
+    F = synth.make_config("knn4096", seed=12, N=128, with_signals=False)["F"]
+    plan = Plan(torch.from_numpy(F).cuda(), 12)
+    alphas = rng.uniform(-2, 2, 5)
+    X = torch.from_numpy(synth.real_signals((5, 128, 8), rng).astype(np.float32)).cuda()
+    GY = torch.from_numpy((rng.standard_normal((5, 128, 8)) + 1j * rng.standard_normal((5, 128, 8)))
+                          .astype(np.complex64)).cuda()
+    Xd = X.permute(1, 0, 2).reshape(128, 40).contiguous()
+    cols = np.repeat(np.arange(5, dtype=np.int32), 8)
+    ref = (plan.update(alphas), plan.apply(alphas, X), plan.apply_direct(alphas, cols, Xd), plan.grad(alphas, X, GY))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    got = (plan.update(alphas, stream=side), plan.apply(alphas, X, stream=side),
+           plan.apply_direct(alphas, cols, Xd, stream=side), plan.grad(alphas, X, GY, stream=side))
+    side.synchronize()
+    for a, b in zip(ref[:3], got[:3]):
+        assert torch.equal(a, b)
+    assert np.array_equal(ref[3][0], got[3][0]) and torch.equal(ref[3][1], got[3][1])
