@@ -290,7 +290,7 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
                                                              const float2* __restrict__ gsc, int spw, int nstage,
                                                              int kb0, double* __restrict__ partial) {
   using LY = InnerLayout<CPLX, PC>;
-  constexpr int EB = LY::EB, NPL = CPLX ? 2 : 1;
+  constexpr int EB = LY::EB;
   extern __shared__ __align__(16) char smc[];
   char* sm = smc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
