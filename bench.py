@@ -32,10 +32,10 @@ COPY_BYTES = 1 << 31          # plain device copy used as the counter and bandwi
 # copy of COPY_BYTES that this script runs.  Valid only for the kernel sources with this digest:
 # once update.hip or internal.h change, the figure is reported as null until re-measured.
 UPDATE_TRAFFIC = {"fetch_bytes": 4363793625, "write_bytes": 34363689621,
-                  "source_sha256": "caa14e125d4b6884ce3fb2f8ba779d981013e56ee12d94e3423dbf4079832af1"}
+                  "source_sha256": "2a06964048fefa9ee809b16ce1d1b24fd50da25fb88f747f7d5c2136dfa28161"}
 # The same for one k_direct_pair launch over 64 signal columns of the knn4096 plan (direct.hip + internal.h).
 DIRECT_TRAFFIC = {"fetch_bytes": 2224839884, "write_bytes": 67108864, "ncols": 64,
-                  "source_sha256": "5f976c1bc9d4534f5a214563de20a46334b91a60bd621a0f038b9828e2cc2904"}
+                  "source_sha256": "fb36de014e2b5e3c0c7e6b4d04deb943d708ef5fdd38f57ef873ceaac378a6e8"}
 
 
 def log(msg):

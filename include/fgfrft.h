@@ -20,6 +20,14 @@
  *   - Pointers named *_dev are HIP device memory owned by the caller; the
  *     library never allocates or frees device memory.  Pointers without the
  *     suffix are host memory.
+ *   - Alignment: every device pointer is aligned to its element type (4 bytes
+ *     for float32 and int32; 8 for float64, complex64 and complex128); every
+ *     workspace (ws_dev) and the plan's persistent and scratch buffers are
+ *     256-byte aligned.  Two calls need more: Q_dev of fgfrft_apply_operator
+ *     16 bytes, and X_dev and Y_dev of fgfrft_apply and fgfrft_apply_operator
+ *     8 bytes, also for float32 data.  hipMalloc and the torch caching
+ *     allocator return blocks aligned to 256 bytes or more; a misaligned
+ *     pointer is an argument error (FGFRFT_EINVAL).
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Every call only enqueues work on it, except fgfrft_plan and
  *     fgfrft_grad, which synchronise it (they read results back to the host).
@@ -163,7 +171,7 @@ FGFRFT_API size_t fgfrft_apply_operator_workspace_bytes(int N, int n_alpha, int 
  * X_dev: [n_alpha][N][B] (x_shared = 0) or one [N][B] block for every order
  * (x_shared = 1), float32 (x_complex = 0) or complex64 (x_complex = 1).
  * Y_dev: complex64 [n_alpha][N][B], or float32 holding only the real part
- * when y_real = 1.  1 <= B <= 4096. */
+ * when y_real = 1.  1 <= B <= 4096.  Q_dev 16-byte, X_dev and Y_dev 8-byte aligned. */
 FGFRFT_API fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_alpha, int adjoint,
                                                const void* X_dev, int x_complex, int x_shared, int B,
                                                void* Y_dev, int y_real, void* ws_dev, size_t ws_bytes,

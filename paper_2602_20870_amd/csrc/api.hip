@@ -4,7 +4,10 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <map>
+#include <mutex>
 #include <new>
+#include <utility>
 
 namespace fgfrft {
 
@@ -22,6 +25,24 @@ fgfrft_status hip_fail(hipError_t e, const char* what) {
   return FGFRFT_EHIP;
 }
 
+// Dynamic-LDS limits set so far, per (kernel, device): the attribute belongs to the device the
+// call is made on, and a later plan may need more LDS than an earlier one (the per-tile
+// gradient kernel's LDS grows with L), so the largest value set is kept and only ever raised.
+static std::mutex g_lds_mu;
+static std::map<std::pair<const void*, int>, int> g_lds_set;
+
+hipError_t raise_lds_limit(const void* kern, int bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_lds_mu);
+  int& cur = g_lds_set[std::make_pair(kern, dev)];
+  if (cur >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) cur = bytes;
+  return e;
+}
+
 static bool valid_sizes(int N, int L, int intype, int stacktype) {
   if (N < 1 || N > 32768) { set_error("N=%d outside [1, 32768]", N); return false; }
   if (L < 1 || L > 64) { set_error("L=%d outside [1, 64]", L); return false; }
@@ -29,6 +50,8 @@ static bool valid_sizes(int N, int L, int intype, int stacktype) {
   if (stacktype != FGFRFT_STACK_FP32 && stacktype != FGFRFT_STACK_BF16X2) { set_error("bad stacktype %d", stacktype); return false; }
   return true;
 }
+
+static bool aligned(const void* p, size_t a) { return (uintptr_t)p % a == 0; }
 
 static size_t stack_elem_bytes(bool cplx) { return cplx ? 8 : 4; }
 
@@ -70,6 +93,10 @@ fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stack
   if (rc) return rc;
   if (form != FGFRFT_FORM_SPLIT && form != FGFRFT_FORM_STANDARD) { set_error("bad form %d", form); return FGFRFT_EINVAL; }
   if (!F_dev || !persistent_dev || !scratch_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if (!aligned(F_dev, 8) || !aligned(persistent_dev, 256) || !aligned(scratch_dev, 256)) {
+    set_error("F_dev must be 8-byte, persistent_dev and scratch_dev 256-byte aligned");
+    return FGFRFT_EINVAL;
+  }
   if (persistent_bytes < need_p) { set_error("persistent buffer %zu < %zu bytes", persistent_bytes, need_p); return FGFRFT_ENOMEM; }
   if (scratch_bytes < need_s) { set_error("scratch buffer %zu < %zu bytes", scratch_bytes, need_s); return FGFRFT_ENOMEM; }
   if (!(tau > 0.0)) tau = 1e-6;
@@ -125,7 +152,7 @@ fgfrft_status fgfrft_update(fgfrft_plan_t plan, const double* alphas, int n_alph
   fgfrft_status rc = check_alphas(p, alphas, n_alpha);
   if (rc) return rc;
   if (!Q_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
-  if ((uintptr_t)Q_dev % 8) { set_error("Q_dev must be 8-byte aligned"); return FGFRFT_EINVAL; }
+  if (!aligned(Q_dev, 8) || !aligned(ws_dev, 256)) { set_error("Q_dev must be 8-byte and ws_dev 256-byte aligned"); return FGFRFT_EINVAL; }
   const size_t need = update_ws_bytes(p, n_alpha);
   if (ws_bytes < need) { set_error("update workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
   hipStream_t s = (hipStream_t)stream;
@@ -139,7 +166,10 @@ fgfrft_status fgfrft_update_dev(fgfrft_plan_t plan, const double* alphas_dev, in
   const Plan* p = (const Plan*)plan;
   if (!alphas_dev || n_alpha < 1) { set_error("alphas_dev is NULL or n_alpha=%d < 1", n_alpha); return FGFRFT_EINVAL; }
   if (!Q_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
-  if ((uintptr_t)Q_dev % 8 || (uintptr_t)ws_dev % 256) { set_error("Q_dev must be 8-byte and ws_dev 256-byte aligned"); return FGFRFT_EINVAL; }
+  if (!aligned(alphas_dev, 8) || !aligned(Q_dev, 8) || !aligned(ws_dev, 256)) {
+    set_error("alphas_dev, Q_dev must be 8-byte and ws_dev 256-byte aligned");
+    return FGFRFT_EINVAL;
+  }
   const size_t need = update_ws_bytes(p, n_alpha);
   if (ws_bytes < need) { set_error("update workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
   return update_launch(p, alphas_dev, n_alpha, Q_dev, ws_dev, (hipStream_t)stream);
@@ -158,8 +188,8 @@ fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_alpha, int a
     return FGFRFT_EINVAL;
   }
   if (!Q_dev || !X_dev || !Y_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
-  if ((uintptr_t)Q_dev % 16 || (uintptr_t)X_dev % 8 || (uintptr_t)Y_dev % 8) {
-    set_error("Q_dev must be 16-byte and X_dev, Y_dev 8-byte aligned");
+  if (!aligned(Q_dev, 16) || !aligned(X_dev, 8) || !aligned(Y_dev, 8) || !aligned(ws_dev, 256)) {
+    set_error("Q_dev must be 16-byte, X_dev, Y_dev 8-byte and ws_dev 256-byte aligned");
     return FGFRFT_EINVAL;
   }
   const size_t need = apply_ws_bytes(N, n_alpha, B, x_shared);
@@ -256,7 +286,11 @@ fgfrft_status fgfrft_grad(fgfrft_plan_t plan, const double* alphas, int n_alpha,
   if (rc) return rc;
   if (B < 1 || B > 4096) { set_error("B=%d outside [1, 4096]", B); return FGFRFT_EINVAL; }
   if (!X_dev || !GY_dev || !dalpha || !ws_dev) { set_error("NULL pointer"); return FGFRFT_EINVAL; }
-  if ((uintptr_t)ws_dev % 256) { set_error("ws_dev must be 256-byte aligned"); return FGFRFT_EINVAL; }
+  const size_t xe = x_complex ? 8 : 4;
+  if (!aligned(X_dev, xe) || !aligned(GY_dev, 8) || !aligned(dX_dev, xe) || !aligned(ws_dev, 256)) {
+    set_error("X_dev, dX_dev must be element-aligned, GY_dev 8-byte and ws_dev 256-byte aligned");
+    return FGFRFT_EINVAL;
+  }
   if (p->stacktype != FGFRFT_STACK_FP32) { set_error("grad needs an FP32 power stack"); return FGFRFT_EUNSUPPORTED; }
   return grad_run(p, alphas, n_alpha, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, GY_dev, dalpha, dX_dev, ws_dev,
                   ws_bytes, (hipStream_t)stream);
@@ -288,6 +322,11 @@ fgfrft_status fgfrft_gfrft_exact(const void* V_dev, const void* Vh_dev, const do
   if (N < 1 || N > 32768) { set_error("N=%d outside [1, 32768]", N); return FGFRFT_EINVAL; }
   if (!std::isfinite(alpha)) { set_error("alpha is not finite"); return FGFRFT_EALPHA; }
   if (!V_dev || !Vh_dev || !theta_dev || !out_dev || !ws_dev) { set_error("NULL pointer"); return FGFRFT_EINVAL; }
+  if (!aligned(V_dev, 8) || !aligned(Vh_dev, 8) || !aligned(theta_dev, 8) || !aligned(out_dev, 8) ||
+      !aligned(ws_dev, 256)) {
+    set_error("V_dev, Vh_dev, theta_dev, out_dev must be 8-byte and ws_dev 256-byte aligned");
+    return FGFRFT_EINVAL;
+  }
   if (ws_bytes < fgfrft_gfrft_exact_workspace_bytes(N)) {
     set_error("workspace %zu < %zu bytes", ws_bytes, fgfrft_gfrft_exact_workspace_bytes(N));
     return FGFRFT_ENOMEM;

@@ -500,12 +500,7 @@ static void launch_apply2_t(unsigned g, hipStream_t s, const cplx64* Q, int N, i
                             int B, const float2* sc, void* Y, int nrb, int ncb) {
   constexpr int lds = NS * Apply2Layout<XC, K2>::SB;
   static_assert(lds <= 80 * 1024, "two workgroups per CU");
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_apply2<XC, YR, NS, K2, PRE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lds);
-    attr_set = true;
-  }
+  (void)raise_lds_limit((const void*)k_apply2<XC, YR, NS, K2, PRE>, lds);   // a failure surfaces at the launch
   k_apply2<XC, YR, NS, K2, PRE><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 

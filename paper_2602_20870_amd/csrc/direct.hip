@@ -499,12 +499,8 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
     set_error("direct grid too large");
     return FGFRFT_EUNSUPPORTED;
   }
-  static int attr_lds[2] = {0, 0};
   auto kp = bf ? k_direct_pair<true> : k_direct_pair<false>;
-  if (attr_lds[bf] < d.lds) {
-    FG_HIP(hipFuncSetAttribute((const void*)kp, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds));
-    attr_lds[bf] = d.lds;
-  }
+  FG_HIP(raise_lds_limit((const void*)kp, d.lds));
   kp<<<(unsigned)nb, 256, d.lds, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs, d.ncp, w.gam, d.CPR,
                                       d.G, d.nIB, d.ncb, w.part_re, w.part_im, w.part_neg);
   FG_LAUNCHED("direct");

@@ -595,7 +595,7 @@ static fgfrft_status inner_mfma_launch(const Plan* p, const cplx64* G, int nc, c
   const int nwg = inner_mfma_grid(p), spw = ceil_div(nstage, nwg);
   const int lds = (int)(2 * LY::stage_bytes(p->L));
   const int KB = LY::kp2(p->L) / 32;
-  FG_HIP(hipFuncSetAttribute((const void*)k_inner_mfma<CPLX, PC, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  FG_HIP(raise_lds_limit((const void*)k_inner_mfma<CPLX, PC, 1>, lds));
   // four k-blocks (one per wave pair) per pass over the positions
   for (int kb0 = 0; kb0 < KB; kb0 += 4)
     k_inner_mfma<CPLX, PC, 1><<<nwg, 64 * IM_NW, lds, s>>>(p->stack, p->P, p->N, p->L, G, nc, gsc, spw, nstage, kb0,
@@ -630,12 +630,8 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   const bool use_mfma = inner_mfma_ok(p);
 
   const size_t lds = inner_lds(p);
-  static bool attr[2] = {false, false};
-  if (!attr[p->cplx]) {
-    if (p->cplx) FG_HIP(hipFuncSetAttribute((const void*)k_inner<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    else FG_HIP(hipFuncSetAttribute((const void*)k_inner<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr[p->cplx] = true;
-  }
+  if (!use_mfma)
+    FG_HIP(raise_lds_limit(p->cplx ? (const void*)k_inner<true> : (const void*)k_inner<false>, (int)lds));
   std::vector<double> neg(n_alpha);
   for (int a = 0; a < n_alpha; ++a) neg[a] = -alphas[a];
   FG_HIP(hipMemcpyAsync(neg_dev, neg.data(), (size_t)n_alpha * 8, hipMemcpyHostToDevice, s));

@@ -71,6 +71,9 @@ struct Plan {
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
 fgfrft_status hip_fail(hipError_t e, const char* what);
+// Raises a kernel's dynamic-LDS limit to at least `bytes` on the current device (a no-op when an
+// earlier call on that device already set as much).  Safe to call from several host threads.
+hipError_t raise_lds_limit(const void* kern, int bytes);
 #define FG_HIP(call)                                              \
   do {                                                            \
     hipError_t e_ = (call);                                       \

@@ -523,11 +523,7 @@ static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, c
   const bool off32 = (size_t)5 * p->N * p->N * sizeof(cplx64) < ((size_t)1 << 32);
   auto kern = off32 ? k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, true, CAPV, PAIR>
                     : k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, false, CAPV, PAIR>;
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[off32]) {
-    FG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set[off32] = true;
-  }
+  FG_HIP(raise_lds_limit((const void*)kern, (int)lds));
   const int nI = ceil_div(p->N, TR), nJ = ceil_div(p->N, TC);
   kern<<<nI * nJ, NT, lds, s>>>(p->stack, p->P, p->N, p->L, nJ, table, epi, n_alpha, n_pad, (cplx64*)Q);
   FG_LAUNCHED("update");

@@ -82,6 +82,31 @@ def test_null_and_small_arguments_are_rejected_on_host(L):
     assert L.fgfrft_apply_direct_workspace_bytes(None, 4, 4) == 0
 
 
+
+def test_misaligned_pointers_are_rejected_on_host(L):
+    """Every argument but one pointer is valid; the misaligned pointer is refused before any HIP
+    call (the fake addresses are never dereferenced)."""
+    P = ctypes.c_void_p
+    h = ctypes.c_void_p()
+    pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.fgfrft_plan_bytes(64, 4, 1, 0, ctypes.byref(pb), ctypes.byref(sb)) == 0
+    for F, pers, scr in ((0x100004, 0x200000, 0x300000), (0x100000, 0x200080, 0x300000),
+                         (0x100000, 0x200000, 0x300010)):
+        rc = L.fgfrft_plan(P(F), 64, 4, 1, 0, 0, 0.0, P(pers), pb.value, P(scr), sb.value, None, ctypes.byref(h))
+        assert rc == -1 and not h.value and b"aligned" in L.fgfrft_last_error(), (F, pers, scr)
+    N, n, B = 64, 2, 64
+    ws = L.fgfrft_apply_operator_workspace_bytes(N, n, B, 0)
+    for Q, X, Y, W in ((0x100008, 0x200000, 0x300000, 0x400000), (0x100000, 0x200004, 0x300000, 0x400000),
+                       (0x100000, 0x200000, 0x300004, 0x400000), (0x100000, 0x200000, 0x300000, 0x400040)):
+        rc = L.fgfrft_apply_operator(P(Q), N, n, 0, P(X), 0, 0, B, P(Y), 0, P(W), ws, None)
+        assert rc == -1 and b"aligned" in L.fgfrft_last_error(), (Q, X, Y, W)
+    wsx = L.fgfrft_gfrft_exact_workspace_bytes(N)
+    for V, Vh, th, out, W in ((0x100004, 0x200000, 0x300000, 0x400000, 0x500000),
+                              (0x100000, 0x200000, 0x300000, 0x400000, 0x500010)):
+        rc = L.fgfrft_gfrft_exact(P(V), P(Vh), P(th), N, 0.5, P(out), P(W), wsx, None)
+        assert rc == -1 and b"aligned" in L.fgfrft_last_error(), (V, W)
+
+
 def test_strerror_names(L):
     for code in range(0, -8, -1):
         assert L.fgfrft_strerror(code)

@@ -308,6 +308,9 @@ def test_grad_outer_product_row_scales(xc, B):
 
 
 @pytest.mark.parametrize("N,L,n,cplxF", [(50, 9, 5, False),    # N % 8 != 0: per-tile inner products
+                                         # the same kernel after it, needing more LDS than 64 KB (69 KB,
+                                         # 90 KB): the limit set by the first call must be raised
+                                         (50, 30, 4, False), (42, 20, 3, True),
                                          (64, 64, 3, False),   # five k-blocks: two passes over the positions
                                          (40, 5, 70, False),   # two chunks of orders
                                          (56, 32, 4, True)])   # complex stack, three k-blocks
