@@ -96,7 +96,30 @@ class AdmissionError(RuntimeError):
     """A plan does not fit the server's HBM budget."""
 
 
+def _direct_blocks(plan, route: str) -> range:
+    """Direct-route block counts a slot set offers.  Only plans the matrix-core direct kernel takes
+    (real F, N % 32 == 0) offer the route; the plain kernel of the other configurations is far slower
+    than the operator route."""
+    if route != "operator" and not plan.complex and plan.N % 32 == 0:
+        return range(1, DIRECT_BLOCKS + 1)
+    return range(0)
+
+
 class _SlotSet:
+    @staticmethod
+    def device_bytes(plan, K: int, bmax: int, route: str) -> int:
+        """Device bytes one slot set of `plan` allocates (the constructor checks its tensors add up to
+        exactly this)."""
+        from ._lib import lib
+        N = plan.N
+        b = K * 8 + K * N * bmax * 4 + K * N * N * 8 + K * N * bmax * 8      # orders, X, Q, Y
+        b += plan.update_workspace_bytes(K)
+        b += max(256, int(lib().fgfrft_apply_operator_workspace_bytes(N, K, bmax, 0)))
+        nbs = _direct_blocks(plan, route)
+        b += sum(N * 64 * nb * 4 + 64 * nb * 4 + N * 64 * nb * 8 for nb in nbs)   # dX, dcols, dY
+        b += max([256] + [plan.direct_workspace_bytes(64 * nb, 64 * nb) for nb in nbs])
+        return b
+
     def __init__(self, plan: Plan, K: int, bmax: int, device, use_graphs: bool, route: str = "auto", stream=None):
         N = plan.N
         self.K, self.bmax, self.route = K, bmax, route
@@ -112,11 +135,8 @@ class _SlotSet:
         self.h_alphas = torch.zeros(K, dtype=torch.float64).pin_memory()
         self.h_X = torch.zeros((K, N, bmax), dtype=torch.float32).pin_memory()
         self.h_Y = torch.empty((K, N, bmax), dtype=torch.complex64).pin_memory()
-        # direct route: per block count nb, signals [N, 64 nb] side by side, column -> order index.
-        # Only plans the matrix-core direct kernel takes (real F, N % 32 == 0) offer it; the plain
-        # kernel of the other configurations is far slower than the operator route.
-        direct_ok = route != "operator" and not plan.complex and N % 32 == 0
-        self.dblocks = range(1, DIRECT_BLOCKS + 1) if direct_ok else range(0)
+        # direct route: per block count nb, signals [N, 64 nb] side by side, column -> order index
+        self.dblocks = _direct_blocks(plan, route)
         self.dX = {nb: torch.zeros((N, 64 * nb), dtype=torch.float32, device=device) for nb in self.dblocks}
         self.dcols = {nb: torch.zeros(64 * nb, dtype=torch.int32, device=device) for nb in self.dblocks}
         self.dY = {nb: torch.empty((N, 64 * nb), dtype=torch.complex64, device=device) for nb in self.dblocks}
@@ -136,6 +156,8 @@ class _SlotSet:
         self.plan = plan
         self.graphs = {}
         self.batch = None
+        if self.nbytes() != _SlotSet.device_bytes(plan, K, bmax, route):
+            raise AssertionError("slot-set byte count out of step with its allocation")
         if use_graphs:
             self._capture()
 
@@ -240,7 +262,7 @@ class _Request:
     def __init__(self, gid, alpha, X, t_arrive):
         self.gid, self.alpha = gid, float(alpha)
         self.X = np.asarray(X, dtype=np.float32)
-        self.B = self.X.shape[1]
+        self.B = self.X.shape[1] if self.X.ndim == 2 else 0
         self.t_arrive, self.t_launch, self.t_done, self.batch_size = t_arrive, None, None, 0
         self.future, self.route = Future(), None
 
@@ -274,26 +296,40 @@ class Server:
         self.streams = []
 
     # ------------------------------------------------------------------ admission
-    def footprint(self, N: int, L: int) -> int:
+    def footprint(self, N: int, L: int, complex_F: bool = False) -> int:
+        """Device bytes of a plan before it exists: its resident stack and projector (exact) plus the
+        operators, signal blocks and direct-route blocks of its S slot sets.  Their workspaces depend
+        on the plan and are added at admission, once it exists; the FP64 scratch of the offline
+        stage is released when planning ends and is not counted."""
         from ._lib import lib
         import ctypes
         pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
-        lib().fgfrft_plan_bytes(N, L, 1, 0, ctypes.byref(pb), ctypes.byref(sb))
+        if lib().fgfrft_plan_bytes(N, L, 0 if complex_F else 1, 0, ctypes.byref(pb), ctypes.byref(sb)) != 0:
+            raise ValueError(f"no plan for N={N}, L={L}: {lib().fgfrft_last_error().decode()}")
         per_set = self.K * N * N * 8 + self.K * N * self.bmax * (4 + 8)
-        if self.route != "operator" and N % 32 == 0:      # direct-route blocks (1..4 x 64 columns)
+        if self.route != "operator" and not complex_F and N % 32 == 0:   # direct-route blocks (1..4 x 64 columns)
             per_set += 10 * 64 * N * (4 + 8)
         return int(pb.value) + self.S * per_set
 
     def add_plan(self, gid, F: np.ndarray, L: int) -> None:
-        """Make graph `gid` resident; raises AdmissionError if it does not fit the budget."""
+        """Make graph `gid` resident; raises AdmissionError if it does not fit the budget.  The check
+        runs twice: on the footprint before anything is allocated, then on the exact bytes (stack,
+        projector and every slot-set tensor) once the plan exists, before its slot sets are made."""
+        F = np.asarray(F)
+        cplx = np.iscomplexobj(F)
         N = F.shape[0]
-        need = self.footprint(N, L)
-        if self.used + need > self.budget:
-            raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {need / 1e9:.2f} GB; "
-                                 f"{(self.budget - self.used) / 1e9:.2f} GB left")
+        left = self.budget - self.used
+        est = self.footprint(N, L, cplx)
+        if est > left:
+            raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {est / 1e9:.2f} GB; {left / 1e9:.2f} GB left")
         if not self.streams:
             self.streams = _distinct_queue_streams(self.n_queues, self.device)
-        plan = Plan(torch.from_numpy(np.ascontiguousarray(F)).to(self.device), L)
+        F = np.ascontiguousarray(F, dtype=np.complex128 if cplx else np.float64)
+        plan = Plan(torch.from_numpy(F).to(self.device), L)
+        need = plan.persistent.numel() + self.S * _SlotSet.device_bytes(plan, self.K, self.bmax, self.route)
+        if need > left:
+            del plan
+            raise AdmissionError(f"plan {gid} (N={N}, L={L}) needs {need / 1e9:.2f} GB; {left / 1e9:.2f} GB left")
         sets = [_SlotSet(plan, self.K, self.bmax, self.device, self.use_graphs, self.route, self.streams[0])
                 for _ in range(self.S)]
         self.plans[gid] = plan
@@ -326,8 +362,10 @@ class Server:
         plan = self.plans[gid]
         if not abs(alpha) < plan.L:
             raise ValueError(f"order {alpha} outside (-L, L)")
+        if np.iscomplexobj(X):
+            raise TypeError("the server takes real signal blocks (float32)")
         r = _Request(gid, alpha, X, time.perf_counter() if t_arrive is None else t_arrive)
-        if r.X.shape[0] != plan.N or not 1 <= r.B <= self.bmax:
+        if r.X.ndim != 2 or r.X.shape[0] != plan.N or not 1 <= r.B <= self.bmax:
             raise ValueError("X must be [N, B] with 1 <= B <= bmax")
         self.pending[gid].append(r)
         return r.future

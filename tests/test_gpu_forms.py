@@ -190,6 +190,39 @@ def test_serving_result_alone_equals_result_in_mix_and_oracle(route):
         assert np.array_equal(fe.result(), y)
 
 
+def test_serving_admission_counts_every_allocated_byte():
+    """A complex-F plan: the server's count is the plan's stack and projector plus every slot-set
+    tensor; a budget one byte short is refused after the plan exists (nothing stays counted or
+    resident), the exact budget is admitted, requests on it match the oracle, and complex signal
+    blocks are refused."""
+    torch = torch_cuda()
+    announce("serving admission, complex F N=64 L=8")
+    from paper_2602_20870_amd.serve import AdmissionError, Server
+    F = synth.haar_unitary(64, np.random.default_rng(5))
+    kw = dict(K=4, bmax=8, slot_sets=2, use_graphs=False)
+    probe = Server(hbm_budget=1 << 40, **kw)
+    probe.add_plan(0, F, 8)
+    need = probe.used
+    assert need == probe.plans[0].persistent.numel() + sum(s.nbytes() for s in probe.slots[0])
+    assert probe.footprint(64, 8, complex_F=True) < need
+    tight = Server(hbm_budget=need - 1, **kw)
+    with pytest.raises(AdmissionError):
+        tight.add_plan(0, F, 8)
+    assert tight.used == 0 and not tight.plans
+    srv = Server(hbm_budget=need, **kw)
+    srv.add_plan(0, F, 8)
+    assert srv.used == need
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((64, 5)).astype(np.float32)
+    fut = [srv.submit(0, a, X) for a in (0.4, -1.7, 1.0)]
+    srv.drain()
+    ref = O.Plan(F, 8)
+    for a, f in zip((0.4, -1.7, 1.0), fut):
+        assert rel_fro(f.result(), ref.combine(a) @ X.astype(np.float64)) <= TOL_FP32, a
+    with pytest.raises(TypeError):
+        srv.submit(0, 0.5, X.astype(np.complex64))
+
+
 # ----------------------------------------------------------------------------
 # standard-form ablation (Sec. IV-F, Table VI) on the GPU
 # ----------------------------------------------------------------------------

@@ -26,6 +26,29 @@ def test_admission_refuses_plans_beyond_the_budget(built):
     assert srv.used == 0 and not srv.plans
 
 
+def test_footprint_of_a_complex_plan_and_bad_requests(built):
+    import ctypes
+    from types import SimpleNamespace
+    from paper_2602_20870_amd.serve import Server
+    srv = Server(hbm_budget=1 << 40, K=4, bmax=8, slot_sets=2, use_graphs=False, device="cpu")
+    N, L = 96, 10
+    pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert _lib.lib().fgfrft_plan_bytes(N, L, 0, 0, ctypes.byref(pb), ctypes.byref(sb)) == 0
+    # complex stack (8 bytes per entry) and no direct-route blocks for complex F
+    assert pb.value >= 2 * L * N * N * 8 + N * N * 8
+    assert srv.footprint(N, L, complex_F=True) == pb.value + 2 * (4 * N * N * 8 + 4 * N * 8 * 12)
+    with pytest.raises(ValueError):        # complex F takes L <= 32
+        srv.footprint(N, 40, complex_F=True)
+    srv.plans[0] = SimpleNamespace(N=8, L=4)
+    with pytest.raises(TypeError):
+        srv.submit(0, 0.5, np.zeros((8, 2), np.complex64))
+    with pytest.raises(ValueError):
+        srv.submit(0, 0.5, np.zeros(8, np.float32))
+    with pytest.raises(ValueError):
+        srv.submit(0, 4.0, np.zeros((8, 2), np.float32))
+    assert not srv.pending[0]
+
+
 def test_poisson_trace_statistics():
     from paper_2602_20870_amd.serve import poisson_trace
     t, g, a, b = poisson_trace(20000, 5000.0, list(range(8)), 64, seed=1)
