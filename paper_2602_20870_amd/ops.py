@@ -39,6 +39,27 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _on_device(dev, **tensors) -> None:
+    """Every buffer handed to the library is read or written by its kernels as a raw pointer, so each
+    must be device memory on the GPU the call runs on (None entries are skipped)."""
+    for name, t in tensors.items():
+        if t is not None and (not t.is_cuda or t.device != dev):
+            raise ValueError(f"{name} must be a cuda tensor on {dev}")
+
+
+def _caller_ws(ws, need: int, dev):
+    """(workspace, temporary): the caller's workspace when it is large enough, else a new one.  A
+    caller's workspace must be contiguous uint8 memory on `dev` (its size is counted in bytes)."""
+    if ws is not None:
+        _on_device(dev, ws=ws)
+        if ws.dtype != torch.uint8 or not ws.is_contiguous():
+            raise ValueError("ws must be a contiguous uint8 tensor")
+        if ws.numel() >= need:
+            return ws, None
+    tmp = _workspace(need, dev)
+    return tmp, tmp
+
+
 def _keep(stream, *tensors) -> None:
     """Temporaries allocated here on the current stream but used by work queued on `stream`: tell
     the caching allocator, so their memory is not handed out again before that work has run."""
@@ -134,6 +155,7 @@ class Plan:
         n = a.size
         if out is None:
             out = torch.empty((n, self.N, self.N), dtype=torch.complex64, device=self.device)
+        _on_device(self.device, out=out)
         if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() < n * self.N * self.N:
             raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*N elements")
         L_ = lib()
@@ -149,16 +171,14 @@ class Plan:
 
         Orders with |alpha| >= L give NaN planes (no host-side check is possible).
         """
-        if alphas_dev.dtype != torch.float64 or not alphas_dev.is_cuda or not alphas_dev.is_contiguous():
+        _on_device(self.device, alphas_dev=alphas_dev, out=out)
+        if alphas_dev.dtype != torch.float64 or not alphas_dev.is_contiguous():
             raise ValueError("alphas_dev must be a contiguous float64 cuda tensor")
         n = alphas_dev.numel()
         if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() < n * self.N * self.N:
             raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*N elements")
         L_ = lib()
-        need = L_.fgfrft_update_workspace_bytes(self._h, n)
-        tmp = None
-        if ws is None or ws.numel() < need:
-            ws = tmp = _workspace(need, self.device)
+        ws, tmp = _caller_ws(ws, L_.fgfrft_update_workspace_bytes(self._h, n), self.device)
         check(L_.fgfrft_update_dev(self._h, _ptr(alphas_dev), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
               "fgfrft_update_dev")
         _keep(stream, tmp)
@@ -173,7 +193,7 @@ class Plan:
         n = a.size
         x_shared = X.dim() == 2
         B = X.shape[-1]
-        xc = _check_signal(X, n, self.N, x_shared)
+        xc = _check_signal(X, n, self.N, x_shared, self.device)
         Y = torch.empty((n, self.N, B), dtype=torch.complex64, device=self.device)
         L_ = lib()
         ws = _workspace(L_.fgfrft_apply_workspace_bytes(self._h, n, B, int(x_shared), chunk), self.device)
@@ -198,6 +218,7 @@ class Plan:
         if not isinstance(col_order, torch.Tensor) or not col_order.is_cuda:
             col_order = torch.as_tensor(np.asarray(col_order, dtype=np.int32)).to(dev)
             tmps.append(col_order)
+        _on_device(dev, alphas=alphas, col_order=col_order, X=X, out=out)
         if alphas.dtype != torch.float64 or not alphas.is_contiguous():
             raise ValueError("alphas must be a contiguous float64 tensor")
         if col_order.dtype != torch.int32 or not col_order.is_contiguous():
@@ -219,10 +240,8 @@ class Plan:
         if out.dim() != 2 or out.shape[0] != self.N or out.dtype != torch.complex64 or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous complex64 tensor of shape [{self.N}, ldy]")
         L_ = lib()
-        need = L_.fgfrft_apply_direct_workspace_bytes(self._h, ncols, ldx)
-        if ws is None or ws.numel() < need:
-            ws = _workspace(need, dev)
-            tmps.append(ws)
+        ws, tmp = _caller_ws(ws, L_.fgfrft_apply_direct_workspace_bytes(self._h, ncols, ldx), dev)
+        tmps.append(tmp)
         check(L_.fgfrft_apply_direct(self._h, _ptr(alphas), alphas.numel(), _ptr(col_order), _ptr(X), xc, ncols, ldx,
                                      _ptr(out), out.shape[1], _ptr(ws), ws.numel(), _stream(stream)),
               "fgfrft_apply_direct")
@@ -238,7 +257,8 @@ class Plan:
         n = a.size
         x_shared = X.dim() == 2
         B = X.shape[-1]
-        xc = _check_signal(X, n, self.N, x_shared)
+        xc = _check_signal(X, n, self.N, x_shared, self.device)
+        _on_device(self.device, GY=GY)
         if GY.dtype != torch.complex64 or not GY.is_contiguous() or tuple(GY.shape) != (n, self.N, B):
             raise ValueError("GY must be contiguous complex64 [n_alpha, N, B]")
         dX = torch.empty_like(X) if want_dX else None
@@ -252,8 +272,9 @@ class Plan:
         return dal, dX
 
 
-def _check_signal(X: torch.Tensor, n: int, N: int, x_shared: bool) -> int:
-    if not X.is_cuda or not X.is_contiguous():
+def _check_signal(X: torch.Tensor, n: int, N: int, x_shared: bool, dev) -> int:
+    _on_device(dev, X=X)
+    if not X.is_contiguous():
         raise ValueError("X must be a contiguous cuda tensor")
     if X.dtype == torch.float32:
         xc = 0
@@ -272,12 +293,15 @@ def _check_signal(X: torch.Tensor, n: int, N: int, x_shared: bool) -> int:
 def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_real: bool = False,
                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Y[a] = op(Q[a]) X[a] for a complex64 operator batch Q [n, N, N]."""
-    if Q.dtype != torch.complex64 or not Q.is_contiguous() or Q.dim() != 3:
+    if not Q.is_cuda:
+        raise ValueError("Q must be a cuda tensor")
+    if Q.dtype != torch.complex64 or not Q.is_contiguous() or Q.dim() != 3 or Q.shape[1] != Q.shape[2]:
         raise ValueError("Q must be contiguous complex64 [n, N, N]")
     n, N, _ = Q.shape
     x_shared = X.dim() == 2
     B = X.shape[-1]
-    xc = _check_signal(X, n, N, x_shared)
+    xc = _check_signal(X, n, N, x_shared, Q.device)
+    _on_device(Q.device, out=out)
     ydt = torch.float32 if y_real else torch.complex64
     if out is None:
         Y = torch.empty((n, N, B), dtype=ydt, device=Q.device)
@@ -286,10 +310,7 @@ def apply_operator(Q: torch.Tensor, X: torch.Tensor, adjoint: bool = False, y_re
             raise ValueError("out has the wrong dtype, shape or layout")
         Y = out
     L_ = lib()
-    need = L_.fgfrft_apply_operator_workspace_bytes(N, n, B, int(x_shared))
-    tmp = None
-    if ws is None or ws.numel() < need:
-        ws = tmp = _workspace(need, Q.device)
+    ws, tmp = _caller_ws(ws, L_.fgfrft_apply_operator_workspace_bytes(N, n, B, int(x_shared)), Q.device)
     check(L_.fgfrft_apply_operator(_ptr(Q), N, n, int(adjoint), _ptr(X), xc, int(x_shared), B, _ptr(Y), int(y_real),
                                    _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply_operator")
     _keep(stream, tmp)
@@ -303,10 +324,15 @@ def gfrft_exact(V: torch.Tensor, Vh: torch.Tensor, theta: torch.Tensor, alpha: f
         if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
             raise ValueError(f"{name} must be a contiguous complex128 cuda matrix")
     N = V.shape[0]
-    if theta.dtype != torch.float64 or not theta.is_cuda or theta.numel() != N or not theta.is_contiguous():
+    if tuple(V.shape) != (N, N) or tuple(Vh.shape) != (N, N):
+        raise ValueError("V and Vh must be N x N")
+    _on_device(V.device, Vh=Vh, theta=theta, out=out)
+    if theta.dtype != torch.float64 or theta.numel() != N or not theta.is_contiguous():
         raise ValueError("theta must be a contiguous float64 cuda vector of length N")
     if out is None:
         out = torch.empty((N, N), dtype=torch.complex128, device=V.device)
+    if out.dtype != torch.complex128 or not out.is_contiguous() or tuple(out.shape) != (N, N):
+        raise ValueError("out must be a contiguous complex128 N x N tensor")
     L_ = lib()
     ws = _workspace(L_.fgfrft_gfrft_exact_workspace_bytes(N), V.device)
     check(L_.fgfrft_gfrft_exact(_ptr(V), _ptr(Vh), _ptr(theta), N, float(alpha), _ptr(out), _ptr(ws),

@@ -359,6 +359,43 @@ def test_fractional_mask_denoiser_reduces_the_error():
     assert np.isfinite(float(model.alpha.detach()))
 
 
+def test_binding_refuses_buffers_the_kernels_cannot_use():
+    """Host tensors, workspaces that are not device bytes and mis-shaped outputs are refused on the
+    host before anything is launched; the plan still works afterwards."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan, apply_operator, gfrft_exact
+    announce("binding refuses foreign buffers")
+    N, L = 40, 6
+    plan = Plan(torch.from_numpy(_orth(N, 2, 9)).cuda(), L)
+    al = [0.3, -0.8]
+    with pytest.raises(ValueError, match="cuda"):
+        plan.update(al, out=torch.empty((2, N, N), dtype=torch.complex64))
+    ald = torch.tensor(al, dtype=torch.float64, device="cuda")
+    Q = torch.empty((2, N, N), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError, match="cuda"):
+        plan.update_dev(ald, out=Q, ws=torch.empty(1 << 16, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="uint8"):
+        plan.update_dev(ald, out=Q, ws=torch.empty(1 << 16, dtype=torch.float32, device="cuda"))
+    X = torch.randn((2, N, 3), device="cuda")
+    with pytest.raises(ValueError, match="cuda"):
+        plan.grad(al, X, torch.zeros((2, N, 3), dtype=torch.complex64))
+    with pytest.raises(ValueError, match="cuda"):
+        apply_operator(Q, X, out=torch.empty((2, N, 3), dtype=torch.complex64))
+    with pytest.raises(ValueError, match="cuda"):
+        plan.apply_direct(ald, torch.zeros(3, dtype=torch.int32, device="cuda"), X[0].contiguous(),
+                          out=torch.empty((N, 3), dtype=torch.complex64))
+    V = torch.eye(N, dtype=torch.complex128, device="cuda")
+    th = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for bad in (torch.empty((N, N), dtype=torch.complex64, device="cuda"),
+                torch.empty((N, N - 1), dtype=torch.complex128, device="cuda")):
+        with pytest.raises(ValueError, match="out"):
+            gfrft_exact(V, V, th, 0.5, out=bad)
+    Qr = plan.update(al).cpu().numpy()
+    ref = O.Plan(_orth(N, 2, 9), L)
+    for a, q in zip(al, Qr):
+        assert rel_fro(q, ref.combine(a)) <= TOL_FP32
+
+
 def test_calls_on_an_explicit_stream_match_the_current_stream():
     """update, apply, the direct route and the gradient queued on a side stream (the binding's
     temporaries are kept for that stream) give bitwise the results of the same calls on the
