@@ -113,6 +113,18 @@ def _exact_conj(F, alpha, decomposition=None):
     return (Z * np.exp(-1j * alpha * theta)[None, :]) @ Z.conj().T   # slip: e^{-j alpha theta}
 
 
+def _standard_with_split(F, alpha, L):
+    from oracle import fgfrft as m
+    return m.fgfrft_operator(F, alpha, L)           # slip: the -1 eigenspace still split off
+
+
+def _standard_stack_from_Pc(F, alpha, L):
+    from oracle import fgfrft as m
+    n = F.shape[0]
+    _, Pc, _ = m.split_projectors(F)
+    return m.fgfrft_combine(np.zeros((n, n)), m.power_stack(F, Pc, L), alpha)   # slip: M_0 = P_c, not I
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -129,6 +141,8 @@ MUTATIONS = {
     "grad_no_conj": ("grad", _grad_no_conj),
     "residual_sign": ("truncation_residual", _residual_sign),
     "exact_conj": ("gfrft_exact", _exact_conj),
+    "standard_with_split": ("fgfrft_operator_standard", _standard_with_split),
+    "standard_stack_from_Pc": ("fgfrft_operator_standard", _standard_stack_from_Pc),
 }
 
 _ORIG: dict = {}
