@@ -125,6 +125,46 @@ def _standard_stack_from_Pc(F, alpha, L):
     return m.fgfrft_combine(np.zeros((n, n)), m.power_stack(F, Pc, L), alpha)   # slip: M_0 = P_c, not I
 
 
+def _sampled_rows(variant):
+    def f(F, P, alphas, L, rows):
+        from oracle import fgfrft as m
+        rows = np.asarray(rows)
+        N = F.shape[0]
+        Pc = np.eye(N) - P
+        rr = [Pc[rows, :].astype(np.complex128)]
+        cc = [Pc[:, rows].astype(np.complex128)]
+        step = F.conj().T if variant == "inverse_rows" else F
+        for _ in range(L):
+            rr.append(rr[-1] @ step)                # slip (inverse_rows): rows of F^{-n} P_c
+            cc.append(F @ cc[-1])
+        out = np.empty((len(alphas), rows.size, N), dtype=np.complex128)
+        for a, al in enumerate(alphas):
+            c = m.coefficients(al, L)
+            acc = np.exp(1j * np.pi * al) * P[rows, :] + c[L] * rr[0]
+            for n in range(1, L + 1):
+                neg = cc[n].T if variant == "no_conj" else cc[n].conj().T   # slip (no_conj): plain transpose
+                acc = acc + c[L + n] * rr[n] + c[L - n] * neg
+            out[a] = acc
+        return out
+    return f
+
+
+def _symmetric_route_plus1(F, cos_tol=1e-10):
+    F = np.asarray(F, dtype=np.float64)
+    w, V = np.linalg.eigh(0.5 * (F + F.T))
+    m1 = w >= 1.0 - cos_tol                         # slip: the +1 eigenspace instead of -1
+    W = V[:, m1]
+    P = W @ W.T
+    nxt = float(w[~m1].min()) if (~m1).any() else float("nan")
+    return P, np.eye(F.shape[0]) - P, int(m1.sum()), nxt
+
+
+def _metrics_nmse_per_entry(E):
+    N = E.shape[0]
+    f2 = float(np.sum(np.abs(E) ** 2))
+    return dict(MSE=f2 / N ** 2, MAE=float(np.sum(np.abs(E))) / N ** 2, NMSE=f2 / N ** 2)   # slip: NMSE over N^2
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -143,6 +183,10 @@ MUTATIONS = {
     "exact_conj": ("gfrft_exact", _exact_conj),
     "standard_with_split": ("fgfrft_operator_standard", _standard_with_split),
     "standard_stack_from_Pc": ("fgfrft_operator_standard", _standard_stack_from_Pc),
+    "sampled_rows_no_conj": ("sampled_rows", _sampled_rows("no_conj")),
+    "sampled_rows_inverse_rows": ("sampled_rows", _sampled_rows("inverse_rows")),
+    "symmetric_route_plus1": ("projectors_symmetric_route", _symmetric_route_plus1),
+    "metrics_nmse_per_entry": ("error_metrics", _metrics_nmse_per_entry),
 }
 
 _ORIG: dict = {}

@@ -376,6 +376,13 @@ def test_sampled_rows_match_full_operator():
     S = O.sampled_rows(F, plan.P, al, 7, rows)
     for a, alpha in enumerate(al):
         assert np.max(np.abs(S[a] - plan.combine(alpha)[rows])) < 1e-13
+    # complex F: the negative powers' rows are conjugate transposes of columns (Proposition 2)
+    Fc = synth.haar_unitary(36, np.random.default_rng(32))
+    plan = O.Plan(Fc, 6)
+    rows = np.array([1, 35, 17])
+    S = O.sampled_rows(Fc, plan.P, al, 6, rows)
+    for a, alpha in enumerate(al):
+        assert np.max(np.abs(S[a] - plan.combine(alpha)[rows])) < 1e-12
 
 
 def test_symmetric_route_projector_matches_schur_route():
