@@ -394,6 +394,32 @@ def test_symmetric_route_projector_matches_schur_route():
     assert nxt > -1 + 1e-3
 
 
+def test_unitarity_defect_closed_form():
+    """max |F^H F - I| is 0 up to rounding for a unitary F, and (1+e)^2 - 1 for diag(1, 1+e)."""
+    assert O.unitarity_defect(synth.haar_unitary(30, np.random.default_rng(3))) < 1e-13
+    for e in (1e-3, -0.25):
+        assert abs(O.unitarity_defect(np.diag([1.0, 1.0 + e])) - abs((1.0 + e) ** 2 - 1.0)) < 1e-15
+
+
+def test_exact_gfrft_order_derivative_against_finite_differences():
+    """dF^alpha/dalpha against central differences of F^alpha (h = 1e-5, error O(h^2))."""
+    F = synth.haar_unitary(20, np.random.default_rng(8))
+    dec = O.spectral_decomposition(F)
+    h = 1e-5
+    for alpha in (0.3, -1.45):
+        fd = (O.gfrft_exact(F, alpha + h, dec) - O.gfrft_exact(F, alpha - h, dec)) / (2 * h)
+        assert _rel(O.gfrft_exact_grad(F, alpha, dec), fd) < 1e-8
+
+
+def test_apply_at_integer_order_is_the_graph_fourier_transform():
+    """Definition 2 at alpha = 1 (the operator is F exactly) and alpha = 0 (the identity)."""
+    F = _real_orthogonal_with_minus1(24, 3, 5)
+    plan = O.Plan(F, 6)
+    X = np.random.default_rng(9).standard_normal((24, 4))
+    assert np.max(np.abs(O.apply(plan.combine(1.0), X) - F @ X)) < 1e-13
+    assert np.max(np.abs(O.apply(plan.combine(0.0), X) - X)) < 1e-13
+
+
 def test_degenerate_sizes():
     for f in (np.array([[1.0]]), np.array([[-1.0]]), np.array([[0.0, 1.0], [1.0, 0.0]])):
         plan = O.Plan(f, 3)
