@@ -35,12 +35,16 @@ hipError_t raise_lds_limit(const void* kern, int bytes) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lock(g_lds_mu);
-  int& cur = g_lds_set[std::make_pair(kern, dev)];
-  if (cur >= bytes) return hipSuccess;
-  e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) cur = bytes;
-  return e;
+  try {   // nothing may unwind through the C ABI
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    int& cur = g_lds_set[std::make_pair(kern, dev)];
+    if (cur >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
+  } catch (...) {
+    return hipErrorOutOfMemory;
+  }
 }
 
 static bool valid_sizes(int N, int L, int intype, int stacktype) {
@@ -292,8 +296,13 @@ fgfrft_status fgfrft_grad(fgfrft_plan_t plan, const double* alphas, int n_alpha,
     return FGFRFT_EINVAL;
   }
   if (p->stacktype != FGFRFT_STACK_FP32) { set_error("grad needs an FP32 power stack"); return FGFRFT_EUNSUPPORTED; }
-  return grad_run(p, alphas, n_alpha, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, GY_dev, dalpha, dX_dev, ws_dev,
-                  ws_bytes, (hipStream_t)stream);
+  try {   // host tables of the order loop: an allocation failure must not unwind through the C ABI
+    return grad_run(p, alphas, n_alpha, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, GY_dev, dalpha, dX_dev,
+                    ws_dev, ws_bytes, (hipStream_t)stream);
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return FGFRFT_ENOMEM;
+  }
 }
 
 const char* fgfrft_strerror(int status) {
