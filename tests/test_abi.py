@@ -107,6 +107,35 @@ def test_misaligned_pointers_are_rejected_on_host(L):
         assert rc == -1 and b"aligned" in L.fgfrft_last_error(), (V, W)
 
 
+def test_header_is_plain_c_and_the_library_links_from_c(L, tmp_path):
+    """The boundary is usable from C: the header compiles as C99 with pedantic warnings as errors,
+    and a C program linked against the library queries plan sizes (host-only calls)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_abi.c"
+    src.write_text(
+        "#include <stdio.h>\n#include \"fgfrft.h\"\n"
+        "int main(void) {\n"
+        "  size_t p = 0, s = 0;\n"
+        "  fgfrft_status rc = fgfrft_plan_bytes(64, 8, FGFRFT_IN_F64, FGFRFT_STACK_FP32, &p, &s);\n"
+        "  printf(\"%d %zu %s\\n\", (int)rc, p, fgfrft_strerror(FGFRFT_EALPHA));\n"
+        "  return rc == FGFRFT_OK ? 0 : 1;\n}\n")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = tmp_path / "use_abi"
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-L", libdir, "-lfgfrft", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    rc, pbytes, msg = r.stdout.split(" ", 2)
+    assert rc == "0" and int(pbytes) >= 2 * 8 * 64 * 64 * 4 + 64 * 64 * 4
+    assert msg.startswith("order out of range")
+
+
 def test_strerror_names(L):
     for code in range(0, -8, -1):
         assert L.fgfrft_strerror(code)
