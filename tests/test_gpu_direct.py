@@ -95,14 +95,14 @@ def test_direct_agrees_with_update_then_apply():
 
 
 @pytest.mark.parametrize("case", ["dft64_complex_x", "haar96_real_x", "real_n70", "real_f_complex_x", "bf16x2",
-                                  "bf16x2_n70"])
+                                  "bf16x2_n70", "haar96_bf16x2"])
 def test_direct_other_configurations(case):
     """Complex F, complex signals and N % 32 != 0 take the plain kernel; a BF16X2 stack with
-    N % 32 == 0 takes the bf16 matrix-core kernel, with N = 70 the plain one."""
+    N % 32 == 0 takes the bf16 matrix-core kernel, with N = 70 or a complex F the plain one."""
     torch = torch_cuda()
     announce(f"direct plain kernel: {case}")
     seeds = {"dft64_complex_x": 21, "haar96_real_x": 22, "real_n70": 23, "real_f_complex_x": 24, "bf16x2": 25,
-             "bf16x2_n70": 26}
+             "bf16x2_n70": 26, "haar96_bf16x2": 27}
     rng = np.random.default_rng(seeds[case])
     stacktype, tol, L = "fp32", TOL_FP32, 10
     if case == "dft64_complex_x":
@@ -117,6 +117,10 @@ def test_direct_other_configurations(case):
     elif case == "real_f_complex_x":
         F = synth.make_config("knn4096", seed=6, N=96, with_signals=False)["F"]
         X = synth.complex_signals((96, 11), rng)
+    elif case == "haar96_bf16x2":       # complex F with the BF16 hi/lo stack: plain kernel
+        F = synth.haar_unitary(96, rng)
+        X = synth.real_signals((96, 9), rng)
+        stacktype, tol = "bf16x2", TOL_BF16X2
     else:
         n = 128 if case == "bf16x2" else 70
         F = synth.make_config("knn4096", seed=7, N=n, with_signals=False)["F"]

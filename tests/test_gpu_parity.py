@@ -174,6 +174,18 @@ def test_update_complex_haar_L10():
     _check_update(torch, F, 10, alphas)
 
 
+@pytest.mark.parametrize("case,L", [("haar96", 10), ("dft64", 20)])
+def test_update_complex_f_bf16x2(case, L):
+    """BF16 hi/lo stack of a complex F (both complex strip shapes: 2L padded to 32 and to 64; the
+    DFT matrix has a 16-dimensional -1 eigenspace, so P is exercised too)."""
+    torch = torch_cuda()
+    announce(f"update complex F bf16x2 {case} L={L}")
+    F = synth.haar_unitary(96, np.random.default_rng(40 + L)) if case == "haar96" else synth.dft_matrix(64)
+    alphas = np.array([0.5, -1.7, 0.15, 2.3, -0.001, 1.0])
+    worst, *_ = _check_update(torch, F, L, alphas, tol=TOL_BF16X2, stacktype="bf16x2")
+    print(case, "bf16x2 worst rel err", worst)
+
+
 def test_update_integer_orders_and_adjoint_symmetry():
     torch = torch_cuda()
     announce("update integer orders / adjoint symmetry")
