@@ -165,6 +165,28 @@ def _metrics_nmse_per_entry(E):
     return dict(MSE=f2 / N ** 2, MAE=float(np.sum(np.abs(E))) / N ** 2, NMSE=f2 / N ** 2)   # slip: NMSE over N^2
 
 
+def _pointwise_bound_no_pi(theta, alpha, L):
+    theta = np.asarray(theta, dtype=np.float64)
+    return (np.abs(np.sin(np.pi * alpha)) / np.cos(theta / 2.0)        # slip: the 1/pi dropped
+            * (1.0 / (L + 1 - alpha) + 1.0 / (L + 1 + alpha)))
+
+
+def _frobenius_tight_prefactor(theta, in_minus1, alpha, L):
+    th = np.asarray(theta)[~np.asarray(in_minus1)]
+    pre = 2 * (L + 1) * abs(np.sin(np.pi * alpha)) / (np.pi * ((L + 1) ** 2 + alpha ** 2))   # slip: + alpha^2
+    return float(pre * np.sqrt(np.sum(1.0 / np.cos(th / 2.0) ** 2)))
+
+
+def _worst_case_nmse_no_N(theta, in_minus1, alpha, L):
+    in_minus1 = np.asarray(in_minus1)
+    th = np.asarray(theta)[~in_minus1]
+    if th.size == 0:
+        return 0.0
+    ccmin = float(np.min(np.abs(np.cos(th / 2.0))))
+    return float(4 * (L + 1) ** 2 * np.sin(np.pi * alpha) ** 2
+                 / (np.pi ** 2 * ((L + 1) ** 2 - alpha ** 2) ** 2) * th.size / ccmin ** 2)   # slip: not over N
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -187,6 +209,9 @@ MUTATIONS = {
     "sampled_rows_inverse_rows": ("sampled_rows", _sampled_rows("inverse_rows")),
     "symmetric_route_plus1": ("projectors_symmetric_route", _symmetric_route_plus1),
     "metrics_nmse_per_entry": ("error_metrics", _metrics_nmse_per_entry),
+    "pointwise_bound_no_pi": ("pointwise_bound", _pointwise_bound_no_pi),
+    "frobenius_tight_prefactor": ("frobenius_bound_tight", _frobenius_tight_prefactor),
+    "worst_case_nmse_no_N": ("worst_case_nmse_bound", _worst_case_nmse_no_N),
 }
 
 _ORIG: dict = {}

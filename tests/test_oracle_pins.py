@@ -226,6 +226,32 @@ def test_pointwise_bound_theorem1(L):
         assert np.all(R <= O.pointwise_bound(theta, alpha, L) * (1 + 1e-12) + 1e-15)
 
 
+def test_theorem1_bound_is_twice_the_leading_order_residual():
+    """The bound's size, not only its validity.  c_n = (-1)^n sin(pi alpha) / (pi (alpha - n)), so each
+    tail of R_L is a sum of (-e^{j theta})^n / (n -+ alpha) over n > L.  To leading order in 1/L that is
+    a geometric tail, its first term over 1 + e^{j theta}: modulus 1 / (2 cos(theta/2) (L+1 -+ alpha)).
+    Two tails in phase make half of Theorem 1's bound.  So sup_theta |R_L| / bound tends to 1/2 from
+    above, with an O(1/L) excess."""
+    theta = np.linspace(-np.pi + 1e-3, np.pi - 1e-3, 4001)
+    for L in (10, 20, 32, 48, 64):
+        for alpha in (-1.75, -0.5, 0.25, 0.55, 1.3):
+            ratio = np.max(np.abs(O.truncation_residual(theta, alpha, L)) / O.pointwise_bound(theta, alpha, L))
+            assert 0.5 < ratio < 0.5 + 0.3 / L, (L, alpha, ratio)
+
+
+def test_theorem2_bounds_follow_from_theorem1():
+    """Theorem 2's first bound is the root-sum-square of Theorem 1's pointwise bound over the
+    eigenphases outside the -1 eigenspace; the worst-case NMSE bound is the simplified Frobenius
+    bound squared over N (NMSE = ||E||_F^2 / N)."""
+    F = _random_unitary(40, 12)
+    _, theta, m1 = O.spectral_decomposition(F)
+    for alpha, L in ((0.55, 10), (-1.37, 24)):
+        rss = np.sqrt(np.sum(O.pointwise_bound(theta[~m1], alpha, L) ** 2))
+        assert abs(O.frobenius_bound_tight(theta, m1, alpha, L) - rss) <= 1e-13 * rss
+        bs = O.frobenius_bound_simplified(theta, m1, alpha, L)
+        assert abs(O.worst_case_nmse_bound(theta, m1, alpha, L) - bs ** 2 / 40) <= 1e-13 * bs ** 2
+
+
 def test_residual_limit_at_minus_one_is_cos():
     """Remark (obstruction): the series at theta = pi tends to cos(pi alpha), so R_L(pi) -> j sin(pi alpha)."""
     for alpha in (0.55, -1.3):
