@@ -49,6 +49,21 @@ def test_footprint_of_a_complex_plan_and_bad_requests(built):
     assert not srv.pending[0]
 
 
+def test_route_choice_boundary():
+    """Direct iff the batch fits DIRECT_BLOCKS x 64 columns and the extra column blocks cost less
+    than the operators the batch would otherwise write and read: one block always goes direct,
+    each further block needs 0.15 (2L+1) more orders (L = 32: 9.75 per block)."""
+    from paper_2602_20870_amd.serve import DIRECT_BLOCKS, prefer_direct
+    assert DIRECT_BLOCKS == 4
+    assert all(prefer_direct(n, 1, 32) for n in (1, 2, 16))
+    assert not prefer_direct(9, 2, 32) and prefer_direct(10, 2, 32)
+    assert not prefer_direct(19, 3, 32) and prefer_direct(20, 3, 32)
+    assert not prefer_direct(29, 4, 32) and prefer_direct(30, 4, 32)
+    assert not prefer_direct(1000, 5, 32)
+    # a shorter stack makes the operator route's per-order bytes relatively dearer
+    assert prefer_direct(4, 2, 10) and not prefer_direct(3, 2, 10)
+
+
 def test_poisson_trace_statistics():
     from paper_2602_20870_amd.serve import poisson_trace
     t, g, a, b = poisson_trace(20000, 5000.0, list(range(8)), 64, seed=1)
