@@ -34,3 +34,11 @@ def test_caller_workspace_must_be_device_bytes(ops):
     cuda0 = torch.device("cuda", 0)
     with pytest.raises(ValueError, match="cuda"):
         ops._caller_ws(torch.zeros(1024, dtype=torch.uint8), 256, cuda0)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback path: without the built library the first call raises."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(os.path.dirname(_lib.LIB_PATH), "no_such_libfgfrft.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
