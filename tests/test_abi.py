@@ -136,6 +136,18 @@ def test_header_is_plain_c_and_the_library_links_from_c(L, tmp_path):
     assert msg.startswith("order out of range")
 
 
+def test_binding_constants_match_the_header_enums():
+    """Status codes, stack types and forms the binding passes as integers are the header's values."""
+    text = open(HEADER).read()
+    enum = {name: int(val) for name, val in re.findall(r"\b(FGFRFT_[A-Z0-9_]+)\s*=\s*(-?\d+)", text)}
+    for code, name in _lib.STATUS.items():
+        assert enum[name] == code, name
+    from paper_2602_20870_amd import ops
+    assert ops.STACK_TYPES == {"fp32": enum["FGFRFT_STACK_FP32"], "bf16x2": enum["FGFRFT_STACK_BF16X2"]}
+    assert ops.FORMS == {"split": enum["FGFRFT_FORM_SPLIT"], "standard": enum["FGFRFT_FORM_STANDARD"]}
+    assert (enum["FGFRFT_IN_C128"], enum["FGFRFT_IN_F64"]) == (0, 1)   # the intype ops.Plan passes
+
+
 def test_strerror_names(L):
     for code in range(0, -8, -1):
         assert L.fgfrft_strerror(code)
