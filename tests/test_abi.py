@@ -136,6 +136,28 @@ def test_header_is_plain_c_and_the_library_links_from_c(L, tmp_path):
     assert msg.startswith("order out of range")
 
 
+def test_binding_signatures_match_the_header_prototypes():
+    """Every prototype's parameter count equals the binding's ctypes argtypes, and pointer
+    parameters are passed as pointers: a shifted argument would hand a kernel a wrong address."""
+    import ctypes
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    protos = dict((name, params) for name, params in
+                  re.findall(r"FGFRFT_API\s+[\w\s\*]+?\b(fgfrft_\w+)\s*\(([^)]*)\)\s*;", text))
+    assert set(protos) == set(_lib.SIGNATURES)
+    for name, params in protos.items():
+        ps = [p.strip() for p in params.split(",")] if params.strip() not in ("", "void") else []
+        _, argtypes = _lib.SIGNATURES[name]
+        assert len(ps) == len(argtypes), name
+        scalar = {"int": ctypes.c_int, "double": ctypes.c_double, "size_t": ctypes.c_size_t,
+                  "fgfrft_plan_t": ctypes.c_void_p}
+        for p, t in zip(ps, argtypes):
+            if "*" in p:
+                assert t is ctypes.c_void_p or t is ctypes.c_char_p or issubclass(t, ctypes._Pointer), (name, p, t)
+            else:   # a size_t passed as a 32-bit int would leave the register's upper half undefined
+                ctype = p.replace("const ", "").split()[0]
+                assert scalar[ctype] is t, (name, p, t)
+
+
 def test_binding_constants_match_the_header_enums():
     """Status codes, stack types and forms the binding passes as integers are the header's values."""
     text = open(HEADER).read()
