@@ -29,7 +29,7 @@ __all__ = [
     "TAU_SNAP", "unitarity_defect", "spectral_decomposition", "coefficients",
     "coefficient_derivatives", "gfrft_exact", "gfrft_exact_grad",
     "split_projectors", "projectors_symmetric_route", "power_stack",
-    "fgfrft_combine", "fgfrft_operator", "fgfrft_operator_standard",
+    "fgfrft_combine", "term_matrix", "fgfrft_combine_many", "fgfrft_operator", "fgfrft_operator_standard",
     "fgfrft_operator_eigen", "dQ_dalpha", "dQ_dalpha_eigen", "apply",
     "grad", "truncation_residual", "pointwise_bound", "frobenius_error_exact",
     "frobenius_bound_tight", "frobenius_bound_simplified",
@@ -165,6 +165,44 @@ def fgfrft_combine(P: np.ndarray, M: list[np.ndarray], alpha: float) -> np.ndarr
     Q = np.exp(1j * np.pi * alpha) * P + c[L] * M[0]
     for n in range(1, L + 1):
         Q = Q + c[L + n] * M[n] + c[L - n] * M[n].conj().T
+    return Q
+
+
+def term_matrix(M: list[np.ndarray]) -> np.ndarray:
+    """The 2L+1 real-coefficient terms of the online combination, one per row:
+    [P_c, M_1, .., M_L, M_1^H, .., M_L^H], each flattened row-major -> [(2L+1), N*N]."""
+    L = len(M) - 1
+    N = M[0].shape[0]
+    T = np.empty((2 * L + 1, N * N), dtype=M[0].dtype)
+    T[0] = M[0].reshape(-1)
+    for n in range(1, L + 1):
+        T[n] = M[n].reshape(-1)
+        T[L + n] = M[n].conj().T.reshape(-1)
+    return T
+
+
+def fgfrft_combine_many(P: np.ndarray, T: np.ndarray, alphas) -> np.ndarray:
+    """Q(alpha_a) for a batch of orders (Algorithm 1's online combination, Proposition 2).
+
+    The real coefficients [c_0, c_1..c_L, c_{-1}..c_{-L}] of every order form the rows of C,
+    and C T (one matrix product over the terms of :func:`term_matrix`) is the sum
+    c_0 P_c + sum_n (c_n M_n + c_{-n} M_n^H) for all orders at once; e^{j pi alpha} P is added
+    per order.  Returns complex128 [n_alpha, N, N].
+    """
+    alphas = np.atleast_1d(np.asarray(alphas, dtype=np.float64))
+    K = T.shape[0]
+    L = (K - 1) // 2
+    N = P.shape[0]
+    C = np.empty((alphas.size, K))
+    for a, al in enumerate(alphas):
+        c = coefficients(al, L)                 # c[L + n] = c_n
+        C[a, 0] = c[L]
+        C[a, 1:L + 1] = c[L + 1:]
+        C[a, L + 1:] = c[L - 1::-1]
+    S = (C @ T).reshape(alphas.size, N, N)
+    Q = np.empty((alphas.size, N, N), dtype=np.complex128)
+    for a, al in enumerate(alphas):
+        Q[a] = S[a] + np.exp(1j * np.pi * al) * P
     return Q
 
 

@@ -187,6 +187,60 @@ def _worst_case_nmse_no_N(theta, in_minus1, alpha, L):
                  / (np.pi ** 2 * ((L + 1) ** 2 - alpha ** 2) ** 2) * th.size / ccmin ** 2)   # slip: not over N
 
 
+def _frobenius_tight_keeps_minus1(theta, in_minus1, alpha, L):
+    th = np.asarray(theta)                          # slip: the -1 phases left in the sum
+    pre = 2 * (L + 1) * abs(np.sin(np.pi * alpha)) / (np.pi * ((L + 1) ** 2 - alpha ** 2))
+    return float(pre * np.sqrt(np.sum(1.0 / np.cos(th / 2.0) ** 2)))
+
+
+def _frobenius_simplified_full_N(theta, in_minus1, alpha, L):
+    in_minus1 = np.asarray(in_minus1)
+    th = np.asarray(theta)[~in_minus1]
+    ccmin = float(np.min(np.abs(np.cos(th / 2.0))))
+    pre = 2 * (L + 1) * np.sqrt(in_minus1.size) * abs(np.sin(np.pi * alpha))   # slip: sqrt(N), not sqrt(N - r)
+    return float(pre / (np.pi * ccmin * ((L + 1) ** 2 - alpha ** 2)))
+
+
+def _worst_case_nmse_full_N(theta, in_minus1, alpha, L):
+    in_minus1 = np.asarray(in_minus1)
+    N = in_minus1.size
+    th = np.asarray(theta)[~in_minus1]
+    if th.size == 0:
+        return 0.0
+    ccmin = float(np.min(np.abs(np.cos(th / 2.0))))
+    return float(4 * (L + 1) ** 2 * np.sin(np.pi * alpha) ** 2
+                 / (np.pi ** 2 * ((L + 1) ** 2 - alpha ** 2) ** 2) * N / (N * ccmin ** 2))   # slip: N for N - r
+
+
+def _term_matrix(variant):
+    def f(M):
+        L = len(M) - 1
+        N = M[0].shape[0]
+        T = np.empty((2 * L + 1, N * N), dtype=M[0].dtype)
+        T[0] = M[0].reshape(-1)
+        for n in range(1, L + 1):
+            T[n] = M[n].reshape(-1)
+            T[L + n] = (M[n].T if variant == "transpose_only" else M[n]).reshape(-1)   # slip: no conjugate / no adjoint
+        return T
+    return f
+
+
+def _combine_many_coefficients_unreversed(P, T, alphas):
+    from oracle import fgfrft as m
+    alphas = np.atleast_1d(np.asarray(alphas, dtype=np.float64))
+    K = T.shape[0]
+    L = (K - 1) // 2
+    N = P.shape[0]
+    C = np.empty((alphas.size, K))
+    for a, al in enumerate(alphas):
+        c = m.coefficients(al, L)
+        C[a, 0] = c[L]
+        C[a, 1:L + 1] = c[L + 1:]
+        C[a, L + 1:] = c[:L]                        # slip: c_{-L}..c_{-1} against M_1^H..M_L^H
+    S = (C @ T).reshape(alphas.size, N, N)
+    return np.stack([S[a] + np.exp(1j * np.pi * al) * P for a, al in enumerate(alphas)])
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -212,6 +266,12 @@ MUTATIONS = {
     "pointwise_bound_no_pi": ("pointwise_bound", _pointwise_bound_no_pi),
     "frobenius_tight_prefactor": ("frobenius_bound_tight", _frobenius_tight_prefactor),
     "worst_case_nmse_no_N": ("worst_case_nmse_bound", _worst_case_nmse_no_N),
+    "frobenius_tight_keeps_minus1": ("frobenius_bound_tight", _frobenius_tight_keeps_minus1),
+    "frobenius_simplified_full_N": ("frobenius_bound_simplified", _frobenius_simplified_full_N),
+    "worst_case_nmse_full_N": ("worst_case_nmse_bound", _worst_case_nmse_full_N),
+    "term_matrix_no_adjoint": ("term_matrix", _term_matrix("no_adjoint")),
+    "term_matrix_transpose_only": ("term_matrix", _term_matrix("transpose_only")),
+    "combine_many_coefficients_unreversed": ("fgfrft_combine_many", _combine_many_coefficients_unreversed),
 }
 
 _ORIG: dict = {}

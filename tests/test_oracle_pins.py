@@ -479,3 +479,92 @@ def test_table4_accuracy_columns_on_a_haar_draw():
     assert abs(m["MAE"] * np.sqrt(N) - mae_printed) <= g["rel_tol"] * mae_printed, (m["MAE"], mae_printed)
     # and the expectation sum_{|n| > L} c_n^2 itself (L - 1 or L + 1 would be ~10% off)
     assert abs(m["NMSE"] - O.parseval_tail(alpha, L)) <= 0.03 * O.parseval_tail(alpha, L)
+
+
+# ----------------------------------------------------------------------------
+# the batched online combination (Algorithm 1 for many orders as one product)
+# ----------------------------------------------------------------------------
+def test_batched_combination_dft_closed_form():
+    """C T over the term matrix, plus e^{j pi alpha} P, equals the DFT's closed form
+    Q = sum_m q_m P_m (projectors from F^4 = I, coefficients by quadrature) for every order."""
+    N, L = 64, 10
+    F = synth.dft_matrix(N)
+    Ps, thetas = _dft_projectors(F)
+    plan = O.Plan(F, L)
+    alphas = [0.55, -1.3, 1.99, 0.0, 1.0]
+    Qs = O.fgfrft_combine_many(plan.P, O.term_matrix(plan.M), alphas)
+    for a, alpha in enumerate(alphas):
+        qs = []
+        for t in thetas:
+            if t == np.pi:
+                qs.append(np.exp(1j * np.pi * alpha))
+            else:
+                qs.append(sum(_quad_coeff(alpha, n).real * np.exp(1j * n * t) for n in range(-L, L + 1)))
+        closed = sum(q * P for q, P in zip(qs, Ps))
+        assert _rel(Qs[a], closed) < 1e-12, alpha
+
+
+def test_batched_combination_integer_orders_are_powers():
+    """Real orthogonal F with three eigenvalues at -1: integer orders give F^m, negative ones (F^|m|)^T."""
+    F = _real_orthogonal_with_minus1(14, 3, 21)
+    plan = O.Plan(F, 6)
+    assert plan.r_minus1 == 3
+    ms = [-3, -1, 0, 2, 5]
+    Qs = O.fgfrft_combine_many(plan.P, O.term_matrix(plan.M), [float(m) for m in ms])
+    for a, m in enumerate(ms):
+        ref = np.linalg.matrix_power(F, abs(m))
+        ref = ref if m >= 0 else ref.T
+        assert np.max(np.abs(Qs[a] - ref)) < 1e-13, m
+
+
+# ----------------------------------------------------------------------------
+# Theorem 2 and the worst-case NMSE bound with a nonempty -1 eigenspace
+# ----------------------------------------------------------------------------
+def _dft_phase_multiset(N):
+    """Eigenphases of the unitary DFT, N divisible by 4, from the multiplicities N/4+1, N/4, N/4, N/4-1
+    of the eigenvalues 1, -j, -1, j (traces of the projectors built from F^4 = I, checked below)."""
+    q = N // 4
+    return {0.0: q + 1, -np.pi / 2: q, np.pi: q, np.pi / 2: q - 1}
+
+
+def test_theorem2_bounds_with_minus1_eigenspace_on_dft():
+    """DFT, N = 64 (r_{-1} = 16).  Theorem 2's first bound is the root-sum-square of Theorem 1 over the
+    48 phases outside I_{-1} (17 at 0, 16 at -pi/2, 15 at pi/2); the simplified bound is sqrt(N - r_{-1})
+    times Theorem 1 at the worst remaining phase (cos_{c,min} = cos(pi/4)); the worst-case NMSE bound
+    is that squared over N.  The -1 phases must be left out: at theta = pi Theorem 1 is infinite."""
+    N = 64
+    F = synth.dft_matrix(N)
+    Ps, thetas = _dft_projectors(F)
+    mult = _dft_phase_multiset(N)
+    assert [round(np.trace(P).real) for P in Ps] == [mult[t] for t in thetas]
+    _, theta, m1 = O.spectral_decomposition(F)
+    assert int(m1.sum()) == mult[np.pi] == 16
+    for alpha, L in ((0.55, 10), (-1.37, 24), (1.9, 32)):
+        b = {t: float(O.pointwise_bound(np.array([t]), alpha, L)[0]) for t in mult if t != np.pi}
+        rss = np.sqrt(sum(mult[t] * b[t] ** 2 for t in b))
+        tight = O.frobenius_bound_tight(theta, m1, alpha, L)
+        assert abs(tight - rss) <= 1e-12 * rss, (alpha, L, tight, rss)
+        simp = O.frobenius_bound_simplified(theta, m1, alpha, L)
+        want = np.sqrt(N - 16) * b[np.pi / 2]
+        assert abs(simp - want) <= 1e-12 * want, (alpha, L, simp, want)
+        wc = O.worst_case_nmse_bound(theta, m1, alpha, L)
+        assert abs(wc - want ** 2 / N) <= 1e-12 * want ** 2 / N
+        # the identity side: ||F^alpha - Q||_F from the closed-form projectors
+        plan = O.Plan(F, L)
+        Fa = sum(np.exp(1j * alpha * t) * P for P, t in zip(Ps, thetas))
+        Qc = plan.combine(alpha)
+        ex = O.frobenius_error_exact(theta, m1, alpha, L)
+        assert abs(np.linalg.norm(Fa - Qc) - ex) <= 1e-10 * max(ex, 1e-12)
+        assert ex <= tight <= simp
+        assert np.linalg.norm(Fa - Qc) ** 2 / N <= wc
+
+
+def test_bounds_vanish_when_every_eigenvalue_is_minus_one():
+    """F = -I: I_{-1} is everything, the split reproduces F^alpha exactly and each bound is 0."""
+    F = -np.eye(8)
+    _, theta, m1 = O.spectral_decomposition(F)
+    assert m1.all()
+    for alpha, L in ((0.55, 10), (-1.3, 4)):
+        assert O.worst_case_nmse_bound(theta, m1, alpha, L) == 0.0
+        assert O.frobenius_bound_tight(theta, m1, alpha, L) == 0.0
+        assert O.frobenius_error_exact(theta, m1, alpha, L) == 0.0
