@@ -158,6 +158,20 @@ FGFRFT_API fgfrft_status fgfrft_update(fgfrft_plan_t plan, const double* alphas,
 FGFRFT_API fgfrft_status fgfrft_update_dev(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha,
                                            void* Q_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* The same update as fgfrft_update_dev for callers that cannot allocate (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): no workspace
+ * argument, and the call allocates nothing.  Its coefficient and epilogue tables live in a
+ * fixed 2.25 MiB device array inside the library, one copy per GPU, held until the process
+ * ends; its device address is looked up once per device, on the first call made with that
+ * device current.  1 <= n_alpha <= 4096, else FGFRFT_EINVAL.  Q_dev and alphas_dev as for
+ * fgfrft_update_dev (8-byte aligned; out-of-range orders give NaN planes).  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (different streams or host
+ * threads with work in flight at the same time) race on it and must be serialised by the
+ * caller; calls in order on one stream are safe, since each call rewrites every table entry
+ * it reads. */
+FGFRFT_API fgfrft_status fgfrft_update_dev_static(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha,
+                                                  void* Q_dev, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Apply to graph signals (Definition 2)
  * ------------------------------------------------------------------------- */

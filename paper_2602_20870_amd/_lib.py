@@ -23,6 +23,7 @@ SIGNATURES = {
     "fgfrft_update_workspace_bytes": (c_size_t, [c_void_p, c_int]),
     "fgfrft_update": (c_int, [c_void_p, P_double, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
     "fgfrft_update_dev": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "fgfrft_update_dev_static": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "fgfrft_apply_operator_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int]),
     "fgfrft_apply_operator": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int, c_void_p,
                                       c_int, c_void_p, c_size_t, c_void_p]),

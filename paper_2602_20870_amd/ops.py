@@ -184,6 +184,19 @@ class Plan:
         _keep(stream, tmp)
         return out
 
+    def update_dev_static(self, alphas_dev: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """update_dev without a workspace: the library's fixed per-GPU tables (at most 4096 orders per
+        call; calls that overlap on one GPU race on those tables)."""
+        _on_device(self.device, alphas_dev=alphas_dev, out=out)
+        if alphas_dev.dtype != torch.float64 or not alphas_dev.is_contiguous():
+            raise ValueError("alphas_dev must be a contiguous float64 cuda tensor")
+        n = alphas_dev.numel()
+        if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() < n * self.N * self.N:
+            raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*N elements")
+        check(lib().fgfrft_update_dev_static(self._h, _ptr(alphas_dev), n, _ptr(out), _stream(stream)),
+              "fgfrft_update_dev_static")
+        return out
+
     def update_workspace_bytes(self, n_alpha: int) -> int:
         return int(lib().fgfrft_update_workspace_bytes(self._h, n_alpha))
 
