@@ -87,7 +87,8 @@ typedef struct fgfrft_plan_s* fgfrft_plan_t;
  * ------------------------------------------------------------------------- */
 
 /* Bytes of device memory a plan needs.  `persistent` must stay allocated for
- * the plan's lifetime (power stack, projector, tables); `scratch` is FP64
+ * the plan's lifetime (power stack, projector and, for real F, an N x 32
+ * float32 slot for the -1 eigenspace basis); `scratch` is FP64
  * working memory used only during fgfrft_plan and free again when it returns.
  * Limits: 1 <= N <= 32768, 1 <= L <= 64 (L <= 32 for complex F). */
 FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype,
@@ -107,7 +108,8 @@ FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stackty
  *   3. M_0 = P_c = I - P, M_n = F M_{n-1} for n = 1..L, with the drift
  *      ||M_n^H M_n - P_c||_F / sqrt(N) checked at n = ceil(L/2) and n = L;
  *   4. M_1..M_L, their adjoints M_1^H..M_L^H (= F^{-n} P_c, Proposition 2)
- *      and P stored in `stacktype` format in `persistent_dev`.
+ *      and P stored in `stacktype` format in `persistent_dev`; for real F
+ *      with r_minus1 <= 32 also W as float32 (used by fgfrft_apply).
  * Synchronises `stream`.  F_dev is only read during the call.
  * On success *out receives a host-side handle (free with fgfrft_destroy);
  * persistent_dev must outlive it. */
@@ -118,11 +120,13 @@ FGFRFT_API fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype
 
 /* Facts measured while planning: rank of the -1 eigenspace, max|F^H F - I|,
  * the larger of the two drift values, the largest remaining column norm of
- * F + I when the pivoted QR stopped (0 if r_minus1 = 0) and the smallest
- * column norm it pivoted on (how close the nearest non-(-1) eigenvalue is).
- * Any pointer may be NULL. */
+ * F + I when the pivoted QR stopped (0 if r_minus1 = 0), the smallest
+ * column norm it pivoted on (how close the nearest non-(-1) eigenvalue is)
+ * and the threshold tau the QR stopped at (1e-6 when the plan was given
+ * tau <= 0).  Any pointer may be NULL. */
 FGFRFT_API fgfrft_status fgfrft_plan_info(fgfrft_plan_t plan, int* r_minus1, double* unitarity_defect,
-                                          double* drift, double* stop_norm, double* last_pivot_norm);
+                                          double* drift, double* stop_norm, double* last_pivot_norm,
+                                          double* tau_used);
 
 /* Device pointers to the resident data: stack (2L matrices of N*N elements of
  * the stack format: slot n-1 holds M_n, slot L+n-1 holds M_n^H, n = 1..L) and
@@ -192,13 +196,23 @@ FGFRFT_API fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_a
                                                void* stream);
 
 /* Workspace bytes for fgfrft_apply: operators for `chunk` orders at a time
- * plus the update and apply workspaces.  chunk <= 0 selects min(n_alpha, 16). */
-FGFRFT_API size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared,
-                                               int chunk);
+ * plus the update and apply workspaces.  chunk <= 0 selects min(n_alpha, 16).
+ * Depends on x_complex: the real-F route below keeps 4 bytes per operator
+ * entry instead of 8. */
+FGFRFT_API size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_complex,
+                                               int x_shared, int chunk);
 
-/* Y[a] = Q_L^{alphas[a]} X[a]: fgfrft_update into the workspace, `chunk`
- * orders at a time, followed by fgfrft_apply_operator.  Same layouts as
- * fgfrft_apply_operator with y_real = 0. */
+/* Y[a] = Q_L^{alphas[a]} X[a] (Definition 2): the operator update into the
+ * workspace, `chunk` orders at a time, then the apply.  Same layouts as
+ * fgfrft_apply_operator with y_real = 0.
+ * Real-F route: for a real F (FGFRFT_IN_F64) the powers and P are real, so
+ * Definition 1 splits as Q = R + j sin(pi alpha) P with R = Re Q real, and
+ * P = W W^T with W an orthonormal basis of the -1 eigenspace.  When F is
+ * real, X is real, N % 32 == 0, B % 64 == 0 and r_minus1 <= 32 (the plan
+ * keeps W as float32 then), the update writes only R (float32, half the
+ * bytes of Q) and the apply computes Y = R X + j sin(pi alpha) W (W^T X),
+ * the rank-r term from the signals' projections.  Every other case forms the
+ * complex64 Q and calls fgfrft_apply_operator's kernels. */
 FGFRFT_API fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha,
                                       const void* X_dev, int x_complex, int x_shared, int B,
                                       void* Y_dev, int chunk, void* ws_dev, size_t ws_bytes,
@@ -275,6 +289,16 @@ FGFRFT_API size_t fgfrft_gfrft_exact_workspace_bytes(int N);
 FGFRFT_API fgfrft_status fgfrft_gfrft_exact(const void* V_dev, const void* Vh_dev, const double* theta_dev, int N,
                                             double alpha, void* out_dev, void* ws_dev, size_t ws_bytes,
                                             void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Measurement helper (not part of the method)
+ * ------------------------------------------------------------------------- */
+
+/* Writes `bytes` zero bytes to dst_dev with 16-byte nontemporal stores from a
+ * grid-stride streaming kernel: the write bandwidth this device attains, the
+ * ceiling for the store-dominated operator update.  dst_dev 16-byte aligned,
+ * bytes a nonzero multiple of 16, else FGFRFT_EINVAL.  Enqueues on `stream`. */
+FGFRFT_API fgfrft_status fgfrft_probe_write(void* dst_dev, size_t bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Errors

@@ -17,7 +17,7 @@ SIGNATURES = {
     "fgfrft_plan_bytes": (c_int, [c_int, c_int, c_int, c_int, P_size_t, P_size_t]),
     "fgfrft_plan": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_double, c_void_p, c_size_t, c_void_p,
                             c_size_t, c_void_p, ctypes.POINTER(c_void_p)]),
-    "fgfrft_plan_info": (c_int, [c_void_p, P_int, P_double, P_double, P_double, P_double]),
+    "fgfrft_plan_info": (c_int, [c_void_p, P_int, P_double, P_double, P_double, P_double, P_double]),
     "fgfrft_plan_buffers": (c_int, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "fgfrft_destroy": (None, [c_void_p]),
     "fgfrft_update_workspace_bytes": (c_size_t, [c_void_p, c_int]),
@@ -27,7 +27,7 @@ SIGNATURES = {
     "fgfrft_apply_operator_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int]),
     "fgfrft_apply_operator": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_int, c_int, c_void_p,
                                       c_int, c_void_p, c_size_t, c_void_p]),
-    "fgfrft_apply_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int]),
+    "fgfrft_apply_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "fgfrft_apply": (c_int, [c_void_p, P_double, c_int, c_void_p, c_int, c_int, c_int, c_void_p, c_int,
                              c_void_p, c_size_t, c_void_p]),
     "fgfrft_apply_direct_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int]),
@@ -39,6 +39,7 @@ SIGNATURES = {
     "fgfrft_gfrft_exact_workspace_bytes": (c_size_t, [c_int]),
     "fgfrft_gfrft_exact": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_size_t,
                                    c_void_p]),
+    "fgfrft_probe_write": (c_int, [c_void_p, c_size_t, c_void_p]),
     "fgfrft_strerror": (ctypes.c_char_p, [c_int]),
     "fgfrft_last_error": (ctypes.c_char_p, []),
 }

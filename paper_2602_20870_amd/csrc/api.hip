@@ -81,7 +81,9 @@ fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype, size_t*
   const bool cplx = intype == FGFRFT_IN_C128;
   if (cplx && L > 32) { set_error("complex F supports L <= 32"); return FGFRFT_EUNSUPPORTED; }
   const size_t NN = (size_t)N * N;
-  if (persistent) *persistent = align_up((size_t)2 * L * NN * stack_elem_bytes(cplx), 256) + align_up(NN * (cplx ? 8 : 4), 256);
+  if (persistent)
+    *persistent = align_up((size_t)2 * L * NN * stack_elem_bytes(cplx), 256) + align_up(NN * (cplx ? 8 : 4), 256) +
+                  (cplx ? 0 : align_up((size_t)N * kWCols * sizeof(float), 256));
   if (scratch) *scratch = plan_scratch_bytes(N, L, cplx);
   return FGFRFT_OK;
 }
@@ -116,6 +118,7 @@ fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stack
   p->stack_elem_bytes = stack_elem_bytes(p->cplx);
   p->stack = persistent_dev;
   p->P = (char*)persistent_dev + align_up((size_t)2 * L * N * N * p->stack_elem_bytes, 256);
+  if (!p->cplx) p->W = (float*)((char*)p->P + align_up((size_t)N * N * sizeof(float), 256));
   rc = plan_build(p, F_dev, tau, scratch_dev, scratch_bytes, (hipStream_t)stream);
   if (rc) { delete p; return rc; }
   *out = (fgfrft_plan_t)p;
@@ -123,7 +126,7 @@ fgfrft_status fgfrft_plan(const void* F_dev, int N, int L, int intype, int stack
 }
 
 fgfrft_status fgfrft_plan_info(fgfrft_plan_t plan, int* r_minus1, double* unitarity_defect, double* drift,
-                               double* stop_norm, double* last_pivot_norm) {
+                               double* stop_norm, double* last_pivot_norm, double* tau_used) {
   if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
   const Plan* p = (const Plan*)plan;
   if (r_minus1) *r_minus1 = p->r_minus1;
@@ -131,6 +134,7 @@ fgfrft_status fgfrft_plan_info(fgfrft_plan_t plan, int* r_minus1, double* unitar
   if (drift) *drift = p->drift;
   if (stop_norm) *stop_norm = p->stop_norm;
   if (last_pivot_norm) *last_pivot_norm = p->last_pivot_norm;
+  if (tau_used) *tau_used = p->tau;
   return FGFRFT_OK;
 }
 
@@ -207,10 +211,13 @@ static int apply_chunk(int n_alpha, int chunk) {
   return chunk < n_alpha ? chunk : n_alpha;
 }
 
-size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared, int chunk) {
+size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_complex, int x_shared, int chunk) {
   if (!plan || n_alpha < 1 || B < 1) return 0;
   const Plan* p = (const Plan*)plan;
   const int ch = apply_chunk(n_alpha, chunk);
+  if (apply_real_supported(p, x_complex, B))   // real F, real X: R = Re Q (4 bytes per entry)
+    return align_up((size_t)n_alpha * 8, 256) + align_up((size_t)ch * p->N * p->N * 4, 256) + update_ws_bytes(p, ch) +
+           apply_real_ws_bytes(p->N, ch, B, x_shared, p->r_minus1);
   return align_up((size_t)n_alpha * 8, 256) + align_up((size_t)ch * p->N * p->N * 8, 256) + update_ws_bytes(p, ch) +
          apply_ws_bytes(p->N, ch, B, x_shared);
 }
@@ -228,22 +235,28 @@ fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha
     return FGFRFT_EINVAL;
   }
   const int ch = apply_chunk(n_alpha, chunk);
-  const size_t need = fgfrft_apply_workspace_bytes(plan, n_alpha, B, x_shared, chunk);
+  const size_t need = fgfrft_apply_workspace_bytes(plan, n_alpha, B, x_complex, x_shared, chunk);
   if (ws_bytes < need) { set_error("apply workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  // real F and real signals: the update writes R = Re Q only and the apply adds the imaginary part
+  // sin(pi alpha) P X from P's rank-r factor (same operator, half the operator bytes)
+  const bool realF = apply_real_supported(p, x_complex, B);
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws_dev;
   double* al = (double*)base; base += align_up((size_t)n_alpha * 8, 256);
-  void* Qc = base; base += align_up((size_t)ch * p->N * p->N * 8, 256);
+  void* Qc = base; base += align_up((size_t)ch * p->N * p->N * (realF ? 4 : 8), 256);
   void* uws = base; base += update_ws_bytes(p, ch);
   void* aws = base;
   FG_HIP(hipMemcpyAsync(al, alphas, (size_t)n_alpha * 8, hipMemcpyHostToDevice, s));
   const size_t NB = (size_t)p->N * B;
   for (int a0 = 0; a0 < n_alpha; a0 += ch) {
     const int nc = n_alpha - a0 < ch ? n_alpha - a0 : ch;
-    if ((rc = update_launch(p, al + a0, nc, Qc, uws, s))) return rc;
+    if ((rc = update_launch(p, al + a0, nc, Qc, uws, s, realF))) return rc;
     const void* xa = x_shared ? X_dev : (const void*)((const char*)X_dev + a0 * NB * (x_complex ? 8 : 4));
     void* ya = (char*)Y_dev + a0 * NB * 8;
-    if ((rc = apply_launch(Qc, p->N, nc, 0, xa, x_complex ? 1 : 0, x_shared ? 1 : 0, B, ya, 0, aws, s))) return rc;
+    if (realF) rc = apply_real_launch(p, (const float*)Qc, nc, al + a0, (const float*)xa, x_shared ? 1 : 0, B,
+                                      (cplx64*)ya, aws, s);
+    else rc = apply_launch(Qc, p->N, nc, 0, xa, x_complex ? 1 : 0, x_shared ? 1 : 0, B, ya, 0, aws, s);
+    if (rc) return rc;
   }
   return FGFRFT_OK;
 }

@@ -505,6 +505,252 @@ static void launch_apply2_t(unsigned g, hipStream_t s, const cplx64* Q, int N, i
 }
 
 
+
+// ---------------------------------------------------------------- real-F apply
+// For real F the operator splits as Q = R + j sin(pi alpha) P with R = Re Q real and P = W W^T of
+// rank r_minus1 (Definition 1 with real powers), so Y = R X + j sin(pi alpha) W (W^T X): the
+// update writes R only (4 N^2 bytes per order instead of 8 N^2) and this apply streams it once.
+//
+// One pass over the real signals X [nx][N][B] for both things the real-F apply needs from them:
+// the column maxima of a CR-row chunk (as k_colmax) and, for q < r, the chunk's part of
+// Z[a][q][b] = (W^T X[a])[q][b] (W row-major [N][kWCols]).  Grid (column blocks x orders, row
+// chunks); 4 row groups x 64 columns per workgroup, fixed-order sums over the row groups.
+__global__ __launch_bounds__(256) void k_colmax_wtx(const float* __restrict__ X, int N, int B,
+                                                    const float* __restrict__ W, int r, float* __restrict__ pmax,
+                                                    float* __restrict__ pz) {
+  __shared__ float red[4][kWCols + 1][64];
+  const int ncb = (B + 63) / 64;
+  const int a = blockIdx.x / ncb, ch = blockIdx.y, nch = gridDim.y;
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int b = (blockIdx.x % ncb) * 64 + c;
+  float m = 0.f, acc[kWCols];
+#pragma unroll
+  for (int q = 0; q < kWCols; ++q) acc[q] = 0.f;
+  if (b < B) {
+    const int i1 = (ch + 1) * CR < N ? (ch + 1) * CR : N;
+    for (int i = ch * CR + rg; i < i1; i += 4) {
+      const float x = X[((size_t)a * N + i) * B + b];
+      m = fmaxf(m, fabsf(x));
+      const float4* w = (const float4*)(W + (size_t)i * kWCols);
+#pragma unroll
+      for (int q4 = 0; q4 < kWCols / 4; ++q4) {
+        if (4 * q4 >= r) break;
+        const float4 v = w[q4];
+        acc[4 * q4] = fmaf(v.x, x, acc[4 * q4]);
+        acc[4 * q4 + 1] = fmaf(v.y, x, acc[4 * q4 + 1]);
+        acc[4 * q4 + 2] = fmaf(v.z, x, acc[4 * q4 + 2]);
+        acc[4 * q4 + 3] = fmaf(v.w, x, acc[4 * q4 + 3]);
+      }
+    }
+  }
+  red[rg][kWCols][c] = m;
+#pragma unroll
+  for (int q = 0; q < kWCols; ++q) red[rg][q][c] = acc[q];
+  __syncthreads();
+  const size_t part = (size_t)a * nch + ch;
+  if (rg == 0 && b < B)
+    pmax[part * B + b] = fmaxf(fmaxf(red[0][kWCols][c], red[1][kWCols][c]), fmaxf(red[2][kWCols][c], red[3][kWCols][c]));
+  for (int e = threadIdx.x; e < r * 64; e += 256) {
+    const int q = e / 64, cc = e % 64, bb = (blockIdx.x % ncb) * 64 + cc;
+    if (bb < B) pz[(part * r + q) * B + bb] = (red[0][q][cc] + red[1][q][cc]) + (red[2][q][cc] + red[3][q][cc]);
+  }
+}
+
+// Z[a][q][b] = sum over the row chunks of the partials, in chunk order.
+__global__ __launch_bounds__(256) void k_zsum(const float* __restrict__ pz, int nch, int r, int B, int nx,
+                                              float* __restrict__ Z) {
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)nx * r * B) return;
+  const int b = (int)(idx % B), q = (int)((idx / B) % r), a = (int)(idx / ((size_t)r * B));
+  float s = 0.f;
+  for (int c = 0; c < nch; ++c) s += pz[(((size_t)a * nch + c) * r + q) * B + b];
+  Z[((size_t)a * kWCols + q) * B + b] = s;
+}
+
+// Y[a] = R[a] X[a] + j sin(pi alpha_a) W Z[a] for N % 32 == 0 and B % 64 == 0: the streaming
+// kernel's structure (128 output rows x 64 signals per workgroup, direct-load LDS ring of NS
+// stages of 32 k) with a real operator: each 32-wide k stage holds 16 KB of R (128-byte row
+// segments, 16-byte chunks swizzled by row) and 8 KB of signals; per 16-wide k step a wave splits
+// its R fragment once (2 parts) and issues 3 products per 32-signal block.
+constexpr int RS_NS = 3, RS_K2 = 32;
+struct ApplyRealLayout {
+  static constexpr int QB = M2 * RS_K2 * 4, XB = RS_K2 * 64 * 4, SB = QB + XB;
+  static constexpr int QROW = RS_K2 * 4, CPR = QROW / 16, RPI = 1024 / QROW;
+  static constexpr int LW = QB / 4096 + XB / 4096;
+};
+
+// PRE: X is the pre-split signal block of xsplit_launch (fp16 hi / lo parts in fragment order), so the
+// waves read their signal fragments with plain 16-byte LDS loads instead of each splitting them.
+template <bool PRE>
+__global__ __launch_bounds__(256, 2) void k_apply_real(const float* __restrict__ R, int N, int n_alpha,
+                                                       const void* __restrict__ X, int x_shared, int B,
+                                                       const float2* __restrict__ xscale,
+                                                       const double* __restrict__ alphas, const float* __restrict__ W,
+                                                       int r, const float* __restrict__ Z, cplx64* __restrict__ Y,
+                                                       int nrb, int ncb) {
+  using LY = ApplyRealLayout;
+  constexpr int CPR = LY::CPR, RPI = LY::RPI, NS = RS_NS, K2 = RS_K2;
+  static_assert(RPI % CPR == 0, "row swizzle constant per lane");
+  extern __shared__ __align__(16) char sm[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per_a = nrb * ncb;
+  const int a = xcd + 8 * (slot / per_a);
+  if (a >= n_alpha) return;
+  const int rem = slot % per_a, rb = rem / ncb, cb = rem % ncb;
+  const int i0 = rb * M2, b0 = cb * 64;
+  const size_t NN = (size_t)N * N;
+  const char* Ra = (const char*)(R + (size_t)a * NN);
+  const char* Xa = (const char*)X + (x_shared ? 0 : (size_t)a * N * B * 4);
+  const float2* xs = xscale + (x_shared ? 0 : (size_t)a * B);
+  const int nch = N / K2;
+
+  // R instruction i (i = wave + 4q) moves rows i0 + RPI i .. + RPI - 1 (a row group past N: rows
+  // N - RPI.., never written back); lane: row + lane / CPR, LDS chunk lane % CPR holds source chunk
+  // (lane % CPR) ^ (row mod CPR) = (lane % CPR) ^ (lane / CPR) since RPI is a multiple of CPR.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int qrow = lane / CPR;
+  const uint32_t qoff = (uint32_t)(((size_t)qrow * N + 4 * ((lane % CPR) ^ (qrow % CPR))) * 4);
+  const uint32_t xoff_l = (uint32_t)(((size_t)(lane >> 4) * B + 4 * (lane & 15)) * 4);
+  auto issue = [&](int it) {
+    char* st = sm + (it % NS) * LY::SB;
+    const int k0 = it * K2;
+#pragma unroll
+    for (int q = 0; q < LY::QB / 4096; ++q) {
+      const int i = wv + 4 * q;
+      const int row0 = i0 + RPI * i < N ? i0 + RPI * i : N - RPI;
+      lds_dma16(Ra + ((size_t)row0 * N + k0) * 4 + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
+    }
+#pragma unroll
+    for (int q = 0; q < LY::XB / 4096; ++q) {
+      const int i = wv + 4 * q;
+      if (PRE) {
+        const char* gb = (const char*)X + (((size_t)(x_shared ? 0 : a) * ncb + cb) * nch + it) * LY::XB + i * 1024;
+        lds_dma16(gb + 16 * lane, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
+      } else {
+        const char* gb = Xa + ((size_t)(k0 + 4 * i) * B + b0) * 4;
+        lds_dma16(gb + xoff_l, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
+      }
+    }
+  };
+
+  float xsc[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) xsc[c] = xs[b0 + 32 * c + l32].x;
+  asm volatile("" ::"v"(xsc[0]), "v"(xsc[1]));   // settled before the ring starts
+  floatx16 acc[2] = {};
+  const int rr = 32 * wave + l32;
+
+  for (int it = 0; it < NS - 1 && it < nch; ++it) issue(it);
+  for (int it = 0; it < nch; ++it) {
+    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NS - 2) * LY::LW));
+    else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    barrier_nofence();
+    if (it + NS - 1 < nch) issue(it + NS - 1);
+    const char* st = sm + (it % NS) * LY::SB;
+#pragma unroll
+    for (int ks = 0; ks < K2 / 16; ++ks) {
+      shortx8 arh, arl;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {   // R[rr][16 ks + 8 lh .. + 7]: two chunks of four reals
+        const int c = (4 * ks + 2 * lh + q) ^ (rr % CPR);
+        const float4 v = *(const float4*)(st + rr * LY::QROW + c * 16);
+        short h, l;
+        split_h(v.x * kStackScale, h, l); arh[4 * q] = h; arl[4 * q] = l;
+        split_h(v.y * kStackScale, h, l); arh[4 * q + 1] = h; arl[4 * q + 1] = l;
+        split_h(v.z * kStackScale, h, l); arh[4 * q + 2] = h; arl[4 * q + 2] = l;
+        split_h(v.w * kStackScale, h, l); arh[4 * q + 3] = h; arl[4 * q + 3] = l;
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int col = 32 * c + l32;
+        shortx8 xh, xl;
+        if (PRE) {
+          const char* xb = st + LY::QB + ((ks * 2 + c) * 2) * 1024 + 16 * lane;
+          xh = *(const shortx8*)xb;
+          xl = *(const shortx8*)(xb + 1024);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int k = 16 * ks + 8 * lh + j;
+            const float v = *(const float*)(st + LY::QB + (k * 64 + col) * 4);
+            short h, l;
+            split_h(v * xsc[c], h, l); xh[j] = h; xl[j] = l;
+          }
+        }
+        acc[c] = mma(arh, xh, acc[c]);
+        acc[c] = mma(arh, xl, acc[c]);
+        acc[c] = mma(arl, xh, acc[c]);
+      }
+    }
+  }
+  // write back: lane holds signal b0 + 32c + l32, rows 32 wave + 8(e/4) + 4 lh + e%4; the imaginary
+  // part is sin(pi alpha) (W Z[a]) with the rank-r factor (zero when r = 0)
+  const float sn = r > 0 ? (float)sinpi(alphas[a]) : 0.f;
+  const float* Za = Z + (size_t)(x_shared ? 0 : a) * kWCols * B;
+  const size_t yoff = (size_t)a * N * B;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int gb = b0 + 32 * c + l32;
+    const float u = xs[gb].y * (1.0f / kStackScale);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int gi = i0 + 32 * wave + 8 * (e >> 2) + 4 * lh + (e & 3);
+      if (gi < N) {
+        float im = 0.f;
+        for (int q = 0; q < r; ++q) im = fmaf(W[(size_t)gi * kWCols + q], Za[(size_t)q * B + gb], im);
+        Y[yoff + (size_t)gi * B + gb] = cplx64{acc[c][e] * u, sn * im};
+      }
+    }
+  }
+}
+
+size_t apply_real_ws_bytes(int N, int n_alpha, int B, int x_shared, int r) {
+  const size_t nx = x_shared ? 1 : n_alpha;
+  const size_t nch = ceil_div(N, CR);
+  return align_up(nx * B * sizeof(float2), 256) + colscale_partial_bytes(N, (int)nx, B) +
+         align_up(nx * kWCols * B * sizeof(float), 256) + align_up(nx * nch * (size_t)r * B * sizeof(float), 256) +
+         xsplit_bytes(N, (int)nx, B);
+}
+
+bool apply_real_supported(const Plan* p, int x_complex, int B) {
+  return !p->cplx && !x_complex && p->w_ok && p->N % 32 == 0 && B % 64 == 0;
+}
+
+fgfrft_status apply_real_launch(const Plan* p, const float* R, int n_alpha, const double* alphas_dev, const float* X,
+                                int x_shared, int B, cplx64* Y, void* ws, hipStream_t s) {
+  const int N = p->N, r = p->form == FGFRFT_FORM_SPLIT ? p->r_minus1 : 0;
+  const int nx = x_shared ? 1 : n_alpha;
+  const int nch = ceil_div(N, CR);
+  float2* sc = (float2*)ws;
+  float* partial = (float*)((char*)ws + align_up((size_t)nx * B * sizeof(float2), 256));
+  float* Z = (float*)((char*)partial + colscale_partial_bytes(N, nx, B));
+  float* pz = (float*)((char*)Z + align_up((size_t)nx * kWCols * B * sizeof(float), 256));
+  short* Xs = (short*)((char*)pz + align_up((size_t)nx * nch * r * B * sizeof(float), 256));
+  k_colmax_wtx<<<dim3(ceil_div(B, 64) * nx, nch), 256, 0, s>>>(X, N, B, p->W, r, partial, pz);
+  k_colscale<<<ceil_div(nx * B, 256), 256, 0, s>>>(partial, nch, B, nx, sc);
+  if (r > 0) k_zsum<<<(unsigned)(((size_t)nx * r * B + 255) / 256), 256, 0, s>>>(pz, nch, r, B, nx, Z);
+  FG_LAUNCHED("signal scales and W^T X");
+  // the signals are split into fp16 hi / lo once (one extra pass over X) rather than by each of the
+  // four waves of every workgroup that reads them: 3.57 against 3.80 ms per knn4096 launch
+  fgfrft_status rc = xsplit_launch(X, B, B, N, nx, x_shared ? 0 : (size_t)N * B, sc, B, Xs, s);
+  if (rc) return rc;
+  const int nrb = ceil_div(N, M2), ncb = B / 64;
+  const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
+  if (nblocks > 0x7fffffff) {
+    set_error("apply grid too large");
+    return FGFRFT_EUNSUPPORTED;
+  }
+  constexpr int lds = RS_NS * ApplyRealLayout::SB;
+  static_assert(lds <= 80 * 1024, "two workgroups per CU");
+  FG_HIP(raise_lds_limit((const void*)k_apply_real<true>, lds));
+  k_apply_real<true><<<(unsigned)nblocks, 256, lds, s>>>(R, N, n_alpha, Xs, x_shared, B, sc, alphas_dev, p->W, r, Z, Y,
+                                                         nrb, ncb);
+  FG_LAUNCHED("apply (real operator)");
+  return FGFRFT_OK;
+}
+
 fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex, int x_shared,
                            int B, void* Y, int y_real, void* ws, hipStream_t s) {
   float2* sc = (float2*)ws;

@@ -65,8 +65,14 @@ struct Plan {
   double unitarity_defect = 0, drift = 0, stop_norm = 0, last_pivot_norm = 0, tau = 1e-6;
   void* stack = nullptr;           // [L][N][N] elements (4 B real / 8 B complex)
   void* P = nullptr;               // [N][N] float (real) or cplx64 (complex)
+  float* W = nullptr;              // real F: [N][kWCols] float, P = W W^T (columns >= r_minus1 zero)
+  int w_ok = 0;                    // 1: W holds the -1 eigenspace basis (real F, r_minus1 <= kWCols)
   size_t stack_elem_bytes = 0;
 };
+
+// Real F keeps an orthonormal basis W of the -1 eigenspace (P = W W^T) as float32, row-major
+// [N][kWCols], when r_minus1 <= kWCols: the real-F apply forms P X = W (W^T X) from it.
+constexpr int kWCols = 32;
 
 // ---------------------------------------------------------------- errors
 void set_error(const char* fmt, ...);
@@ -100,8 +106,9 @@ fgfrft_status gfrft_exact_run(const void* V, const void* Vh, const double* theta
 
 // Online side (update.hip)
 size_t update_ws_bytes(const Plan* p, int n_alpha);
+// real_plane (real F only): write R = Re Q as float32 [n_alpha][N][N] instead of complex64 Q.
 fgfrft_status update_launch(const Plan* p, const double* alphas_dev, int n_alpha, void* Q,
-                            void* ws, hipStream_t s);
+                            void* ws, hipStream_t s, bool real_plane = false);
 fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, int n_alpha_pad,
                           void* table, float4* epi, int deriv, hipStream_t s);
 
@@ -128,6 +135,13 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
                             hipStream_t s);
 fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const void* X, int x_complex,
                            int x_shared, int B, void* Y, int y_real, void* ws, hipStream_t s);
+
+// Real-F apply (apply.hip): Y[a] = R[a] X[a] + j sin(pi alpha_a) W (W^T X[a]) with R = Re Q float32
+// [n_alpha][N][N] from update_launch(..., real_plane = true); real X, N % 32 == 0, B % 64 == 0.
+size_t apply_real_ws_bytes(int N, int n_alpha, int B, int x_shared, int r);
+bool apply_real_supported(const Plan* p, int x_complex, int B);
+fgfrft_status apply_real_launch(const Plan* p, const float* R, int n_alpha, const double* alphas_dev, const float* X,
+                                int x_shared, int B, cplx64* Y, void* ws, hipStream_t s);
 
 // Gradient (grad.hip)
 size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared);

@@ -439,6 +439,16 @@ __global__ __launch_bounds__(256) void k_store(const double* __restrict__ M, siz
   }
 }
 
+// Real F: the -1 eigenspace basis (column-major FP64 N x r) as float32 row-major [N][kWCols],
+// columns r..kWCols-1 zero.
+__global__ __launch_bounds__(256) void k_store_W(const double* __restrict__ W, int N, int r, float* __restrict__ out) {
+  const size_t total = (size_t)N * kWCols;
+  for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+    const int i = (int)(idx / kWCols), q = (int)(idx % kWCols);
+    out[idx] = q < r ? (float)W[(size_t)q * N + i] : 0.f;
+  }
+}
+
 // out = conj(M)^T in the resident format (the negative powers F^{-n} P_c = M_n^H of
 // Proposition 2), through 32x32 LDS tiles so both the FP64 read and the store are coalesced.
 template <bool C>
@@ -595,6 +605,12 @@ fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size
     if (C) k_form_W<true><<<r, 256, 0, s>>>(Abuf, N, k, taub, Mcur);
     else k_form_W<false><<<r, 256, 0, s>>>(Abuf, N, k, taub, Mcur);
     FG_LAUNCHED("form_W");
+  }
+  p->w_ok = 0;
+  if (!C && p->W && r <= kWCols) {
+    k_store_W<<<grid_for((size_t)N * kWCols), 256, 0, s>>>(Mcur, N, r, p->W);
+    FG_LAUNCHED("store W");
+    p->w_ok = 1;
   }
   if (C) k_projector<true><<<grid_for(total), 256, 0, s>>>(Mcur, N, r, P64, Mprev);
   else k_projector<false><<<grid_for(total), 256, 0, s>>>(Mcur, N, r, P64, Mprev);

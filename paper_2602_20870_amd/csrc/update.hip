@@ -114,12 +114,16 @@ __device__ __forceinline__ void split_f32(float x, short& hi, short& lo) {
 // OFF32: the per-lane part of the store address, (4 lh N^2 + row N + col) * 8 bytes, fits 32 bits
 // (N <= 10240); the plane part is uniform, so every store is one scalar base plus one fixed 32-bit
 // vector offset and no per-store 64-bit vector addresses are kept in registers.
-template <bool CPLX, int KP, bool BF, bool OFF32>
+//
+// ROUT (real F only): the real plane alone, R = Re Q, is written as float32 [n_alpha][N][N]; for real
+// F the imaginary plane is sin(pi alpha) P, which the real-F apply adds from the projector's factor.
+template <bool CPLX, int KP, bool BF, bool OFF32, bool ROUT = false>
 __device__ __forceinline__ void order_group(const shortx8* T, const float4* E, int g0, int a0, int n_alpha,
                                             bool fast, int row, int col, int N, size_t NN, int l32, int lh,
                                             const shortx8 (&bh)[CPLX ? 2 : 1][KP / 16],
                                             const shortx8 (&bl)[CPLX ? 2 : 1][KP / 16], shortx8 bxh, shortx8 bxl,
-                                            cplx64* __restrict__ Q) {
+                                            void* __restrict__ Qv) {
+  static_assert(!(ROUT && CPLX), "real-plane output needs a real F");
   constexpr int NPL = CPLX ? 2 : 1;
   constexpr int CH = KP / 4, G8 = KP / 8, KS = KP / 16;
   const float unscale = BF ? 1.0f : kUnscale;
@@ -151,6 +155,34 @@ __device__ __forceinline__ void order_group(const shortx8* T, const float4* E, i
   acc_re = mfma16<BF>(xrH, bxh, acc_re);
   acc_re = mfma16<BF>(xrH, bxl, acc_re);
   acc_re = mfma16<BF>(xrL, bxh, acc_re);
+  if constexpr (ROUT) {
+    // lanes of a half-wave: 32 consecutive positions of one order's row (128-byte runs); the plane
+    // offset walks in scalar registers, each store adds one fixed per-lane offset
+    float* ql = (float*)Qv + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
+    if (fast) {
+      const size_t plane = NN * sizeof(float);
+      size_t po = (size_t)a0 * plane;
+      const size_t vo = ((size_t)4 * lh * NN + (size_t)row * N + col) * sizeof(float);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float* dst = OFF32 ? (float*)((char*)Qv + po + (uint32_t)vo) : (float*)((char*)Qv + po + vo);
+          __builtin_nontemporal_store(acc_re[4 * m + i] * unscale, dst);
+          po += plane;
+          asm volatile("" : "+s"(po));
+        }
+        po += 4 * plane;
+        asm volatile("" : "+s"(po));
+      }
+    } else if (row < N && col < N) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha) ql[(size_t)(8 * (r >> 2) + (r & 3)) * NN] = acc_re[r] * unscale;
+    }
+    return;
+  }
+  cplx64* __restrict__ Q = (cplx64*)Qv;
   acc_im = mfma16<BF>(xiH, bxh, acc_im);
   acc_im = mfma16<BF>(xiH, bxl, acc_im);
   acc_im = mfma16<BF>(xiL, bxh, acc_im);
@@ -346,20 +378,56 @@ __device__ __forceinline__ void store_pair(const floatx16& re0, const floatx16& 
   }
 }
 
+// Real-plane epilogue (ROUT): lane l32 holds positions col, col + 1 of orders a0 + 8(r/4) + 4 lh + r%4
+// in (re0[r], re1[r]); each store instruction writes one 256-byte row run in each of two planes.
+template <bool OFF32>
+__device__ __forceinline__ void store_pair_real(const floatx16& re0, const floatx16& re1, int a0, int n_alpha,
+                                                bool fast, int row, int col, int N, size_t NN, int lh, float unscale,
+                                                float* __restrict__ R) {
+  if (fast) {
+    const size_t plane = NN * sizeof(float);
+    size_t po = (size_t)a0 * plane;
+    const size_t vo = ((size_t)4 * lh * NN + (size_t)row * N + col) * sizeof(float);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const f32x2 v = f32x2{re0[4 * m + i] * unscale, re1[4 * m + i] * unscale};
+        if (OFF32) __builtin_nontemporal_store(v, (f32x2*)((char*)R + po + (uint32_t)vo));
+        else __builtin_nontemporal_store(v, (f32x2*)((char*)R + po + vo));
+        po += plane;
+        asm volatile("" : "+s"(po));
+      }
+      po += 4 * plane;
+      asm volatile("" : "+s"(po));
+    }
+  } else if (row < N) {
+    float* ql = R + (size_t)(a0 + 4 * lh) * NN + (size_t)row * N + col;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (a0 + 8 * (r >> 2) + 4 * lh + (r & 3) < n_alpha) {
+        float* q = ql + (size_t)(8 * (r >> 2) + (r & 3)) * NN;
+        if (col < N) q[0] = re0[r] * unscale;
+        if (col + 1 < N) q[1] = re1[r] * unscale;
+      }
+  }
+}
+
 // Two 32-position blocks whose lanes hold the even (block 0) and odd (block 1) position of one
 // column pair: the same MFMA sequence per block as order_group; a half-wave exchange then gives each
 // lane one position of two orders, so every store instruction writes one order's 64-position row
 // run (512 contiguous bytes of a single plane; against two 512-byte runs in planes four orders apart
 // the stores alone stream 7% faster and the whole kernel runs 2% faster).  The operator planes are
 // streamed out with nontemporal stores (they are far larger than the caches).
-template <bool CPLX, int KP, bool BF, bool OFF32>
+template <bool CPLX, int KP, bool BF, bool OFF32, bool ROUT = false>
 __device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, int g0, int a0, int n_alpha, bool fast,
                                            int row, int col, int N, size_t NN, int l32, int lh,
                                            const shortx8 (&bh0)[CPLX ? 2 : 1][KP / 16],
                                            const shortx8 (&bl0)[CPLX ? 2 : 1][KP / 16], shortx8 bxh0, shortx8 bxl0,
                                            const shortx8 (&bh1)[CPLX ? 2 : 1][KP / 16],
                                            const shortx8 (&bl1)[CPLX ? 2 : 1][KP / 16], shortx8 bxh1, shortx8 bxl1,
-                                           cplx64* __restrict__ Q) {
+                                           void* __restrict__ Q) {
+  static_assert(!(ROUT && CPLX), "real-plane output needs a real F");
   constexpr int NPL = CPLX ? 2 : 1;
   constexpr int CH = KP / 4, G8 = KP / 8, KS = KP / 16;
   const float unscale = BF ? 1.0f : kUnscale;
@@ -393,10 +461,14 @@ __device__ __forceinline__ void order_pair(const shortx8* T, const float4* E, in
   re0 = mfma16<BF>(xrH, bxh0, re0); re1 = mfma16<BF>(xrH, bxh1, re1);
   re0 = mfma16<BF>(xrH, bxl0, re0); re1 = mfma16<BF>(xrH, bxl1, re1);
   re0 = mfma16<BF>(xrL, bxh0, re0); re1 = mfma16<BF>(xrL, bxh1, re1);
+  if constexpr (ROUT) {
+    store_pair_real<OFF32>(re0, re1, a0, n_alpha, fast, row, col, N, NN, lh, unscale, (float*)Q);
+    return;
+  }
   im0 = mfma16<BF>(xiH, bxh0, im0); im1 = mfma16<BF>(xiH, bxh1, im1);
   im0 = mfma16<BF>(xiH, bxl0, im0); im1 = mfma16<BF>(xiH, bxl1, im1);
   im0 = mfma16<BF>(xiL, bxh0, im0); im1 = mfma16<BF>(xiL, bxh1, im1);
-  store_pair<OFF32>(re0, im0, re1, im1, a0, n_alpha, fast, row, col, N, NN, lh, unscale, Q);
+  store_pair<OFF32>(re0, im0, re1, im1, a0, n_alpha, fast, row, col, N, NN, lh, unscale, (cplx64*)Q);
 }
 
 // Table chunk of ncap orders into LDS with direct HBM/L2-to-LDS loads: LDS 16-byte chunk m =
@@ -420,11 +492,11 @@ __device__ __forceinline__ void load_table_direct(const uint16_t* __restrict__ t
 // then reuses the LDS for the coefficient table, CAP orders at a time, and runs the order loop,
 // which touches only LDS, the matrix cores and stores: nothing in it waits on the memory counter
 // the stores also use, so the stores stream without drains.
-template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, bool OFF32, int CAPV, bool PAIR>
+template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, bool OFF32, int CAPV, bool PAIR, bool ROUT>
 __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restrict__ stack, const void* __restrict__ Pm,
                                                            int N, int L, int nJ, const uint16_t* __restrict__ table,
                                                            const float4* __restrict__ epi, int n_alpha, int n_pad,
-                                                           cplx64* __restrict__ Q) {
+                                                           void* __restrict__ Q) {
   using LY = StripLayout<CPLX, KP, TR, TC, CAPV>;
   constexpr int NPL = LY::NPL, CH = LY::CH, KS = KP / 16, PT = LY::PT, CAP = LY::CAP;
   constexpr int NW = NT / 64, NBLK = PT / 32, BPW = NBLK >= NW ? NBLK / NW : 1;
@@ -476,7 +548,7 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
 #pragma unroll
         for (int j = 0; j < BPW; j += 2) {
           const int p = pos_of(j);
-          order_pair<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast && (N % 2) == 0, row0 + p / TC,
+          order_pair<CPLX, KP, BF, OFF32, ROUT>(T, E, g0, a0, n_alpha, fast && (N % 2) == 0, row0 + p / TC,
                                           col0 + p % TC, N, NN, l32, lh, bh[j], bl[j], bxh[j], bxl[j], bh[j + 1],
                                           bl[j + 1], bxh[j + 1], bxl[j + 1], Q);
         }
@@ -486,7 +558,7 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
           const int blk = wave + NW * j;
           if (blk >= NBLK) break;
           const int p = blk * 32 + l32;
-          order_group<CPLX, KP, BF, OFF32>(T, E, g0, a0, n_alpha, fast, row0 + p / TC, col0 + p % TC, N, NN,
+          order_group<CPLX, KP, BF, OFF32, ROUT>(T, E, g0, a0, n_alpha, fast, row0 + p / TC, col0 + p % TC, N, NN,
                                            l32, lh, bh[j], bl[j], bxh[j], bxl[j], Q);
         }
       }
@@ -514,36 +586,37 @@ fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, 
   return FGFRFT_OK;
 }
 
-template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false>
+template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false,
+          bool ROUT = false>
 static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha,
                                          int n_pad, void* Q, hipStream_t s) {
   using LY = StripLayout<CPLX, KP, TR, TC, CAPV>;
   constexpr size_t lds = LY::RB + LY::PB > LY::TB + (size_t)LY::CAP * 16 ? LY::RB + LY::PB : LY::TB + (size_t)LY::CAP * 16;
   static_assert(lds <= 160 * 1024, "LDS budget");
   const bool off32 = (size_t)5 * p->N * p->N * sizeof(cplx64) < ((size_t)1 << 32);
-  auto kern = off32 ? k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, true, CAPV, PAIR>
-                    : k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, false, CAPV, PAIR>;
+  auto kern = off32 ? k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, true, CAPV, PAIR, ROUT>
+                    : k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, false, CAPV, PAIR, ROUT>;
   FG_HIP(raise_lds_limit((const void*)kern, (int)lds));
   const int nI = ceil_div(p->N, TR), nJ = ceil_div(p->N, TC);
-  kern<<<nI * nJ, NT, lds, s>>>(p->stack, p->P, p->N, p->L, nJ, table, epi, n_alpha, n_pad, (cplx64*)Q);
+  kern<<<nI * nJ, NT, lds, s>>>(p->stack, p->P, p->N, p->L, nJ, table, epi, n_alpha, n_pad, Q);
   FG_LAUNCHED("update");
   return FGFRFT_OK;
 }
 
 // (KP, TR, pairing): strips of TR rows x 64 columns; the staged tiles, and then the order table
 // (up to 256 orders for KP <= 64, 128 beyond), fit 64-68 KB of LDS, two workgroups of 4 waves per CU.
-template <bool BF>
+template <bool BF, bool ROUT = false>
 static fgfrft_status dispatch(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha, int np, void* Q,
                               hipStream_t s) {
   const int KP = kp_of(p->L);
   if (!p->cplx) {
     switch (KP) {
-      case 32: return launch_update_strip<false, 32, 8, 64, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_strip<false, 64, 4, 64, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
-      case 96: return launch_update_strip<false, 96, 2, 64, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
-      case 128: return launch_update_strip<false, 128, 2, 64, BF, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<false, 32, 8, 64, BF, 256, 2, 256, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<false, 64, 4, 64, BF, 256, 2, 256, true, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 96: return launch_update_strip<false, 96, 2, 64, BF, 256, 2, 128, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 128: return launch_update_strip<false, 128, 2, 64, BF, 256, 2, 128, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
     }
-  } else {
+  } else if constexpr (!ROUT) {
     switch (KP) {
       case 32: return launch_update_strip<true, 32, 4, 64, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
       case 64: return launch_update_strip<true, 64, 2, 64, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
@@ -553,15 +626,22 @@ static fgfrft_status dispatch(const Plan* p, const uint16_t* table, const float4
   return FGFRFT_EUNSUPPORTED;
 }
 
-fgfrft_status update_launch(const Plan* p, const double* alphas_dev, int n_alpha, void* Q, void* ws, hipStream_t s) {
+fgfrft_status update_launch(const Plan* p, const double* alphas_dev, int n_alpha, void* Q, void* ws, hipStream_t s,
+                            bool real_plane) {
+  if (real_plane && p->cplx) {
+    set_error("the real-plane update needs a real F");
+    return FGFRFT_EUNSUPPORTED;
+  }
   const int np = n_pad_of(n_alpha), KP = kp_of(p->L);
   char* base = (char*)ws + align_up((size_t)n_alpha * 8, 256);
   uint16_t* table = (uint16_t*)base;
   float4* epi = (float4*)(base + align_up((size_t)np * 2 * KP * 2, 256));
   fgfrft_status rc = coef_launch(p, alphas_dev, n_alpha, np, table, epi, 0, s);
   if (rc) return rc;
-  return p->stacktype == FGFRFT_STACK_BF16X2 ? dispatch<true>(p, table, epi, n_alpha, np, Q, s)
-                                             : dispatch<false>(p, table, epi, n_alpha, np, Q, s);
+  const bool bf = p->stacktype == FGFRFT_STACK_BF16X2;
+  if (real_plane)
+    return bf ? dispatch<true, true>(p, table, epi, n_alpha, np, Q, s) : dispatch<false, true>(p, table, epi, n_alpha, np, Q, s);
+  return bf ? dispatch<true>(p, table, epi, n_alpha, np, Q, s) : dispatch<false>(p, table, epi, n_alpha, np, Q, s);
 }
 
 }  // namespace fgfrft

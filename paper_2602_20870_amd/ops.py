@@ -122,11 +122,11 @@ class Plan:
     # ------------------------------------------------------------------ info
     def info(self) -> dict:
         r = ctypes.c_int()
-        u, d, sn, lp = (ctypes.c_double() for _ in range(4))
+        u, d, sn, lp, tu = (ctypes.c_double() for _ in range(5))
         check(lib().fgfrft_plan_info(self._h, ctypes.byref(r), ctypes.byref(u), ctypes.byref(d), ctypes.byref(sn),
-                                     ctypes.byref(lp)), "fgfrft_plan_info")
+                                     ctypes.byref(lp), ctypes.byref(tu)), "fgfrft_plan_info")
         return dict(r_minus1=r.value, unitarity_defect=u.value, drift=d.value, stop_norm=sn.value,
-                    last_pivot_norm=lp.value)
+                    last_pivot_norm=lp.value, tau_used=tu.value)
 
     @property
     def r_minus1(self) -> int:
@@ -200,20 +200,33 @@ class Plan:
     def update_workspace_bytes(self, n_alpha: int) -> int:
         return int(lib().fgfrft_update_workspace_bytes(self._h, n_alpha))
 
-    def apply(self, alphas, X: torch.Tensor, chunk: int = 0, stream=None) -> torch.Tensor:
-        """Y[a] = Q(alphas[a]) X[a] with X [n_alpha, N, B] or a shared [N, B] block."""
+    def apply(self, alphas, X: torch.Tensor, chunk: int = 0, stream=None, out: torch.Tensor | None = None,
+              ws: torch.Tensor | None = None) -> torch.Tensor:
+        """Y[a] = Q(alphas[a]) X[a] with X [n_alpha, N, B] or a shared [N, B] block.
+
+        A real F with real signals takes the library's real-F route (the operator's real part R plus
+        the rank-r imaginary part from P's basis).  out: complex64 [n_alpha, N, B]; ws: a caller
+        workspace (contiguous uint8 cuda tensor) reused when large enough."""
         a = _alphas(alphas)
         n = a.size
         x_shared = X.dim() == 2
         B = X.shape[-1]
         xc = _check_signal(X, n, self.N, x_shared, self.device)
-        Y = torch.empty((n, self.N, B), dtype=torch.complex64, device=self.device)
+        if out is None:
+            out = torch.empty((n, self.N, B), dtype=torch.complex64, device=self.device)
+        _on_device(self.device, out=out)
+        if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() != n * self.N * B:
+            raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*B elements")
         L_ = lib()
-        ws = _workspace(L_.fgfrft_apply_workspace_bytes(self._h, n, B, int(x_shared), chunk), self.device)
-        check(L_.fgfrft_apply(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(Y), chunk,
+        ws, tmp = _caller_ws(ws, L_.fgfrft_apply_workspace_bytes(self._h, n, B, xc, int(x_shared), chunk), self.device)
+        check(L_.fgfrft_apply(self._h, a.ctypes.data_as(P_double), n, _ptr(X), xc, int(x_shared), B, _ptr(out), chunk,
                               _ptr(ws), ws.numel(), _stream(stream)), "fgfrft_apply")
-        _keep(stream, ws)
-        return Y
+        _keep(stream, tmp)
+        return out
+
+    def apply_workspace_bytes(self, n_alpha: int, B: int, x_complex: bool = False, x_shared: bool = False,
+                              chunk: int = 0) -> int:
+        return int(lib().fgfrft_apply_workspace_bytes(self._h, n_alpha, B, int(x_complex), int(x_shared), chunk))
 
     def apply_direct(self, alphas, col_order, X: torch.Tensor, ncols: int | None = None, out: torch.Tensor | None = None,
                      ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:

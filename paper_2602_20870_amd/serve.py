@@ -449,6 +449,11 @@ def _run_trace(server: Server, trace, signals: dict, warmup: int, keep_every: in
     rs = reqs[warmup:]
     direct_share = float(np.mean([r.route == "direct" for r in rs]))
     lat = np.array([r.t_done - r.t_arrive for r in rs])
+    per_plan = {}
+    for gid in sorted(set(r.gid for r in rs), key=str):
+        lg = np.array([r.t_done - r.t_arrive for r in rs if r.gid == gid])
+        per_plan[str(gid)] = dict(N=server.plans[gid].N, requests=len(lg), p50_ms=float(np.percentile(lg, 50) * 1e3),
+                                  p99_ms=float(np.percentile(lg, 99) * 1e3))
     wait = np.array([r.t_launch - r.t_arrive for r in rs])
     service = np.array([r.t_done - r.t_launch for r in rs])
     return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
@@ -458,7 +463,52 @@ def _run_trace(server: Server, trace, signals: dict, warmup: int, keep_every: in
                 queue_wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
                 service_p50_ms=float(np.percentile(service, 50) * 1e3),
                 service_p99_ms=float(np.percentile(service, 99) * 1e3),
-                mean_batch=float(np.mean([r.batch_size for r in rs])), direct_share=direct_share, kept=kept)
+                mean_batch=float(np.mean([r.batch_size for r in rs])), direct_share=direct_share, per_plan=per_plan,
+                kept=kept)
+
+
+def run_trace_one_launch(plans: dict, trace, signals: dict, warmup: int = 0, keep_every: int = 1, bmax: int = 64,
+                         route: str = "auto", use_graphs: bool = True, device: str = "cuda:0") -> dict:
+    """Baseline without coalescing or overlap: one launch per request, in arrival order, on the route
+    the server picks for a batch of one (the direct route where the plan offers it), from buffers
+    allocated once per plan (a slot set of one order, replayed from its captured graph), with only the
+    result copy waited for.  Latency = completion - arrival.  `outputs`: index -> result of every
+    `keep_every`-th request."""
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        dev = torch.device(device)
+        stream = torch.cuda.Stream(device=dev)
+        sets = {gid: _SlotSet(p, 1, bmax, dev, use_graphs, route, stream) for gid, p in plans.items()}
+        t_arr, gids, alphas, Bs = trace
+        t0 = time.perf_counter()
+        lat, service, routes, outs = [], [], [], {}
+        for i in range(len(t_arr)):
+            now = time.perf_counter() - t0
+            if t_arr[i] > now:
+                time.sleep(t_arr[i] - now)
+            r = _Request(gids[i], alphas[i], signals[gids[i]][:, : Bs[i]], t0 + t_arr[i])
+            fut = r.future
+            s = sets[gids[i]]
+            s.launch([r])
+            s.event.synchronize()
+            s.retire(time.perf_counter())
+            lat.append(r.t_done - r.t_arrive)
+            service.append(r.t_done - r.t_launch)
+            routes.append(r.route)
+            if i % keep_every == 0:
+                outs[i] = fut.result()
+        wall = time.perf_counter() - t0
+    finally:
+        if gc_was:
+            gc.enable()
+    lat = np.array(lat[warmup:])
+    service = np.array(service[warmup:])
+    return dict(p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                mean_ms=float(lat.mean() * 1e3), requests=len(lat), wall_s=wall,
+                throughput_req_s=len(t_arr) / wall, service_mean_ms=float(service.mean() * 1e3),
+                service_p99_ms=float(np.percentile(service, 99) * 1e3),
+                direct_share=float(np.mean([x == "direct" for x in routes[warmup:]])), outputs=outs)
 
 
 def run_trace_per_request(plans: dict, trace, signals: dict, warmup: int = 0, keep_every: int = 1) -> dict:

@@ -2,7 +2,8 @@
 on sampled outputs the FP64 oracle computes row by row.
 
 * knn4096: N = 4096, L = 32, one update launch of 256 orders (34 GB of Q), then one apply
-  launch to 64 real signals per order, as in the benchmark step.
+  launch to 64 real signals per order, as in the benchmark step; then the same orders and
+  signals through the real-F route of the apply call (R = Re Q written, rank-r imaginary part).
 * grid8192 (precision form): N = 8192, L = 64, one update launch of a 32-order chunk for the
   FP32 stack and for the BF16 hi/lo stack, the direct route on both (32 orders x 2 signals),
   and the apply of the FP32 operators to one shared block of 1024 real signals; per-order errors against the oracle are printed (and written as
@@ -73,7 +74,15 @@ def test_knn4096_bench_launch_sampled_rows():
     Yr = _sample_rows(torch, Y, sample, rows)
     Qcol = Q[4][:, torch.as_tensor(rows, device="cuda")].cpu().numpy()    # columns R of Q^{0.73}
     Xs = X[torch.as_tensor(sample, device="cuda")].cpu().numpy().astype(np.float64)
-    del Q, Y, X
+    del Q, Y
+    torch.cuda.empty_cache()
+    # the real-F route of the apply call, as the benchmark's real-F leg runs it: one 256-order
+    # update of R = Re Q and one apply with the rank-r imaginary part
+    announce("knn4096: real-F route (plan.apply, 256 orders in one chunk)")
+    Yf = plan.apply(alphas, X, chunk=256)
+    torch.cuda.synchronize()
+    Yfr = _sample_rows(torch, Yf, sample, rows)
+    del Yf, X
     torch.cuda.empty_cache()
 
     # properties that need no oracle: Q^0 = I, Q^1 = F, Q^{-1} = F^T (Definition 1), and
@@ -89,16 +98,18 @@ def test_knn4096_bench_launch_sampled_rows():
     P, _, r, nxt = O.projectors_symmetric_route(F)
     assert plan.r_minus1 == r
     ref = O.sampled_rows(F, P, alphas[sample], L, rows)
-    errs_q, errs_y = [], []
+    errs_q, errs_y, errs_yf = [], [], []
     for i, a in enumerate(sample):
         errs_q.append(rel_fro(Qr[i], ref[i]))
         errs_y.append(rel_fro(Yr[i], ref[i] @ Xs[i]))
-    announce(f"knn4096: r_-1={r}, worst Q row error {max(errs_q):.2e}, worst Y row error {max(errs_y):.2e} "
-             f"[{time.time() - t0:.0f}s]")
+        errs_yf.append(rel_fro(Yfr[i], ref[i] @ Xs[i]))
+    announce(f"knn4096: r_-1={r}, worst Q row error {max(errs_q):.2e}, worst Y row error {max(errs_y):.2e}, "
+             f"real-F route {max(errs_yf):.2e} [{time.time() - t0:.0f}s]")
     _report("knn4096_fullsize.json", dict(alphas=[float(alphas[a]) for a in sample], rows=rows.tolist(),
-                                          q_err=errs_q, y_err=errs_y, r_minus1=r))
+                                          q_err=errs_q, y_err=errs_y, y_realF_err=errs_yf, r_minus1=r))
     assert max(errs_q) <= TOL_FP32, errs_q
     assert max(errs_y) <= TOL_FP32, errs_y
+    assert max(errs_yf) <= TOL_FP32, errs_yf
 
 
 @pytest.mark.timeout(900)

@@ -1,0 +1,121 @@
+"""GPU parity of the real-F route of the apply call: for a real orthogonal F and real signals the
+library writes only R = Re Q and adds the imaginary part sin(pi alpha) W (W^T X) from the -1
+eigenspace basis (Definition 1 with real powers, Definition 2).  Against the FP64 oracle's Q X, per
+order, at the FP32 bar; against the complex-operator route of the same call; and on the cases that
+must leave the route (complex signals, ragged signal counts, N % 32 != 0, r_-1 above the kept basis)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_common import TOL_FP32, announce, rel_fro, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _orth_with_minus1(n, r, seed, margin=0.3):
+    """Real orthogonal V D V^T with r eigenvalues at -1 and the rest in rotation blocks away from -1."""
+    rng = np.random.default_rng(seed)
+    rest = n - r
+    pairs = rest // 2
+    d = np.zeros((n, n))
+    d[: 2 * pairs, : 2 * pairs] = synth.rotation_blocks(rng.uniform(0.05, np.pi - margin, size=pairs))
+    k = 2 * pairs
+    if rest % 2:
+        d[k, k] = 1.0
+        k += 1
+    for i in range(k, n):
+        d[i, i] = -1.0
+    v, rr = np.linalg.qr(rng.standard_normal((n, n)))
+    v = v * np.sign(np.diag(rr))[None, :]
+    return v @ d @ v.T
+
+
+def _run(torch, F, L, alphas, X, chunk=0, form="split", stacktype="fp32"):
+    from paper_2602_20870_amd import Plan
+    plan = Plan(torch.from_numpy(F).cuda(), L, form=form, stacktype=stacktype)
+    Xt = torch.from_numpy(X).cuda()
+    Y = plan.apply(alphas, Xt, chunk=chunk).cpu().numpy()
+    return plan, Y
+
+
+def _check(F, L, alphas, X, Y, shared, form="split", tol=TOL_FP32):
+    ref = O.Plan(F, L) if form == "split" else None
+    worst = 0.0
+    for a, al in enumerate(alphas):
+        Q = ref.combine(float(al)) if ref else O.fgfrft_operator_standard(F, float(al), L)
+        Xa = (X if shared else X[a]).astype(np.float64)
+        e = rel_fro(Y[a], Q @ Xa)
+        worst = max(worst, e)
+        assert e <= tol, (a, al, e)
+    return worst
+
+
+@pytest.mark.parametrize("N,r,B,shared,n", [(96, 3, 64, False, 7),     # rank-3 imaginary part
+                                            (128, 0, 128, False, 5),   # no -1 eigenvalue: Q real
+                                            (64, 1, 64, True, 9),      # shared signal block
+                                            (160, 32, 64, False, 4),   # largest basis the plan keeps
+                                            (96, 40, 64, False, 3)])   # r_-1 > 32: complex route
+def test_real_route_against_oracle(N, r, B, shared, n):
+    torch = torch_cuda()
+    announce(f"real-F apply N={N} r={r} B={B} shared={shared} orders={n}")
+    F = _orth_with_minus1(N, r, seed=N + r)
+    L = 12
+    rng = np.random.default_rng(N * 7 + r)
+    alphas = rng.uniform(-2, 2, n)
+    alphas[0] = 0.5                               # sin(pi alpha) = 1: the full imaginary part
+    X = (synth.real_signals((N, B) if shared else (n, N, B), rng) * 300.0).astype(np.float32)
+    plan, Y = _run(torch, F, L, alphas, X, chunk=3)
+    assert plan.r_minus1 == r
+    worst = _check(F, L, alphas, X, Y, shared)
+    print(f"worst {worst:.2e}")
+
+
+def test_real_route_matches_complex_route_and_integer_orders():
+    torch = torch_cuda()
+    from paper_2602_20870_amd import apply_operator
+    announce("real-F apply vs update + complex apply, integer orders")
+    N, L, B = 128, 10, 64
+    F = _orth_with_minus1(N, 5, seed=3)
+    alphas = np.array([0.0, 1.0, -1.0, 2.0, 0.5, -0.5, 1.37])
+    rng = np.random.default_rng(4)
+    X = synth.real_signals((len(alphas), N, B), rng).astype(np.float32)
+    plan, Y = _run(torch, F, L, alphas, X)
+    Q = plan.update(alphas)
+    Y2 = apply_operator(Q, torch.from_numpy(X).cuda()).cpu().numpy()
+    for a in range(len(alphas)):
+        assert rel_fro(Y[a], Y2[a]) <= 2e-6, a
+    X64 = X.astype(np.float64)
+    assert rel_fro(Y[0], X64[0]) <= TOL_FP32                 # Q^0 = I
+    assert rel_fro(Y[1], F @ X64[1]) <= TOL_FP32             # Q^1 = F
+    assert rel_fro(Y[2], F.T @ X64[2]) <= TOL_FP32           # Q^-1 = F^T
+    assert rel_fro(Y[3], F @ F @ X64[3]) <= TOL_FP32         # Q^2 = F^2
+    assert np.max(np.abs(Y[:4].imag)) < 1e-5 * np.max(np.abs(Y[:4].real))
+
+
+@pytest.mark.parametrize("case", ["complex_x", "ragged_B", "ragged_N", "standard_form", "bf16x2"])
+def test_cases_around_the_real_route(case):
+    torch = torch_cuda()
+    announce(f"real-F apply neighbour case {case}")
+    rng = np.random.default_rng(hash(case) % 1000)
+    N, B, n, form, st, tol = 96, 64, 4, "split", "fp32", TOL_FP32
+    if case == "ragged_B":
+        B = 70
+    if case == "ragged_N":
+        N = 100
+    if case == "standard_form":
+        form = "standard"
+    if case == "bf16x2":
+        st, tol = "bf16x2", 5e-5
+    F = _orth_with_minus1(N, 2, seed=N)
+    L = 9
+    alphas = rng.uniform(-2, 2, n)
+    if case == "complex_x":
+        X = synth.complex_signals((n, N, B), rng).astype(np.complex64)
+    else:
+        X = synth.real_signals((n, N, B), rng).astype(np.float32)
+    _, Y = _run(torch, F, L, alphas, X, form=form, stacktype=st)
+    ref = O.Plan(F, L)
+    for a, al in enumerate(alphas):
+        Q = ref.combine(float(al)) if form == "split" else O.fgfrft_operator_standard(F, float(al), L)
+        assert rel_fro(Y[a], Q @ X[a].astype(np.complex128)) <= tol, (case, a)
