@@ -31,12 +31,25 @@ __device__ __forceinline__ floatx16 mfma_f32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// Split layout of G for the matrix-core inner products (PRE): per order, positions in blocks of 8
+// consecutive ones, 64 bytes per block: fp16 parts [Re hi x 8][Re lo x 8][Im hi x 8][Im lo x 8] of
+// G * s_a (s_a the order's power-of-two scale), the same 8 bytes per position as complex64.
+
 // VEC: B % 4 == 0 and 16-byte aligned GY and X, so the staging moves 16 bytes per load.
-template <bool XC, bool VEC>
+// PRE: G is written in the split layout above, scaled by gsc[blockIdx.z].x (N % 8 == 0); otherwise
+// as complex64 FP32.
+template <bool XC, bool VEC, bool PRE>
 __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, const void* __restrict__ X, int x_shared,
                                                int N, int B, int a_first, cplx64* __restrict__ G,
-                                               float* __restrict__ gmax) {
-  __shared__ float Ar[64][OPITCH], Ai[64][OPITCH], Br[64][OPITCH], Bi[XC ? 64 : 1][OPITCH];
+                                               const float2* __restrict__ gsc) {
+  constexpr int SM_IN = (XC ? 4 : 3) * 64 * OPITCH;
+  constexpr int SM_FLOATS = PRE && SM_IN < 8192 ? 8192 : SM_IN;
+  static_assert(!PRE || SM_FLOATS * 4 >= 64 * 512, "LDS staging of one split 64 x 64 tile");
+  __shared__ __align__(16) float smf[SM_FLOATS];
+  float (*Ar)[OPITCH] = (float (*)[OPITCH])smf;
+  float (*Ai)[OPITCH] = (float (*)[OPITCH])(smf + 64 * OPITCH);
+  float (*Br)[OPITCH] = (float (*)[OPITCH])(smf + 2 * 64 * OPITCH);
+  float (*Bi)[OPITCH] = (float (*)[OPITCH])(smf + 3 * 64 * OPITCH);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lk = lane >> 5;
   const int a = a_first + blockIdx.z;
@@ -103,48 +116,108 @@ __global__ __launch_bounds__(256) void k_outer(const cplx64* __restrict__ GY, co
     }
     __syncthreads();
   }
-  // lane holds column j0 + wj + l32, rows i0 + wi + 8 (e / 4) + 4 lk + e % 4; G is streamed out with
-  // nontemporal stores (the chunk's G is far larger than the caches; 4% faster than plain stores)
+  // lane holds column j0 + wj + l32, rows i0 + wi + 8 (e / 4) + 4 lk + e % 4
   typedef float f2v __attribute__((ext_vector_type(2)));
-  cplx64* g = G + (size_t)blockIdx.z * N * N;
+  typedef int i4v __attribute__((ext_vector_type(4)));
   const int gj = j0 + wj + l32;
-  float m = 0.f;
+  if constexpr (PRE) {
+    // split into fp16 parts, staged in LDS as 64 rows x 512 bytes in the split layout, then written
+    // out as 16-byte pieces (each tile row is 512 contiguous bytes of G), nontemporal
+    const float sc = gsc[blockIdx.z].x;
+    uint16_t* st = (uint16_t*)smf;
+    const int c = wj + l32;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rr = wi + 8 * (e >> 2) + 4 * lk + (e & 3);
+      const float vr = accr[e] * sc, vi = acci[e] * sc;
+      const _Float16 rh = (_Float16)vr, ih = (_Float16)vi;
+      const _Float16 rl = (_Float16)(vr - (float)rh), il = (_Float16)(vi - (float)ih);
+      uint16_t* blk = st + rr * 256 + (c >> 3) * 32 + (c & 7);
+      blk[0] = __builtin_bit_cast(uint16_t, rh);
+      blk[8] = __builtin_bit_cast(uint16_t, rl);
+      blk[16] = __builtin_bit_cast(uint16_t, ih);
+      blk[24] = __builtin_bit_cast(uint16_t, il);
+    }
+    __syncthreads();
+    char* g = (char*)(G + (size_t)blockIdx.z * N * N);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int idx = k * 256 + tid;            // 16-byte piece: row idx / 32, piece idx % 32 of the row
+      const int rr = idx >> 5, pc = idx & 31;
+      const int gi = i0 + rr, gpos = j0 + 2 * pc;   // first of the piece's positions (4 B per position per part)
+      if (gi < N && j0 + (pc >> 2) * 8 < N) {
+        const i4v v = *(const i4v*)((const char*)st + rr * 512 + pc * 16);
+        __builtin_nontemporal_store(v, (i4v*)(g + ((size_t)gi * N + j0) * 8 + pc * 16));
+      }
+      (void)gpos;
+    }
+    return;
+  }
+  // complex64 G streamed out with nontemporal stores (the chunk's G is far larger than the caches;
+  // 4% faster than plain stores)
+  cplx64* g = G + (size_t)blockIdx.z * N * N;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int gi = i0 + wi + 8 * (e >> 2) + 4 * lk + (e & 3);
-    if (gi < N && gj < N) {
-      __builtin_nontemporal_store(f2v{accr[e], acci[e]}, (f2v*)(g + (size_t)gi * N + gj));
-      m = fmaxf(m, fmaxf(fabsf(accr[e]), fabsf(acci[e])));
-    }
-  }
-  // largest |Re|, |Im| of this tile -> gmax[order][tile] (the scale of the split operands)
-  if (gmax) {
-    float* red = &Ar[0][0];
-    red[tid] = m;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] = fmaxf(red[tid], red[tid + st]);
-      __syncthreads();
-    }
-    if (tid == 0) gmax[(size_t)blockIdx.z * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (gi < N && gj < N) __builtin_nontemporal_store(f2v{accr[e], acci[e]}, (f2v*)(g + (size_t)gi * N + gj));
   }
 }
 
-// per order: 2^e with max |G_a| 2^e in [2^13, 2^14) (fp16 parts stay normal and far from
-// overflow), stored as (scale, 1 / scale)
-__global__ __launch_bounds__(256) void k_gscale(const float* __restrict__ gmax, int ntile, float2* __restrict__ gsc) {
-  __shared__ float red[256];
-  const int a = blockIdx.x;
+// Largest row norm^2 sum_b |V[a][i][b]|^2 over the 64 rows of a chunk (grid: orders x chunks; V
+// complex64 or float32 [n][N][B], order stride `stride` elements, 0 for one block shared by all).
+template <bool CPX>
+__global__ __launch_bounds__(256) void k_rownorm2_max(const void* __restrict__ V, int N, int B, size_t stride,
+                                                      float* __restrict__ out) {
+  __shared__ float red[4];
+  const int a = blockIdx.x, ch = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i1 = (ch + 1) * 64 < N ? (ch + 1) * 64 : N;
   float m = 0.f;
-  for (int t = threadIdx.x; t < ntile; t += 256) m = fmaxf(m, gmax[(size_t)a * ntile + t]);
-  red[threadIdx.x] = m;
+  for (int i = ch * 64 + w; i < i1; i += 4) {
+    float t = 0.f;
+    for (int b = lane; b < B; b += 64) {
+      const size_t o = (size_t)a * stride + (size_t)i * B + b;
+      if (CPX) {
+        const float2 v = ((const float2*)V)[o];
+        t += v.x * v.x + v.y * v.y;
+      } else {
+        const float v = ((const float*)V)[o];
+        t += v * v;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    m = fmaxf(m, t);
+  }
+  if (lane == 0) red[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[(size_t)a * gridDim.y + ch] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Order scale from an a-priori bound: |G_a[i][j]| <= ||GY_a[i,:]|| ||X_a[j,:]|| (Cauchy-Schwarz), so
+// with m = max_i ||GY_a[i,:]|| max_j ||X_a[j,:]|| (1 + 2^-10 for the rounding of the norms) the scale
+// 2^e puts m 2^e in [2^13, 2^14): every scaled entry of G is below 2^14, its fp16 parts stay finite.
+__global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ gy2, const float* __restrict__ x2,
+                                                      int nch, int x_shared, float2* __restrict__ gsc) {
+  __shared__ float r1[256], r2[256];
+  const int a = blockIdx.x;
+  float m1 = 0.f, m2 = 0.f;
+  for (int c = threadIdx.x; c < nch; c += 256) {
+    m1 = fmaxf(m1, gy2[(size_t)a * nch + c]);
+    m2 = fmaxf(m2, x2[(size_t)(x_shared ? 0 : a) * nch + c]);
+  }
+  r1[threadIdx.x] = m1;
+  r2[threadIdx.x] = m2;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    if (threadIdx.x < st) {
+      r1[threadIdx.x] = fmaxf(r1[threadIdx.x], r1[threadIdx.x + st]);
+      r2[threadIdx.x] = fmaxf(r2[threadIdx.x], r2[threadIdx.x + st]);
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    m = red[0];
+    const float m = sqrtf(r1[0]) * sqrtf(r2[0]) * (1.f + 1.f / 1024.f);
     int e = 0;
     if (m > 0.f && isfinite(m)) {
       int E;
@@ -255,14 +328,15 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
 // T[a][k] = sum_p conj(G_a[p]) B_k[p] is a contraction over the N^2 positions p of
 // [orders x positions] . [positions x k].  One workgroup per CU streams a contiguous range of
 // positions in stages of PC: the stage's G values (64 orders) and its 2L + 1 stack/P rows move
-// into LDS with direct loads (two-stage ring), the identity row is written in place, and 8
-// waves (a-block = w & 1, k-block kb0 + (w >> 1)) run v_mfma_f32_32x32x16_f16 on operands
-// split into fp16 hi/lo (scaled by 2^12 each).  FP32 accumulators are flushed into FP64 every
-// FL stages; per-workgroup FP64 partials are summed over workgroups in a fixed order.
+// into LDS with direct loads (a ring of NS stages, NS - 1 of them in flight while one is
+// consumed), the identity row is written in place, and 8 waves (a-block = w & 1, k-block
+// kb0 + (w >> 1)) run v_mfma_f32_32x32x16_f16 on operands split into fp16 hi/lo (scaled by 2^12
+// each).  FP32 accumulators are flushed into FP64 every 256 positions; per-workgroup FP64
+// partials are summed over workgroups in a fixed order.
 // Rows of B in LDS: 0..2L-1 stack, 2L P, 2L+1..RD-1 copies (ignored columns), RD identity,
 // then zero rows up to KP2 = 32 KB.  G rows and B rows keep their 16-byte chunks swizzled by
 // row so fragment reads of 32 rows spread over the banks.
-constexpr int IM_NA = 64, IM_NW = 8, IM_FL = 4;
+constexpr int IM_NA = 64, IM_NW = 8, IM_FLPOS = 256;   // FP32 -> FP64 flush every IM_FLPOS positions
 
 __device__ __forceinline__ void split16h(float v, short& hi, short& lo) {
   const _Float16 h = (_Float16)v;
@@ -284,7 +358,20 @@ struct InnerLayout {
   __host__ __device__ static size_t stage_bytes(int L) { return (size_t)GB + (size_t)kp2(L) * SROW; }
 };
 
-template <bool CPLX, int PC, int KBW>
+// s_waitcnt vmcnt <= n (n < 64, lgkmcnt 0) for a value known only at run time (the direct loads a wave
+// issues per stage depend on L and on the wave)
+__device__ __forceinline__ void wait_vm_upto(int n) {
+  switch (n) {
+#define FG_W(k) case k: __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(k)); break;
+    FG_W(0) FG_W(1) FG_W(2) FG_W(3) FG_W(4) FG_W(5) FG_W(6) FG_W(7) FG_W(8) FG_W(9) FG_W(10) FG_W(11)
+    FG_W(12) FG_W(13) FG_W(14) FG_W(15) FG_W(16) FG_W(17) FG_W(18) FG_W(19) FG_W(20) FG_W(21) FG_W(22)
+    FG_W(23) FG_W(24) FG_W(25) FG_W(26) FG_W(27) FG_W(28) FG_W(29) FG_W(30) FG_W(31)
+#undef FG_W
+    default: __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0)); break;
+  }
+}
+
+template <bool CPLX, int PC, int KBW, int NS>
 __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __restrict__ stack, const void* __restrict__ Pm,
                                                              int N, int L, const cplx64* __restrict__ G, int n_c,
                                                              const float2* __restrict__ gsc, int spw, int nstage,
@@ -302,14 +389,18 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
   const int st0 = blockIdx.x * spw, st1 = st0 + spw < nstage ? st0 + spw : nstage;
   const int wv = __builtin_amdgcn_readfirstlane(wave);
 
-  // zero rows past the identity row (both ring slots); never written afterwards
-  for (int s = 0; s < 2; ++s) {
+  // direct loads this wave issues per stage (G rows, then stack/P rows), for the ring's waits
+  const int nbi = RD / LY::SRPI;
+  const int lw = (LY::GB / 1024 - wv + IM_NW - 1) / IM_NW + (nbi - wv + IM_NW - 1) / IM_NW;
+  constexpr int FL = IM_FLPOS / PC;
+  // zero rows past the identity row (every ring slot); never written afterwards
+  for (int s = 0; s < NS; ++s) {
     uint32_t* z = (uint32_t*)(sm + s * SB + LY::GB + (size_t)(RD + 1) * LY::SROW);
     for (int e = tid; e < (KP2 - RD - 1) * LY::SROW / 4; e += 64 * IM_NW) z[e] = 0u;
   }
 
   auto issue = [&](int st) {
-    char* buf = sm + (st & 1) * SB;
+    char* buf = sm + (st % NS) * SB;
     const size_t p0 = (size_t)st * PC;
     // G: instruction i moves order rows 1024/GROW * i .. (orders past n_c read order 0)
     for (int i = wv; i < LY::GB / 1024; i += IM_NW) {
@@ -344,31 +435,26 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
 #pragma unroll
     for (int e = 0; e < 16; ++e) { dre[m][e] = 0.0; dim[m][e] = 0.0; }
   }
-  const int r = 32 * ab + l32;
-  const float ascale = r < n_c ? gsc[r].x : 1.f;   // this lane's order row
-  // settle that load before the ring starts (a wait for it later would wait for the ring too)
-  asm volatile("" ::"v"(ascale));
-  if (st0 < st1) issue(st0);
+  const int r = 32 * ab + l32;   // this lane's order row (G is split and scaled per order by k_outer)
+  for (int q = 0; q < NS - 1 && st0 + q < st1; ++q) issue(st0 + q);
   int since = 0;
   for (int st = st0; st < st1; ++st) {
-    // this wave's loads of stage st (the only ones in flight) and its LDS reads are complete
-    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    // this wave's loads of stage st have landed (only the NS - 2 younger stages may still be in
+    // flight) and its LDS reads of stage st - 1 are done; after the barrier that holds for every wave
+    if (st + NS - 1 <= st1) wait_vm_upto((NS - 2) * lw);
+    else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
     barrier_nofence();
-    if (st + 1 < st1) issue(st + 1);   // fills the slot read in the previous stage
-    const char* buf = sm + (st & 1) * SB;
+    if (st + NS - 1 < st1) issue(st + NS - 1);   // refills the slot read in stage st - 1
+    const char* buf = sm + (st % NS) * SB;
 #pragma unroll
     for (int ks = 0; ks < PC / 16; ++ks) {
-      shortx8 arh, arl, aih, ail;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {   // G[r][16 ks + 8 lh .. + 7]: chunks of two complex
-        const int c = (8 * ks + 4 * lh + q) ^ (r % LY::GCPR);
-        const float4 v = *(const float4*)(buf + (size_t)r * LY::GROW + c * 16);
-        short h, l;
-        split16h(v.x * ascale, h, l); arh[2 * q] = h; arl[2 * q] = l;
-        split16h(v.y * ascale, h, l); aih[2 * q] = h; ail[2 * q] = l;
-        split16h(v.z * ascale, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
-        split16h(v.w * ascale, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
-      }
+      // G[r][16 ks + 8 lh .. + 7], already split and scaled: block 2 ks + lh, parts Re hi / lo, Im hi / lo
+      const char* grow = buf + (size_t)r * LY::GROW;
+      const int sw = r % LY::GCPR;
+      const shortx8 arh = *(const shortx8*)(grow + ((8 * ks + 4 * lh + 0) ^ sw) * 16);
+      const shortx8 arl = *(const shortx8*)(grow + ((8 * ks + 4 * lh + 1) ^ sw) * 16);
+      const shortx8 aih = *(const shortx8*)(grow + ((8 * ks + 4 * lh + 2) ^ sw) * 16);
+      const shortx8 ail = *(const shortx8*)(grow + ((8 * ks + 4 * lh + 3) ^ sw) * 16);
 #pragma unroll
       for (int m = 0; m < KBW; ++m) {
         const int kb = kb0 + kg + 4 * m;
@@ -418,7 +504,7 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
         }
       }
     }
-    if (++since == IM_FL || st + 1 == st1) {   // flush into FP64
+    if (++since == FL || st + 1 == st1) {   // flush into FP64
       since = 0;
 #pragma unroll
       for (int m = 0; m < KBW; ++m)
@@ -540,12 +626,19 @@ static size_t inner_lds(const Plan* p) {
   return ((size_t)GPOS * 2 * p->L * NPL + GPOS * NPL + (size_t)AC * GPOS * 2) * sizeof(float);
 }
 
-// matrix-core inner products: stages of 64 positions (real stack) or 32 (complex), N % 8 == 0
+// matrix-core inner products: stages of 32 positions (real stack) or 16 (complex), N % 8 == 0, as
+// many ring stages as fit the LDS (at most 4, at least 2)
+constexpr int IM_PC_REAL = 32, IM_PC_CPLX = 16;
+static int inner_stages(const Plan* p) {
+  const size_t sb = p->cplx ? InnerLayout<true, IM_PC_CPLX>::stage_bytes(p->L)
+                            : InnerLayout<false, IM_PC_REAL>::stage_bytes(p->L);
+  const int ns = (int)((160 * 1024) / sb);
+  return ns > 4 ? 4 : ns;
+}
 static bool inner_mfma_ok(const Plan* p) {
   if (p->N % 8) return false;
-  const size_t lds = 2 * (p->cplx ? InnerLayout<true, 32>::stage_bytes(p->L) : InnerLayout<false, 64>::stage_bytes(p->L));
-  const int kp2 = p->cplx ? InnerLayout<true, 32>::kp2(p->L) : InnerLayout<false, 64>::kp2(p->L);
-  return lds <= 160 * 1024 && kp2 <= 256;
+  const int kp2 = p->cplx ? InnerLayout<true, IM_PC_CPLX>::kp2(p->L) : InnerLayout<false, IM_PC_REAL>::kp2(p->L);
+  return inner_stages(p) >= 2 && kp2 <= 256;
 }
 static int inner_mfma_wgs() { return 256; }
 
@@ -564,7 +657,7 @@ size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   s += update_ws_bytes(p, ch);
   s += apply_ws_bytes(N, ch, B, 0);
   s += align_up((size_t)n_alpha * 8, 256);
-  s += align_up((size_t)ch * ntile * 4, 256);                       // tile maxima of G
+  s += align_up((size_t)2 * ch * ceil_div(N, 64) * 4, 256);         // row-norm maxima of GY and X
   s += align_up((size_t)ch * 8, 256);                               // G scales
   (void)x_shared;
   return s;
@@ -582,26 +675,37 @@ static void coefficient_derivatives(double alpha, int L, std::vector<double>& d)
 }
 
 static int inner_mfma_grid(const Plan* p) {
-  const int pc = p->cplx ? 32 : 64;
+  const int pc = p->cplx ? IM_PC_CPLX : IM_PC_REAL;
   const int nstage = (int)(((size_t)p->N * p->N) / pc);
   return nstage < inner_mfma_wgs() ? nstage : inner_mfma_wgs();
+}
+
+template <bool CPLX, int PC, int NS>
+static fgfrft_status inner_mfma_launch_ns(const Plan* p, const cplx64* G, int nc, const float2* gsc, double* partial,
+                                          hipStream_t s) {
+  using LY = InnerLayout<CPLX, PC>;
+  static_assert(IM_FLPOS % PC == 0, "flush interval in whole stages");
+  const int nstage = (int)(((size_t)p->N * p->N) / PC);
+  const int nwg = inner_mfma_grid(p), spw = ceil_div(nstage, nwg);
+  const int lds = (int)(NS * LY::stage_bytes(p->L));
+  const int KB = LY::kp2(p->L) / 32;
+  auto kern = k_inner_mfma<CPLX, PC, 1, NS>;
+  FG_HIP(raise_lds_limit((const void*)kern, lds));
+  // four k-blocks (one per wave pair) per pass over the positions
+  for (int kb0 = 0; kb0 < KB; kb0 += 4)
+    kern<<<nwg, 64 * IM_NW, lds, s>>>(p->stack, p->P, p->N, p->L, G, nc, gsc, spw, nstage, kb0, partial);
+  FG_LAUNCHED("inner_mfma");
+  return FGFRFT_OK;
 }
 
 template <bool CPLX, int PC>
 static fgfrft_status inner_mfma_launch(const Plan* p, const cplx64* G, int nc, const float2* gsc, double* partial,
                                        hipStream_t s) {
-  using LY = InnerLayout<CPLX, PC>;
-  const int nstage = (int)(((size_t)p->N * p->N) / PC);
-  const int nwg = inner_mfma_grid(p), spw = ceil_div(nstage, nwg);
-  const int lds = (int)(2 * LY::stage_bytes(p->L));
-  const int KB = LY::kp2(p->L) / 32;
-  FG_HIP(raise_lds_limit((const void*)k_inner_mfma<CPLX, PC, 1>, lds));
-  // four k-blocks (one per wave pair) per pass over the positions
-  for (int kb0 = 0; kb0 < KB; kb0 += 4)
-    k_inner_mfma<CPLX, PC, 1><<<nwg, 64 * IM_NW, lds, s>>>(p->stack, p->P, p->N, p->L, G, nc, gsc, spw, nstage, kb0,
-                                                           partial);
-  FG_LAUNCHED("inner_mfma");
-  return FGFRFT_OK;
+  switch (inner_stages(p)) {
+    case 2: return inner_mfma_launch_ns<CPLX, PC, 2>(p, G, nc, gsc, partial, s);
+    case 3: return inner_mfma_launch_ns<CPLX, PC, 3>(p, G, nc, gsc, partial, s);
+    default: return inner_mfma_launch_ns<CPLX, PC, 4>(p, G, nc, gsc, partial, s);
+  }
 }
 
 fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const void* X, int x_complex, int x_shared,
@@ -613,7 +717,7 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
     set_error("grad workspace too small: %zu < %zu", ws_bytes, grad_ws_bytes(p, n_alpha, B, x_shared));
     return FGFRFT_ENOMEM;
   }
-  const size_t ntile = (size_t)ceil_div(N, 64) * ceil_div(N, 64);
+  const int nrch = ceil_div(N, 64);
   size_t part = (size_t)npairs * ch * 2 * K * 16;
   const size_t part2 = (size_t)inner_mfma_wgs() * ch * K * 16;
   if (part2 > part) part = part2;
@@ -625,7 +729,9 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   void* uws = base; base += update_ws_bytes(p, ch);
   void* aws = base; base += apply_ws_bytes(N, ch, B, 0);
   double* neg_dev = (double*)base; base += align_up((size_t)n_alpha * 8, 256);
-  float* gmax = (float*)base; base += align_up((size_t)ch * ntile * 4, 256);
+  float* gy2 = (float*)base;
+  float* x2 = gy2 + (size_t)ch * nrch;
+  base += align_up((size_t)2 * ch * nrch * 4, 256);
   float2* gsc = (float2*)base;
   const bool use_mfma = inner_mfma_ok(p);
 
@@ -653,27 +759,36 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
         FG_LAUNCHED("sum_orders");
       }
     }
-    // ---- G = GY X^H for the chunk
+    // ---- G = GY X^H for the chunk (split and scaled per order for the matrix-core inner products)
     {
       dim3 g(ceil_div(N, 64), ceil_div(N, 64), nc);
       const void* xa = x_shared ? X : (const void*)((const char*)X + (size_t)a0 * NB * (x_complex ? 8 : 4));
-      float* gm = use_mfma ? gmax : nullptr;
       const cplx64* gya = gy + (size_t)a0 * NB;
+      if (use_mfma) {   // per-order scales from the row norms of GY and X
+        k_rownorm2_max<true><<<dim3(nc, nrch), 256, 0, s>>>(gya, N, B, NB, gy2);
+        const int nx = x_shared ? 1 : nc;
+        if (x_complex) k_rownorm2_max<true><<<dim3(nx, nrch), 256, 0, s>>>(xa, N, B, NB, x2);
+        else k_rownorm2_max<false><<<dim3(nx, nrch), 256, 0, s>>>(xa, N, B, NB, x2);
+        k_gbound_scale<<<nc, 256, 0, s>>>(gy2, x2, nrch, x_shared, gsc);
+        FG_LAUNCHED("gradient scales");
+      }
       const bool vec = B % 4 == 0 && (uintptr_t)gya % 16 == 0 && (uintptr_t)xa % 16 == 0;
-      if (x_complex) {
-        if (vec) k_outer<true, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
-        else k_outer<true, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
-      } else {
-        if (vec) k_outer<false, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
-        else k_outer<false, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gm);
+      const int key = (x_complex ? 4 : 0) | (vec ? 2 : 0) | (use_mfma ? 1 : 0);
+      switch (key) {
+        case 0: k_outer<false, false, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 1: k_outer<false, false, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 2: k_outer<false, true, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 3: k_outer<false, true, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 4: k_outer<true, false, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 5: k_outer<true, false, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 6: k_outer<true, true, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
+        case 7: k_outer<true, true, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
       }
       FG_LAUNCHED("outer");
     }
     if (use_mfma) {
-      k_gscale<<<nc, 256, 0, s>>>(gmax, (int)ntile, gsc);
-      FG_LAUNCHED("gscale");
-      fgfrft_status rc = p->cplx ? inner_mfma_launch<true, 32>(p, Gbuf, nc, gsc, partial, s)
-                                 : inner_mfma_launch<false, 64>(p, Gbuf, nc, gsc, partial, s);
+      fgfrft_status rc = p->cplx ? inner_mfma_launch<true, IM_PC_CPLX>(p, Gbuf, nc, gsc, partial, s)
+                                 : inner_mfma_launch<false, IM_PC_REAL>(p, Gbuf, nc, gsc, partial, s);
       if (rc) return rc;
       k_inner_sum_wg<<<dim3(K, nc), 256, 0, s>>>(partial, inner_mfma_grid(p), nc, K, a0, T);
       FG_LAUNCHED("inner_sum");
