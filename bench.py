@@ -581,7 +581,7 @@ def main():
     ap.add_argument("--n-alpha", type=int, default=256)
     ap.add_argument("--signals", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stacktype", default="fp32", choices=["fp32", "bf16x2"])
+    ap.add_argument("--stacktype", default="fp32", choices=["fp32", "fp16x2", "bf16x2"])
     ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-route comparison")
@@ -668,7 +668,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (split fp16 MFMA operands, fp32 accumulate)" if args.stacktype == "fp32" else "bf16x2",
+        "dtype": {"fp32": "f32 (split fp16 MFMA operands, fp32 accumulate)",
+                  "fp16x2": "f32 (stack stored as its split fp16 MFMA operands, fp32 accumulate)",
+                  "bf16x2": "bf16x2"}[args.stacktype],
         "data": "synthetic",
         "config": {"workload": "knn4096: kNN k=10 on 5-GMM 3-D points, N=4096, L=32, 256 orders in [-2,2], "
                                "64 real N(0,1) signals per order", "n_alpha": na, "signals_per_order": B,
@@ -695,7 +697,7 @@ def main():
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
 
-    if plan.info()["r_minus1"] <= 32 and args.stacktype in ("fp32", "bf16x2"):
+    if plan.info()["r_minus1"] <= 32:
         leg("real_F_route", lambda: realf_bench(plan, alphas, X))
         if "ms" in out["real_F_route"]:
             r = out["real_F_route"]

@@ -70,7 +70,11 @@ typedef enum {
 /* Storage of the resident power stack (M_1..M_L and M_1^H..M_L^H). */
 typedef enum {
   FGFRFT_STACK_FP32 = 0,     /* float32 (real F) or complex64 (complex F)                  */
-  FGFRFT_STACK_BF16X2 = 1    /* per real value a bf16 pair (hi, lo = bf16(x - hi)), 4 bytes */
+  FGFRFT_STACK_BF16X2 = 1,   /* per real value a bf16 pair (hi, lo = bf16(x - hi)), 4 bytes */
+  FGFRFT_STACK_FP16X2 = 2    /* per real value the fp16 pair of v = float(x) 2^12 (hi = fp16(v),
+                                lo = fp16(v - hi)), 4 bytes: the operands the FP32 stack is
+                                split into on the matrix cores, stored split, so every call
+                                gives bitwise the FP32 stack's results without the split work */
 } fgfrft_stacktype;
 
 /* Which operator the plan's online stage produces. */

@@ -51,7 +51,10 @@ static bool valid_sizes(int N, int L, int intype, int stacktype) {
   if (N < 1 || N > 32768) { set_error("N=%d outside [1, 32768]", N); return false; }
   if (L < 1 || L > 64) { set_error("L=%d outside [1, 64]", L); return false; }
   if (intype != FGFRFT_IN_C128 && intype != FGFRFT_IN_F64) { set_error("bad intype %d", intype); return false; }
-  if (stacktype != FGFRFT_STACK_FP32 && stacktype != FGFRFT_STACK_BF16X2) { set_error("bad stacktype %d", stacktype); return false; }
+  if (stacktype != FGFRFT_STACK_FP32 && stacktype != FGFRFT_STACK_BF16X2 && stacktype != FGFRFT_STACK_FP16X2) {
+    set_error("bad stacktype %d", stacktype);
+    return false;
+  }
   return true;
 }
 
@@ -308,7 +311,7 @@ fgfrft_status fgfrft_grad(fgfrft_plan_t plan, const double* alphas, int n_alpha,
     set_error("X_dev, dX_dev must be element-aligned, GY_dev 8-byte and ws_dev 256-byte aligned");
     return FGFRFT_EINVAL;
   }
-  if (p->stacktype != FGFRFT_STACK_FP32) { set_error("grad needs an FP32 power stack"); return FGFRFT_EUNSUPPORTED; }
+  if (p->stacktype == FGFRFT_STACK_BF16X2) { set_error("grad needs an FP32 or FP16X2 power stack"); return FGFRFT_EUNSUPPORTED; }
   try {   // host tables of the order loop: an allocation failure must not unwind through the C ABI
     return grad_run(p, alphas, n_alpha, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, GY_dev, dalpha, dX_dev,
                     ws_dev, ws_bytes, (hipStream_t)stream);

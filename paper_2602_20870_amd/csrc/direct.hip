@@ -12,7 +12,8 @@
 // runs and waves are added in a fixed order by a second kernel, with the identity term c_0 X.
 //
 // A BF16X2 stack (a packed bf16 hi / lo pair per entry) feeds the bf16 matrix cores directly with
-// bf16-split signals.  Every other configuration (complex F, complex X, N % 32 != 0) takes a plain
+// bf16-split signals; an FP16X2 stack (the fp16 pair the FP32 stack would be split into) feeds the
+// fp16 matrix cores directly, with the FP32 stack's results bit for bit.  Every other configuration (complex F, complex X, N % 32 != 0) takes a plain
 // kernel with one thread per output and FP64 accumulation.
 #include "internal.h"
 #include <math.h>
@@ -92,13 +93,15 @@ __device__ __forceinline__ void bsplit(float v, short& hi, short& lo) {
 //             c_{-(t+1)}; written as a partial of rows J when the chunk's terms are done.
 // Partials: pos / im [G][N][ncp] (runs), neg [nIB][N][ncp] (row blocks; the waves' parts are
 // added in LDS first).
-template <bool BF>
+// SM: stack storage, 0 FP32 (split here), 1 bf16 pairs, 2 fp16 pairs (used as stored).
+template <int SM>
 __global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict__ stack, const float* __restrict__ P,
                                                         int N, int L, const short* __restrict__ Xs, int ncp,
                                                         const float* __restrict__ gam, int CPR, int G, int nIB,
                                                         int ncb, float* __restrict__ part_pos,
                                                         float* __restrict__ part_im, float* __restrict__ part_neg) {
   constexpr int NS = 2;
+  constexpr bool BF = SM == 1;
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict_
         const int ch = (4 * ks + 2 * lh + q) ^ (r & 7);
         const float4 v = *(const float4*)(st + r * (DK * 4) + ch * 16);
         short h, l;
-        if (BF && !isP) {
+        if (SM != 0 && !isP) {
           const uint4 u4 = __builtin_bit_cast(uint4, v);
           ah[4 * q + 0] = (short)(u4.x & 0xffff); al[4 * q + 0] = (short)(u4.x >> 16);
           ah[4 * q + 1] = (short)(u4.y & 0xffff); al[4 * q + 1] = (short)(u4.y >> 16);
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict_
           const int rr = 32 * wave + 16 * ks + 8 * lh + e;
           const float v = *(const float*)(st + rr * (DK * 4) + (((l32 >> 2) ^ (rr & 7)) * 16) + (l32 & 3) * 4);
           short h, l;
-          if (BF) {
+          if (SM != 0) {
             const uint32_t u = __builtin_bit_cast(uint32_t, v);
             h = (short)(u & 0xffff);
             l = (short)(u >> 16);
@@ -328,11 +331,14 @@ __global__ __launch_bounds__(256) void k_direct_pair_reduce(const float* __restr
 // ---------------------------------------------------------------- plain kernel (any configuration)
 struct dc { double re, im; };
 
-template <bool C, bool BF>
+template <bool C, int SM>
 __device__ __forceinline__ dc stack_elem(const void* S, size_t idx) {
-  if (BF) {
+  if (SM != 0) {
     auto dec = [](uint32_t w) {
-      return (double)__uint_as_float(w << 16) + (double)__uint_as_float(w & 0xffff0000u);
+      if (SM == 1) return (double)__uint_as_float(w << 16) + (double)__uint_as_float(w & 0xffff0000u);
+      const _Float16 h = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffff));
+      const _Float16 l = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+      return ((double)h + (double)l) * (1.0 / kStackScale);
     };
     if (C) {
       const uint2 w = ((const uint2*)S)[idx];
@@ -358,7 +364,7 @@ __device__ __forceinline__ dc sig_elem(const void* X, size_t idx) {
 
 // One thread per output (i, c), columns fastest so a wave reads one stack row (broadcast) and
 // consecutive signal entries.  The P matrix is always FP32 / complex64.
-template <bool C, bool BF, bool XC>
+template <bool C, int SM, bool XC>
 __global__ __launch_bounds__(256) void k_direct_plain(const void* __restrict__ stack, const void* __restrict__ P, int N,
                                                       int L, const void* __restrict__ X, int ldx, int ncols, int ncp,
                                                       const float* __restrict__ gam, cplx64* __restrict__ Y,
@@ -372,8 +378,8 @@ __global__ __launch_bounds__(256) void k_direct_plain(const void* __restrict__ s
   for (int t = 0; t <= 2 * L; ++t) {
     double zr = 0.0, zi = 0.0;
     for (int j = 0; j < N; ++j) {
-      const dc s = t < 2 * L ? stack_elem<C, BF>((const char*)stack + (size_t)t * NN * sb, (size_t)i * N + j)
-                             : stack_elem<C, false>(P, (size_t)i * N + j);
+      const dc s = t < 2 * L ? stack_elem<C, SM>((const char*)stack + (size_t)t * NN * sb, (size_t)i * N + j)
+                             : stack_elem<C, 0>(P, (size_t)i * N + j);
       const dc x = sig_elem<XC>(X, (size_t)j * ldx + c);
       zr += s.re * x.re - s.im * x.im;
       zi += s.re * x.im + s.im * x.re;
@@ -451,11 +457,11 @@ size_t direct_ws_bytes(const Plan* p, int ncols, int ldx) {
   return direct_ws(p, ncols, ldx, nullptr).bytes;
 }
 
-template <bool C, bool BF, bool XC>
+template <bool C, int SM, bool XC>
 static void launch_plain(const Plan* p, const void* X, int ldx, int ncols, int ncp, const float* gam, void* Y, int ldy,
                          hipStream_t s) {
   const size_t n = (size_t)p->N * ncols;
-  k_direct_plain<C, BF, XC><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p->stack, p->P, p->N, p->L, X, ldx, ncols, ncp,
+  k_direct_plain<C, SM, XC><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p->stack, p->P, p->N, p->L, X, ldx, ncols, ncp,
                                                                         gam, (cplx64*)Y, ldy);
 }
 
@@ -473,16 +479,21 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
     k_dcoef<<<ceil_div(nrow * d.ncp, 256), 256, 0, s>>>(alphas_dev, n_alpha, col_order_dev, ncols, d.ncp, L, nullptr,
                                                           1.0f, w.gam);
     FG_LAUNCHED("direct coefficients");
-    const int key = (p->cplx ? 4 : 0) | (p->stacktype == FGFRFT_STACK_BF16X2 ? 2 : 0) | (x_complex ? 1 : 0);
+    const int sm = p->stacktype;   // 0 FP32, 1 BF16X2, 2 FP16X2
+    const int key = (p->cplx ? 6 : 0) + 2 * sm + (x_complex ? 1 : 0);
     switch (key) {
-      case 0: launch_plain<false, false, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 1: launch_plain<false, false, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 2: launch_plain<false, true, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 3: launch_plain<false, true, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 4: launch_plain<true, false, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 5: launch_plain<true, false, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 6: launch_plain<true, true, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
-      case 7: launch_plain<true, true, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 0: launch_plain<false, 0, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 1: launch_plain<false, 0, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 2: launch_plain<false, 1, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 3: launch_plain<false, 1, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 4: launch_plain<false, 2, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 5: launch_plain<false, 2, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 6: launch_plain<true, 0, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 7: launch_plain<true, 0, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 8: launch_plain<true, 1, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 9: launch_plain<true, 1, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 10: launch_plain<true, 2, false>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
+      case 11: launch_plain<true, 2, true>(p, X, ldx, ncols, d.ncp, w.gam, Y, ldy, s); break;
     }
     FG_LAUNCHED("direct (plain)");
     return FGFRFT_OK;
@@ -499,7 +510,7 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
     set_error("direct grid too large");
     return FGFRFT_EUNSUPPORTED;
   }
-  auto kp = bf ? k_direct_pair<true> : k_direct_pair<false>;
+  auto kp = bf ? k_direct_pair<1> : p->stacktype == FGFRFT_STACK_FP16X2 ? k_direct_pair<2> : k_direct_pair<0>;
   FG_HIP(raise_lds_limit((const void*)kp, d.lds));
   kp<<<(unsigned)nb, 256, d.lds, s>>>((const float*)p->stack, (const float*)p->P, N, L, w.Xs, d.ncp, w.gam, d.CPR,
                                       d.G, d.nIB, d.ncb, w.part_re, w.part_im, w.part_neg);

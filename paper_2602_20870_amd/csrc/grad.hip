@@ -237,7 +237,15 @@ __global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ 
 // positions for every order of the sub-chunk; B_{2L} = P, B_{2L+1} = I.
 constexpr int AC = 4;
 
-template <bool CPLX>
+// value of one FP16X2 stack entry (fp16 pair of the 2^12-scaled value)
+__device__ __forceinline__ float fp16_pair_value(uint32_t w) {
+  const _Float16 h = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffff));
+  const _Float16 l = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  return ((float)h + (float)l) * (1.0f / kStackScale);
+}
+
+// SM 2: FP16X2 stack entries, decoded on staging.
+template <bool CPLX, int SM>
 __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, const void* __restrict__ Pm, int N, int L,
                                                int nb, const cplx64* __restrict__ G, int n_chunk,
                                                double* __restrict__ partial) {
@@ -257,7 +265,15 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
     const bool inb = row < N && col < N;
     float* dst = S + ((size_t)p * L2 + k) * NPL;
     const size_t off = (size_t)k * NN + (size_t)row * N + col;
-    if (CPLX) {
+    if (SM == 2) {
+      if (CPLX) {
+        const uint2 w = inb ? ((const uint2*)stack)[off] : make_uint2(0u, 0u);
+        dst[0] = fp16_pair_value(w.x);
+        dst[NPL - 1] = fp16_pair_value(w.y);
+      } else {
+        dst[0] = inb ? fp16_pair_value(((const uint32_t*)stack)[off]) : 0.f;
+      }
+    } else if (CPLX) {
       const float2 v = inb ? ((const float2*)stack)[off] : make_float2(0.f, 0.f);
       dst[0] = v.x;
       dst[NPL - 1] = v.y;
@@ -371,7 +387,9 @@ __device__ __forceinline__ void wait_vm_upto(int n) {
   }
 }
 
-template <bool CPLX, int PC, int KBW, int NS>
+// SM 2: the stack rows (k < 2L) are FP16X2 pairs, used as stored; P, its copies and the identity row
+// are FP32 and split here, as every row is for SM 0.
+template <bool CPLX, int PC, int KBW, int NS, int SM>
 __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __restrict__ stack, const void* __restrict__ Pm,
                                                              int N, int L, const cplx64* __restrict__ G, int n_c,
                                                              const float2* __restrict__ gsc, int spw, int nstage,
@@ -462,27 +480,44 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
         const int k = 32 * kb + l32;
         shortx8 brh, brl, bih, bil;
         const char* row = buf + LY::GB + (size_t)k * LY::SROW;
+        const bool pairs = SM == 2 && k < 2 * L;
         if (CPLX) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {   // two complex per chunk
             const int c = (8 * ks + 4 * lh + q) ^ (k % LY::SCPR);
             const float4 v = *(const float4*)(row + c * 16);
-            short h, l;
-            split16h(v.x * kStackScale, h, l); brh[2 * q] = h; brl[2 * q] = l;
-            split16h(v.y * kStackScale, h, l); bih[2 * q] = h; bil[2 * q] = l;
-            split16h(v.z * kStackScale, h, l); brh[2 * q + 1] = h; brl[2 * q + 1] = l;
-            split16h(v.w * kStackScale, h, l); bih[2 * q + 1] = h; bil[2 * q + 1] = l;
+            if (pairs) {
+              const uint4 u = __builtin_bit_cast(uint4, v);
+              brh[2 * q] = (short)(u.x & 0xffff); brl[2 * q] = (short)(u.x >> 16);
+              bih[2 * q] = (short)(u.y & 0xffff); bil[2 * q] = (short)(u.y >> 16);
+              brh[2 * q + 1] = (short)(u.z & 0xffff); brl[2 * q + 1] = (short)(u.z >> 16);
+              bih[2 * q + 1] = (short)(u.w & 0xffff); bil[2 * q + 1] = (short)(u.w >> 16);
+            } else {
+              short h, l;
+              split16h(v.x * kStackScale, h, l); brh[2 * q] = h; brl[2 * q] = l;
+              split16h(v.y * kStackScale, h, l); bih[2 * q] = h; bil[2 * q] = l;
+              split16h(v.z * kStackScale, h, l); brh[2 * q + 1] = h; brl[2 * q + 1] = l;
+              split16h(v.w * kStackScale, h, l); bih[2 * q + 1] = h; bil[2 * q + 1] = l;
+            }
           }
         } else {
 #pragma unroll
           for (int q = 0; q < 2; ++q) {   // four reals per chunk
             const int c = (4 * ks + 2 * lh + q) ^ (k % LY::SCPR);
             const float4 v = *(const float4*)(row + c * 16);
-            short h, l;
-            split16h(v.x * kStackScale, h, l); brh[4 * q] = h; brl[4 * q] = l;
-            split16h(v.y * kStackScale, h, l); brh[4 * q + 1] = h; brl[4 * q + 1] = l;
-            split16h(v.z * kStackScale, h, l); brh[4 * q + 2] = h; brl[4 * q + 2] = l;
-            split16h(v.w * kStackScale, h, l); brh[4 * q + 3] = h; brl[4 * q + 3] = l;
+            if (pairs) {
+              const uint4 u = __builtin_bit_cast(uint4, v);
+              brh[4 * q] = (short)(u.x & 0xffff); brl[4 * q] = (short)(u.x >> 16);
+              brh[4 * q + 1] = (short)(u.y & 0xffff); brl[4 * q + 1] = (short)(u.y >> 16);
+              brh[4 * q + 2] = (short)(u.z & 0xffff); brl[4 * q + 2] = (short)(u.z >> 16);
+              brh[4 * q + 3] = (short)(u.w & 0xffff); brl[4 * q + 3] = (short)(u.w >> 16);
+            } else {
+              short h, l;
+              split16h(v.x * kStackScale, h, l); brh[4 * q] = h; brl[4 * q] = l;
+              split16h(v.y * kStackScale, h, l); brh[4 * q + 1] = h; brl[4 * q + 1] = l;
+              split16h(v.z * kStackScale, h, l); brh[4 * q + 2] = h; brl[4 * q + 2] = l;
+              split16h(v.w * kStackScale, h, l); brh[4 * q + 3] = h; brl[4 * q + 3] = l;
+            }
           }
         }
         // conj(g) b: Re = gr br + gi bi, Im = gr bi - gi br (real b: Re = gr b, Im = -gi b)
@@ -674,13 +709,19 @@ static void coefficient_derivatives(double alpha, int L, std::vector<double>& d)
   }
 }
 
+static const void* inner_tile_kernel(const Plan* p) {
+  const bool f16 = p->stacktype == FGFRFT_STACK_FP16X2;
+  if (p->cplx) return f16 ? (const void*)k_inner<true, 2> : (const void*)k_inner<true, 0>;
+  return f16 ? (const void*)k_inner<false, 2> : (const void*)k_inner<false, 0>;
+}
+
 static int inner_mfma_grid(const Plan* p) {
   const int pc = p->cplx ? IM_PC_CPLX : IM_PC_REAL;
   const int nstage = (int)(((size_t)p->N * p->N) / pc);
   return nstage < inner_mfma_wgs() ? nstage : inner_mfma_wgs();
 }
 
-template <bool CPLX, int PC, int NS>
+template <bool CPLX, int PC, int NS, int SM>
 static fgfrft_status inner_mfma_launch_ns(const Plan* p, const cplx64* G, int nc, const float2* gsc, double* partial,
                                           hipStream_t s) {
   using LY = InnerLayout<CPLX, PC>;
@@ -689,7 +730,7 @@ static fgfrft_status inner_mfma_launch_ns(const Plan* p, const cplx64* G, int nc
   const int nwg = inner_mfma_grid(p), spw = ceil_div(nstage, nwg);
   const int lds = (int)(NS * LY::stage_bytes(p->L));
   const int KB = LY::kp2(p->L) / 32;
-  auto kern = k_inner_mfma<CPLX, PC, 1, NS>;
+  auto kern = k_inner_mfma<CPLX, PC, 1, NS, SM>;
   FG_HIP(raise_lds_limit((const void*)kern, lds));
   // four k-blocks (one per wave pair) per pass over the positions
   for (int kb0 = 0; kb0 < KB; kb0 += 4)
@@ -698,14 +739,21 @@ static fgfrft_status inner_mfma_launch_ns(const Plan* p, const cplx64* G, int nc
   return FGFRFT_OK;
 }
 
+template <bool CPLX, int PC, int SM>
+static fgfrft_status inner_mfma_launch_sm(const Plan* p, const cplx64* G, int nc, const float2* gsc, double* partial,
+                                          hipStream_t s) {
+  switch (inner_stages(p)) {
+    case 2: return inner_mfma_launch_ns<CPLX, PC, 2, SM>(p, G, nc, gsc, partial, s);
+    case 3: return inner_mfma_launch_ns<CPLX, PC, 3, SM>(p, G, nc, gsc, partial, s);
+    default: return inner_mfma_launch_ns<CPLX, PC, 4, SM>(p, G, nc, gsc, partial, s);
+  }
+}
+
 template <bool CPLX, int PC>
 static fgfrft_status inner_mfma_launch(const Plan* p, const cplx64* G, int nc, const float2* gsc, double* partial,
                                        hipStream_t s) {
-  switch (inner_stages(p)) {
-    case 2: return inner_mfma_launch_ns<CPLX, PC, 2>(p, G, nc, gsc, partial, s);
-    case 3: return inner_mfma_launch_ns<CPLX, PC, 3>(p, G, nc, gsc, partial, s);
-    default: return inner_mfma_launch_ns<CPLX, PC, 4>(p, G, nc, gsc, partial, s);
-  }
+  if (p->stacktype == FGFRFT_STACK_FP16X2) return inner_mfma_launch_sm<CPLX, PC, 2>(p, G, nc, gsc, partial, s);
+  return inner_mfma_launch_sm<CPLX, PC, 0>(p, G, nc, gsc, partial, s);
 }
 
 fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const void* X, int x_complex, int x_shared,
@@ -737,7 +785,7 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
 
   const size_t lds = inner_lds(p);
   if (!use_mfma)
-    FG_HIP(raise_lds_limit(p->cplx ? (const void*)k_inner<true> : (const void*)k_inner<false>, (int)lds));
+    FG_HIP(raise_lds_limit(inner_tile_kernel(p), (int)lds));
   std::vector<double> neg(n_alpha);
   for (int a = 0; a < n_alpha; ++a) neg[a] = -alphas[a];
   FG_HIP(hipMemcpyAsync(neg_dev, neg.data(), (size_t)n_alpha * 8, hipMemcpyHostToDevice, s));
@@ -793,8 +841,8 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
       k_inner_sum_wg<<<dim3(K, nc), 256, 0, s>>>(partial, inner_mfma_grid(p), nc, K, a0, T);
       FG_LAUNCHED("inner_sum");
     } else {
-      if (p->cplx) k_inner<true><<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
-      else k_inner<false><<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
+      auto kt = (void (*)(const void*, const void*, int, int, int, const cplx64*, int, double*))inner_tile_kernel(p);
+      kt<<<npairs, 256, lds, s>>>(p->stack, p->P, N, L, nb, Gbuf, nc, partial);
       FG_LAUNCHED("inner");
       k_inner_sum<<<dim3(K, nc), 256, 0, s>>>(partial, npairs, nc, K, a0, T);
       FG_LAUNCHED("inner_sum");

@@ -417,13 +417,22 @@ __global__ __launch_bounds__(256) void k_projector(const double* __restrict__ W,
 }
 
 // FP64 (row-major) -> resident format.  kind 0: float (real) / cplx64 (complex);
-// kind 1: bf16 pair per real value (hi = bf16(x), lo = bf16(x - hi)), packed hi | lo << 16.
+// kind 1: bf16 pair per real value (hi = bf16(x), lo = bf16(x - hi)), packed hi | lo << 16;
+// kind 2: fp16 pair per real value of v = float(x) 2^12 (hi = fp16(v), lo = fp16(v - hi)), packed
+// hi | lo << 16 -- exactly the operands the FP32 stack is split into when it is read.
 __device__ __forceinline__ uint32_t bf16_pair(double x) {
   const float xf = (float)x;
   const __bf16 hi = (__bf16)xf;
   const __bf16 lo = (__bf16)(xf - (float)hi);
   return (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
 }
+__device__ __forceinline__ uint32_t fp16_pair(double x) {
+  const float v = (float)x * kStackScale;
+  const _Float16 hi = (_Float16)v;
+  const _Float16 lo = (_Float16)(v - (float)hi);
+  return (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+}
+__device__ __forceinline__ uint32_t pair_of(double x, int kind) { return kind == 1 ? bf16_pair(x) : fp16_pair(x); }
 
 template <bool C>
 __global__ __launch_bounds__(256) void k_store(const double* __restrict__ M, size_t total, int kind, void* __restrict__ out) {
@@ -433,8 +442,8 @@ __global__ __launch_bounds__(256) void k_store(const double* __restrict__ M, siz
       if (C) ((cplx64*)out)[idx] = cplx64{(float)v.re, (float)v.im};
       else ((float*)out)[idx] = (float)v.re;
     } else {
-      if (C) ((uint2*)out)[idx] = make_uint2(bf16_pair(v.re), bf16_pair(v.im));
-      else ((uint32_t*)out)[idx] = bf16_pair(v.re);
+      if (C) ((uint2*)out)[idx] = make_uint2(pair_of(v.re, kind), pair_of(v.im, kind));
+      else ((uint32_t*)out)[idx] = pair_of(v.re, kind);
     }
   }
 }
@@ -473,8 +482,8 @@ __global__ __launch_bounds__(256) void k_store_adjoint(const double* __restrict_
       if (C) ((cplx64*)out)[idx] = cplx64{(float)re, (float)im};
       else ((float*)out)[idx] = (float)re;
     } else {
-      if (C) ((uint2*)out)[idx] = make_uint2(bf16_pair(re), bf16_pair(im));
-      else ((uint32_t*)out)[idx] = bf16_pair(re);
+      if (C) ((uint2*)out)[idx] = make_uint2(pair_of(re, kind), pair_of(im, kind));
+      else ((uint32_t*)out)[idx] = pair_of(re, kind);
     }
   }
 }
@@ -620,7 +629,7 @@ fgfrft_status plan_build(Plan* p, const void* F, double tau, void* scratch, size
   FG_LAUNCHED("store P");
 
   // ---- 4. M_n = F M_{n-1}, stored as the resident stack; drift at ceil(L/2) and L
-  const int kind = p->stacktype == FGFRFT_STACK_BF16X2 ? 1 : 0;
+  const int kind = p->stacktype == FGFRFT_STACK_BF16X2 ? 1 : p->stacktype == FGFRFT_STACK_FP16X2 ? 2 : 0;
   double drift = 0.0;
   for (int n = 1; n <= L; ++n) {
     if ((rc = gemm_f64(C, false, N, N, N, Fd, N, Mprev, N, Mcur, N, s))) return rc;

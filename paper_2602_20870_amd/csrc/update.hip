@@ -269,7 +269,9 @@ __device__ __forceinline__ void stage_p(const void* __restrict__ Pm, int N, int 
 
 // B fragments for this lane's position p of the strip (all k, split into 16-bit parts) and the
 // extra k-step operand (P_re, P_im, identity at k = 0..2 for lanes lh == 0, zero elsewhere).
-template <bool CPLX, int KP, int TR, int TC, bool BF>
+// SM: stack storage (0 FP32, split here; 1 bf16 pairs; 2 fp16 pairs of the 2^12-scaled value, both
+// used as stored).  The P tile is FP32 in every format.
+template <bool CPLX, int KP, int TR, int TC, int SM>
 __device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const float* Pt, int N, int row0, int col0,
                                                    int p, int lh, shortx8 (&bh)[CPLX ? 2 : 1][KP / 16],
                                                    shortx8 (&bl)[CPLX ? 2 : 1][KP / 16], shortx8& bxh, shortx8& bxl) {
@@ -284,7 +286,7 @@ __device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const floa
       for (int pl = 0; pl < NPL; ++pl) {
         const uint32_t bits = R[((size_t)k * PT + p) * NPL + pl];
         short h, l;
-        if (BF) { h = (short)(bits & 0xffff); l = (short)(bits >> 16); }
+        if (SM != 0) { h = (short)(bits & 0xffff); l = (short)(bits >> 16); }
         else split_f32<false>(__builtin_bit_cast(float, bits), h, l);
         bh[pl][ks][j] = h;
         bl[pl][ks][j] = l;
@@ -297,11 +299,11 @@ __device__ __forceinline__ void load_fragments_raw(const uint32_t* R, const floa
     const float pr = CPLX ? Pt[2 * p] : Pt[p];
     const float pi = CPLX ? Pt[2 * p + 1] : 0.f;
     short h, l;
-    split_f32<BF>(pr, h, l);
+    split_f32<SM == 1>(pr, h, l);
     bxh[0] = h; bxl[0] = l;
-    split_f32<BF>(pi, h, l);
+    split_f32<SM == 1>(pi, h, l);
     bxh[1] = h; bxl[1] = l;
-    split_f32<BF>((row == col && row < N) ? 1.f : 0.f, h, l);
+    split_f32<SM == 1>((row == col && row < N) ? 1.f : 0.f, h, l);
     bxh[2] = h; bxl[2] = l;
   }
 }
@@ -492,7 +494,7 @@ __device__ __forceinline__ void load_table_direct(const uint16_t* __restrict__ t
 // then reuses the LDS for the coefficient table, CAP orders at a time, and runs the order loop,
 // which touches only LDS, the matrix cores and stores: nothing in it waits on the memory counter
 // the stores also use, so the stores stream without drains.
-template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, bool OFF32, int CAPV, bool PAIR, bool ROUT>
+template <bool CPLX, int KP, int TR, int TC, int SM, int NT, int MINW, bool OFF32, int CAPV, bool PAIR, bool ROUT>
 __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restrict__ stack, const void* __restrict__ Pm,
                                                            int N, int L, int nJ, const uint16_t* __restrict__ table,
                                                            const float4* __restrict__ epi, int n_alpha, int n_pad,
@@ -500,6 +502,7 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
   using LY = StripLayout<CPLX, KP, TR, TC, CAPV>;
   constexpr int NPL = LY::NPL, CH = LY::CH, KS = KP / 16, PT = LY::PT, CAP = LY::CAP;
   constexpr int NW = NT / 64, NBLK = PT / 32, BPW = NBLK >= NW ? NBLK / NW : 1;
+  constexpr bool BF = SM == 1;   // bf16 matrix cores for a BF16X2 stack, fp16 otherwise
   extern __shared__ __align__(16) shortx8 smem[];
   char* R = (char*)smem;
   float* Pt = (float*)(R + LY::RB);
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(NT, MINW) void k_update_strip(const void* __restric
   shortx8 bh[BPW][NPL][KS], bl[BPW][NPL][KS], bxh[BPW], bxl[BPW];
 #pragma unroll
   for (int j = 0; j < BPW; ++j)
-    load_fragments_raw<CPLX, KP, TR, TC, BF>((const uint32_t*)R, Pt, N, row0, col0, pos_of(j), lh, bh[j], bl[j], bxh[j],
+    load_fragments_raw<CPLX, KP, TR, TC, SM>((const uint32_t*)R, Pt, N, row0, col0, pos_of(j), lh, bh[j], bl[j], bxh[j],
                                          bxl[j]);
   for (int c0 = 0; c0 < n_pad; c0 += CAP) {
     const int ncap = n_pad - c0 < CAP ? n_pad - c0 : CAP;
@@ -586,7 +589,7 @@ fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, 
   return FGFRFT_OK;
 }
 
-template <bool CPLX, int KP, int TR, int TC, bool BF, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false,
+template <bool CPLX, int KP, int TR, int TC, int SM, int NT, int MINW, int CAPV = (KP <= 64 ? 256 : 128), bool PAIR = false,
           bool ROUT = false>
 static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha,
                                          int n_pad, void* Q, hipStream_t s) {
@@ -594,8 +597,8 @@ static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, c
   constexpr size_t lds = LY::RB + LY::PB > LY::TB + (size_t)LY::CAP * 16 ? LY::RB + LY::PB : LY::TB + (size_t)LY::CAP * 16;
   static_assert(lds <= 160 * 1024, "LDS budget");
   const bool off32 = (size_t)5 * p->N * p->N * sizeof(cplx64) < ((size_t)1 << 32);
-  auto kern = off32 ? k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, true, CAPV, PAIR, ROUT>
-                    : k_update_strip<CPLX, KP, TR, TC, BF, NT, MINW, false, CAPV, PAIR, ROUT>;
+  auto kern = off32 ? k_update_strip<CPLX, KP, TR, TC, SM, NT, MINW, true, CAPV, PAIR, ROUT>
+                    : k_update_strip<CPLX, KP, TR, TC, SM, NT, MINW, false, CAPV, PAIR, ROUT>;
   FG_HIP(raise_lds_limit((const void*)kern, (int)lds));
   const int nI = ceil_div(p->N, TR), nJ = ceil_div(p->N, TC);
   kern<<<nI * nJ, NT, lds, s>>>(p->stack, p->P, p->N, p->L, nJ, table, epi, n_alpha, n_pad, Q);
@@ -605,21 +608,21 @@ static fgfrft_status launch_update_strip(const Plan* p, const uint16_t* table, c
 
 // (KP, TR, pairing): strips of TR rows x 64 columns; the staged tiles, and then the order table
 // (up to 256 orders for KP <= 64, 128 beyond), fit 64-68 KB of LDS, two workgroups of 4 waves per CU.
-template <bool BF, bool ROUT = false>
+template <int SM, bool ROUT = false>
 static fgfrft_status dispatch(const Plan* p, const uint16_t* table, const float4* epi, int n_alpha, int np, void* Q,
                               hipStream_t s) {
   const int KP = kp_of(p->L);
   if (!p->cplx) {
     switch (KP) {
-      case 32: return launch_update_strip<false, 32, 8, 64, BF, 256, 2, 256, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_strip<false, 64, 4, 64, BF, 256, 2, 256, true, ROUT>(p, table, epi, n_alpha, np, Q, s);
-      case 96: return launch_update_strip<false, 96, 2, 64, BF, 256, 2, 128, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
-      case 128: return launch_update_strip<false, 128, 2, 64, BF, 256, 2, 128, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<false, 32, 8, 64, SM, 256, 2, 256, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<false, 64, 4, 64, SM, 256, 2, 256, true, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 96: return launch_update_strip<false, 96, 2, 64, SM, 256, 2, 128, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
+      case 128: return launch_update_strip<false, 128, 2, 64, SM, 256, 2, 128, false, ROUT>(p, table, epi, n_alpha, np, Q, s);
     }
   } else if constexpr (!ROUT) {
     switch (KP) {
-      case 32: return launch_update_strip<true, 32, 4, 64, BF, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
-      case 64: return launch_update_strip<true, 64, 2, 64, BF, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
+      case 32: return launch_update_strip<true, 32, 4, 64, SM, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
+      case 64: return launch_update_strip<true, 64, 2, 64, SM, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
     }
   }
   set_error("unsupported L=%d for %s F", p->L, p->cplx ? "complex" : "real");
@@ -638,10 +641,14 @@ fgfrft_status update_launch(const Plan* p, const double* alphas_dev, int n_alpha
   float4* epi = (float4*)(base + align_up((size_t)np * 2 * KP * 2, 256));
   fgfrft_status rc = coef_launch(p, alphas_dev, n_alpha, np, table, epi, 0, s);
   if (rc) return rc;
-  const bool bf = p->stacktype == FGFRFT_STACK_BF16X2;
-  if (real_plane)
-    return bf ? dispatch<true, true>(p, table, epi, n_alpha, np, Q, s) : dispatch<false, true>(p, table, epi, n_alpha, np, Q, s);
-  return bf ? dispatch<true>(p, table, epi, n_alpha, np, Q, s) : dispatch<false>(p, table, epi, n_alpha, np, Q, s);
+  switch (p->stacktype) {
+    case FGFRFT_STACK_BF16X2:
+      return real_plane ? dispatch<1, true>(p, table, epi, n_alpha, np, Q, s) : dispatch<1>(p, table, epi, n_alpha, np, Q, s);
+    case FGFRFT_STACK_FP16X2:
+      return real_plane ? dispatch<2, true>(p, table, epi, n_alpha, np, Q, s) : dispatch<2>(p, table, epi, n_alpha, np, Q, s);
+    default:
+      return real_plane ? dispatch<0, true>(p, table, epi, n_alpha, np, Q, s) : dispatch<0>(p, table, epi, n_alpha, np, Q, s);
+  }
 }
 
 }  // namespace fgfrft

@@ -16,7 +16,7 @@ import torch
 
 from ._lib import P_double, check, lib
 
-STACK_TYPES = {"fp32": 0, "bf16x2": 1}
+STACK_TYPES = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
 FORMS = {"split": 0, "standard": 1}
 
 
