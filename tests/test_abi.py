@@ -165,7 +165,8 @@ def test_binding_constants_match_the_header_enums():
     for code, name in _lib.STATUS.items():
         assert enum[name] == code, name
     from paper_2602_20870_amd import ops
-    assert ops.STACK_TYPES == {"fp32": enum["FGFRFT_STACK_FP32"], "bf16x2": enum["FGFRFT_STACK_BF16X2"]}
+    assert ops.STACK_TYPES == {"fp32": enum["FGFRFT_STACK_FP32"], "bf16x2": enum["FGFRFT_STACK_BF16X2"],
+                               "fp16x2": enum["FGFRFT_STACK_FP16X2"]}
     assert ops.FORMS == {"split": enum["FGFRFT_FORM_SPLIT"], "standard": enum["FGFRFT_FORM_STANDARD"]}
     assert (enum["FGFRFT_IN_C128"], enum["FGFRFT_IN_F64"]) == (0, 1)   # the intype ops.Plan passes
 
