@@ -226,7 +226,7 @@ def cpu_baseline(F, alphas, L, X, budget_s=12.0, chunk=16, one_thread_orders=8):
     return out
 
 
-def grad_bench(reps=3):
+def grad_bench(reps=3, stacktype="fp32"):
     """Order and signal gradients (Proposition 4) on the sphere workload: kNN (k=10) graph on 2048
     points of the unit sphere, L = 48, 64 orders (one per channel), 64 real signals per order."""
     import torch
@@ -242,7 +242,7 @@ def grad_bench(reps=3):
     X = torch.from_numpy(rng.standard_normal((na, N, B)).astype(np.float32)).to(dev)
     GY = torch.from_numpy((rng.standard_normal((na, N, B)) + 1j * rng.standard_normal((na, N, B)))
                           .astype(np.complex64)).to(dev)
-    plan = Plan(torch.from_numpy(F).to(dev), L)
+    plan = Plan(torch.from_numpy(F).to(dev), L, stacktype=stacktype)
     plan.grad(alphas, X, GY, want_dX=True)       # warm-up (kernel attributes, workspace)
     torch.cuda.synchronize()
     out = {"workload": f"sphere2048: N={N}, L={L}, {na} orders, {B} real signals per order"}
@@ -302,9 +302,11 @@ def table4_bench(sizes=(1000, 2000, 3000, 4000, 5000, 6000, 7000, 8000), L=10, a
 
 
 def precision_form_bench(chunks=(32, 128), reps=3):
-    """Precision-form workload (grid8192: 128x64 grid, lognormal weights, N = 8192, L = 64): one
-    update launch per order chunk on the FP32 stack and on the BF16 hi/lo stack (both 4 bytes per
-    real value), and the apply of a 32-order chunk to one shared block of 1024 real signals."""
+    """Precision-form workload (grid8192: 128x64 grid, lognormal weights, N = 8192, L = 64, 1024 orders):
+    per stack storage form -- FP32, FP16X2 (its split operands stored), BF16 hi/lo pairs (all 4 bytes per
+    real value) and the plain complex64 stack of F handed over as complex (8 bytes) -- one update launch
+    per order chunk, the pass over all 1024 orders in launches of 128, the apply of a 32-order chunk to
+    one shared block of 1024 real signals (real stacks) and the direct route (32 orders x 2 signals)."""
     import torch
     import synth
     from paper_2602_20870_amd import Plan, apply_operator
@@ -315,37 +317,42 @@ def precision_form_bench(chunks=(32, 128), reps=3):
     F, L, N = cfg["F"], cfg["L"], cfg["N"]
     alphas = cfg["alphas"]
     log(f"grid8192 built in {time.time() - t0:.0f}s")
-    Ft = torch.from_numpy(F).to(dev)
     rng = synth.streams(0, 3)[2]
     X = torch.from_numpy(synth.real_signals((N, 1024), rng).astype(np.float32)).to(dev)
-    out = {"workload": "grid8192: 128x64 grid, lognormal(0, 0.5) weights, N=8192, L=64, orders in [-2, 2]",
+    out = {"workload": "grid8192: 128x64 grid, lognormal(0, 0.5) weights, N=8192, L=64, 1024 orders in [-2, 2]",
            "forms": []}
-    for st in ("fp32", "bf16x2"):
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for name in ("fp32", "fp16x2", "bf16x2", "complex64"):
+        cplx = name == "complex64"
+        st = "fp32" if cplx else name
+        Ft = torch.from_numpy(F.astype(np.complex128) if cplx else F).to(dev)
         t0 = time.perf_counter()
         plan = Plan(Ft, L, stacktype=st)
         torch.cuda.synchronize()
         plan_s = time.perf_counter() - t0
+        del Ft
+        es = 8 if cplx else 4
+        Q = torch.empty((max(chunks), N, N), dtype=torch.complex64, device=dev)
         for n in chunks:
-            Q = torch.empty((n, N, N), dtype=torch.complex64, device=dev)
             al = alphas[:n]
-            plan.update(al, out=Q)
+            plan.update(al, out=Q[:n])
             torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0, e1 = ev(), ev()
             e0.record()
             for _ in range(reps):
-                plan.update(al, out=Q)
+                plan.update(al, out=Q[:n])
             e1.record()
             e1.synchronize()
             ms = e0.elapsed_time(e1) / reps
-            alg = update_algorithmic_bytes(N, L, n)
-            row = {"stacktype": st, "orders": n, "update_ms": ms, "updates_per_s": n / (ms * 1e-3),
+            alg = n * 8.0 * N * N + (L + 2) * es * N * N
+            row = {"stack": name, "orders": n, "update_ms": ms, "updates_per_s": n / (ms * 1e-3),
                    "algorithmic_GB": alg / 1e9, "algorithmic_GBps": alg / (ms * 1e-3) / 1e9, "plan_s": plan_s}
-            if n == 32:
-                Y = apply_operator(Q, X)
+            if n == 32 and not cplx:
+                Y = apply_operator(Q[:32], X)
                 torch.cuda.synchronize()
                 e0.record()
                 for _ in range(reps):
-                    apply_operator(Q, X, out=Y)
+                    apply_operator(Q[:32], X, out=Y)
                 e1.record()
                 e1.synchronize()
                 ams = e0.elapsed_time(e1) / reps
@@ -354,15 +361,31 @@ def precision_form_bench(chunks=(32, 128), reps=3):
                 del Y
             log(f"precision form {row}")
             out["forms"].append(row)
-            del Q
-            torch.cuda.empty_cache()
-        # the direct route on the same plan: 32 orders x 2 signals (64 columns, no operator formed)
-        ms = direct_call_ms(plan, alphas[:32], 2, dev)
-        alg = direct_algorithmic_bytes(N, L, 64)
-        row = {"stacktype": st, "direct_orders": 32, "direct_columns": 64, "direct_ms": ms,
-               "direct_algorithmic_GBps": alg / (ms * 1e-3) / 1e9}
+        # all 1024 orders, launches of 128
+        CH = 128
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for c0 in range(0, alphas.size, CH):
+            plan.update(alphas[c0: c0 + CH], out=Q[:CH])
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        nl = alphas.size // CH
+        alg = alphas.size * 8.0 * N * N + nl * (L + 2) * es * N * N
+        row = {"stack": name, "orders": int(alphas.size), "launches": nl, "pass_ms": ms,
+               "updates_per_s": alphas.size / (ms * 1e-3), "algorithmic_GBps": alg / (ms * 1e-3) / 1e9}
         log(f"precision form {row}")
         out["forms"].append(row)
+        del Q
+        torch.cuda.empty_cache()
+        if not cplx:   # the direct route on the same plan: 32 orders x 2 signals (64 columns, no operator formed)
+            ms = direct_call_ms(plan, alphas[:32], 2, dev)
+            alg = direct_algorithmic_bytes(N, L, 64)
+            row = {"stack": name, "direct_orders": 32, "direct_columns": 64, "direct_ms": ms,
+                   "direct_algorithmic_GBps": alg / (ms * 1e-3) / 1e9}
+            log(f"precision form {row}")
+            out["forms"].append(row)
         del plan
         torch.cuda.empty_cache()
     return out
@@ -475,6 +498,7 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
     # split) and the final reduction, about 50 us together; an upper bound on k_direct's time
     n, B = 32, 2
     ms = direct_call_ms(plan, alphas[:n], B, dev)
+    ms_iso = direct_call_ms(plan, alphas[:n], B, dev, isolated=True)
     alg = direct_algorithmic_bytes(N, L, n * B)
     traffic = None
     if DIRECT_TRAFFIC["source_sha256"] == source_digest("direct.hip") and N == 4096 and L == 32:
@@ -482,13 +506,16 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
     res["roofline"] = {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
                        "kernel": "k_direct (timed call includes its set-up and reduction kernels)",
-                       "ms": ms, "ncols": n * B}
+                       "ms": ms, "isolated_call_ms": ms_iso, "ncols": n * B}
     log(f"direct call (64 columns): {ms:.3f} ms, {alg / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
     return res
 
 
-def direct_call_ms(plan, alphas, B, dev, reps=10):
-    """Median duration of one direct-route call (HIP events on the current stream)."""
+def direct_call_ms(plan, alphas, B, dev, reps=10, isolated=False):
+    """Duration of one direct-route call (HIP events on the current stream): `reps` calls queued back to
+    back between two events, so each call's kernels (column scales, coefficients, signal split, the
+    paired kernel, the reduction) run without the host's launch gaps; isolated=True gives the median
+    of single calls with a synchronisation after each instead."""
     import torch
     import synth
     N, n = plan.N, len(alphas)
@@ -499,20 +526,30 @@ def direct_call_ms(plan, alphas, B, dev, reps=10):
     Yd = torch.empty((N, n * B), dtype=torch.complex64, device=dev)
     ws = torch.empty(plan.direct_workspace_bytes(n * B, n * B), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    for _ in range(2):
+        plan.apply_direct(al, cols, Xd, out=Yd, ws=ws)
+    torch.cuda.synchronize()
+    if not isolated:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.apply_direct(al, cols, Xd, out=Yd, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
     times = []
-    for i in range(reps + 2):
+    for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         plan.apply_direct(al, cols, Xd, out=Yd, ws=ws)
         e1.record(stream)
         torch.cuda.synchronize()
-        if i >= 2:
-            times.append(e0.elapsed_time(e1))
+        times.append(e0.elapsed_time(e1))
     return float(np.median(times))
 
 
 def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_sets=1, per_request=True,
-                  warm_trace=4000, keep_every=16, route="auto"):
+                  warm_trace=4000, keep_every=16, route="auto", stacktype="fp32"):
     """p50/p99 latency of the continuous-batching server vs one launch per request.
 
     8 resident plans from kNN graphs (k=10, Gaussian weights) on 3-D GMM points with
@@ -531,7 +568,8 @@ def serving_bench(n_requests=20000, warmup=2000, rate=5000.0, L=32, K=32, slot_s
           for g, N in enumerate(SERVE_NS)}
     rng = np.random.default_rng(7)
     sig = {g: rng.standard_normal((F.shape[0], 64)).astype(np.float32) for g, F in Fs.items()}
-    srv = serve.Server(hbm_budget=120 << 30, K=K, bmax=64, slot_sets=slot_sets, use_graphs=True, route=route)
+    srv = serve.Server(hbm_budget=120 << 30, K=K, bmax=64, slot_sets=slot_sets, use_graphs=True, route=route,
+                       stacktype=stacktype)
     for g, F in Fs.items():
         srv.add_plan(g, F, L)
     torch.cuda.synchronize()
@@ -581,7 +619,9 @@ def main():
     ap.add_argument("--n-alpha", type=int, default=256)
     ap.add_argument("--signals", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stacktype", default="fp32", choices=["fp32", "fp16x2", "bf16x2"])
+    ap.add_argument("--stacktype", default="fp16x2", choices=["fp32", "fp16x2", "bf16x2"],
+                    help="stack storage of the plans (fp16x2: the FP32 stack's split operands, bitwise the "
+                         "FP32 results)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving p50/p99 measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient timing")
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-route comparison")
@@ -720,13 +760,14 @@ def main():
         leg("throughput_configs", throughput_configs)
     if not args.no_grad:
         log("gradients ...")
-        leg("grad", grad_bench)
+        # the gradient takes FP32-class stacks (FP32 or FP16X2)
+        leg("grad", lambda: grad_bench(stacktype="fp32" if args.stacktype == "bf16x2" else args.stacktype))
         log(f"grad {out['grad']}")
     del plan
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving trace ...")
-        leg("serve", serving_bench)
+        leg("serve", lambda: serving_bench(stacktype=args.stacktype))
         if "batched" in out["serve"]:
             b, p = out["serve"]["batched"], out["serve"].get("one_launch_per_request")
             log(f"serve batched p50 {b['p50_ms']:.2f} ms p99 {b['p99_ms']:.2f} ms"

@@ -94,7 +94,7 @@ typedef struct fgfrft_plan_s* fgfrft_plan_t;
  * the plan's lifetime (power stack, projector and, for real F, an N x 32
  * float32 slot for the -1 eigenspace basis); `scratch` is FP64
  * working memory used only during fgfrft_plan and free again when it returns.
- * Limits: 1 <= N <= 32768, 1 <= L <= 64 (L <= 32 for complex F). */
+ * Limits: 1 <= N <= 32768, 1 <= L <= 64. */
 FGFRFT_API fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype,
                                            size_t* persistent, size_t* scratch);
 

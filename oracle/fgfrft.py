@@ -34,7 +34,7 @@ __all__ = [
     "grad", "truncation_residual", "pointwise_bound", "frobenius_error_exact",
     "frobenius_bound_tight", "frobenius_bound_simplified",
     "worst_case_nmse_bound", "parseval_tail", "parseval_nmse_prediction",
-    "error_metrics", "block_errors", "sampled_rows", "Plan",
+    "error_metrics", "block_errors", "sampled_rows", "sampled_term_rows", "Plan",
 ]
 
 TAU_SNAP = 1e-6
@@ -187,20 +187,21 @@ def fgfrft_combine_many(P: np.ndarray, T: np.ndarray, alphas) -> np.ndarray:
     The real coefficients [c_0, c_1..c_L, c_{-1}..c_{-L}] of every order form the rows of C,
     and C T (one matrix product over the terms of :func:`term_matrix`) is the sum
     c_0 P_c + sum_n (c_n M_n + c_{-n} M_n^H) for all orders at once; e^{j pi alpha} P is added
-    per order.  Returns complex128 [n_alpha, N, N].
+    per order.  Returns complex128 [n_alpha, N, N].  With the row-sampled terms of
+    :func:`sampled_term_rows` and P[R, :] in place of P it returns the rows R instead,
+    [n_alpha, |R|, N].
     """
     alphas = np.atleast_1d(np.asarray(alphas, dtype=np.float64))
     K = T.shape[0]
     L = (K - 1) // 2
-    N = P.shape[0]
     C = np.empty((alphas.size, K))
     for a, al in enumerate(alphas):
         c = coefficients(al, L)                 # c[L + n] = c_n
         C[a, 0] = c[L]
         C[a, 1:L + 1] = c[L + 1:]
         C[a, L + 1:] = c[L - 1::-1]
-    S = (C @ T).reshape(alphas.size, N, N)
-    Q = np.empty((alphas.size, N, N), dtype=np.complex128)
+    S = (C @ T).reshape((alphas.size,) + P.shape)
+    Q = np.empty((alphas.size,) + P.shape, dtype=np.complex128)
     for a, al in enumerate(alphas):
         Q[a] = S[a] + np.exp(1j * np.pi * al) * P
     return Q
@@ -404,6 +405,26 @@ def sampled_rows(F: np.ndarray, P: np.ndarray, alphas, L: int, rows) -> np.ndarr
             acc = acc + c[L + n] * rr[n] + c[L - n] * cc[n].conj().T
         out[a] = acc
     return out
+
+
+def sampled_term_rows(F: np.ndarray, P: np.ndarray, L: int, rows) -> np.ndarray:
+    """Rows R of the 2L+1 terms of :func:`term_matrix`, [P_c, M_1..M_L, M_1^H..M_L^H][R, :],
+    flattened per term -> [(2L+1), |R| N], by the row and column recurrences of
+    :func:`sampled_rows` ((M_n)[R, :] = P_c[R, :] F^n, (M_n^H)[R, :] = (F^n P_c[:, R])^H), so that
+    ``fgfrft_combine_many(P[rows, :], T, alphas)`` gives the rows R of Q for many orders at once."""
+    rows = np.asarray(rows)
+    N = F.shape[0]
+    Pc = np.eye(N) - P
+    r = Pc[rows, :].astype(np.result_type(F, Pc))
+    c = Pc[:, rows].astype(np.result_type(F, Pc))
+    T = np.empty((2 * L + 1, rows.size * N), dtype=r.dtype)
+    T[0] = r.reshape(-1)
+    for n in range(1, L + 1):
+        r = r @ F
+        c = F @ c
+        T[n] = r.reshape(-1)
+        T[L + n] = c.conj().T.reshape(-1)
+    return T
 
 
 class Plan:

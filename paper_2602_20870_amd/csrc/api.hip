@@ -82,7 +82,6 @@ extern "C" {
 fgfrft_status fgfrft_plan_bytes(int N, int L, int intype, int stacktype, size_t* persistent, size_t* scratch) {
   if (!valid_sizes(N, L, intype, stacktype)) return FGFRFT_EINVAL;
   const bool cplx = intype == FGFRFT_IN_C128;
-  if (cplx && L > 32) { set_error("complex F supports L <= 32"); return FGFRFT_EUNSUPPORTED; }
   const size_t NN = (size_t)N * N;
   if (persistent)
     *persistent = align_up((size_t)2 * L * NN * stack_elem_bytes(cplx), 256) + align_up(NN * (cplx ? 8 : 4), 256) +

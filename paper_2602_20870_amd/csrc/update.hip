@@ -623,6 +623,9 @@ static fgfrft_status dispatch(const Plan* p, const uint16_t* table, const float4
     switch (KP) {
       case 32: return launch_update_strip<true, 32, 4, 64, SM, 256, 2, 256, true>(p, table, epi, n_alpha, np, Q, s);
       case 64: return launch_update_strip<true, 64, 2, 64, SM, 256, 2, 256, false>(p, table, epi, n_alpha, np, Q, s);
+      // 32 < L <= 64: one-row strips (two of the four waves run the order loop)
+      case 96: return launch_update_strip<true, 96, 1, 64, SM, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
+      case 128: return launch_update_strip<true, 128, 1, 64, SM, 256, 2, 128, false>(p, table, epi, n_alpha, np, Q, s);
     }
   }
   set_error("unsupported L=%d for %s F", p->L, p->cplx ? "complex" : "real");

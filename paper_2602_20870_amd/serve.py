@@ -276,12 +276,17 @@ class Server:
     route: "auto" (per batch, prefer_direct), "operator" or "direct" (when the batch's
     signals fit DIRECT_BLOCKS x 64 columns, else the operator route).  The direct route is
     offered for plans of real F with N % 32 == 0 (the matrix-core direct kernel).
+    stacktype: storage of the plans' stacks, "fp16x2" (default: the FP32 stack's split operands,
+    the same results bit for bit with no split work in the direct kernel) or "fp32".
     """
 
     def __init__(self, hbm_budget: int, K: int = 16, bmax: int = 64, slot_sets: int = 2, use_graphs: bool = True,
-                 device: str = "cuda:0", route: str = "auto"):
+                 device: str = "cuda:0", route: str = "auto", stacktype: str = "fp16x2"):
         if route not in ROUTES:
             raise ValueError(f"route must be one of {ROUTES}")
+        if stacktype not in ("fp32", "fp16x2"):
+            raise ValueError("stacktype must be fp32 or fp16x2 (the same results bit for bit)")
+        self.stacktype = stacktype
         self.budget, self.used = int(hbm_budget), 0
         self.K, self.bmax, self.S, self.route = K, bmax, slot_sets, route
         self.use_graphs = use_graphs
@@ -325,7 +330,7 @@ class Server:
         if not self.streams:
             self.streams = _distinct_queue_streams(self.n_queues, self.device)
         F = np.ascontiguousarray(F, dtype=np.complex128 if cplx else np.float64)
-        plan = Plan(torch.from_numpy(F).to(self.device), L)
+        plan = Plan(torch.from_numpy(F).to(self.device), L, stacktype=self.stacktype)
         need = plan.persistent.numel() + self.S * _SlotSet.device_bytes(plan, self.K, self.bmax, self.route)
         if need > left:
             del plan

@@ -241,6 +241,25 @@ def _combine_many_coefficients_unreversed(P, T, alphas):
     return np.stack([S[a] + np.exp(1j * np.pi * al) * P for a, al in enumerate(alphas)])
 
 
+def _sampled_term_rows(variant):
+    def f(F, P, L, rows):
+        rows = np.asarray(rows)
+        N = F.shape[0]
+        Pc = np.eye(N) - P
+        r = Pc[rows, :].astype(np.result_type(F, Pc))
+        c = Pc[:, rows].astype(np.result_type(F, Pc))
+        step = F.conj().T if variant == "inverse_rows" else F
+        T = np.empty((2 * L + 1, rows.size * N), dtype=r.dtype)
+        T[0] = r.reshape(-1)
+        for n in range(1, L + 1):
+            r = r @ step                                # slip (inverse_rows): rows of F^{-n} P_c
+            c = F @ c
+            T[n] = r.reshape(-1)
+            T[L + n] = (c.T if variant == "no_conj" else c.conj().T).reshape(-1)   # slip (no_conj)
+        return T
+    return f
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -272,6 +291,8 @@ MUTATIONS = {
     "term_matrix_no_adjoint": ("term_matrix", _term_matrix("no_adjoint")),
     "term_matrix_transpose_only": ("term_matrix", _term_matrix("transpose_only")),
     "combine_many_coefficients_unreversed": ("fgfrft_combine_many", _combine_many_coefficients_unreversed),
+    "sampled_term_rows_no_conj": ("sampled_term_rows", _sampled_term_rows("no_conj")),
+    "sampled_term_rows_inverse_rows": ("sampled_term_rows", _sampled_term_rows("inverse_rows")),
 }
 
 _ORIG: dict = {}

@@ -51,7 +51,9 @@ def test_plan_bytes_validation(L):
     assert L.fgfrft_plan_bytes(0, 10, 1, 0, ctypes.byref(p), ctypes.byref(s)) == -1
     assert L.fgfrft_plan_bytes(64, 0, 1, 0, ctypes.byref(p), ctypes.byref(s)) == -1
     assert L.fgfrft_plan_bytes(64, 65, 1, 0, ctypes.byref(p), ctypes.byref(s)) == -1
-    assert L.fgfrft_plan_bytes(64, 33, 0, 0, ctypes.byref(p), ctypes.byref(s)) == -7  # complex F, L > 32
+    assert L.fgfrft_plan_bytes(64, 64, 0, 0, ctypes.byref(p), ctypes.byref(s)) == 0   # complex F up to L = 64
+    assert L.fgfrft_plan_bytes(64, 65, 0, 0, ctypes.byref(p), ctypes.byref(s)) == -1
+    assert L.fgfrft_plan_bytes(64, 10, 1, 3, ctypes.byref(p), ctypes.byref(s)) == -1   # no stack type 3
     assert L.fgfrft_plan_bytes(64, 10, 5, 0, ctypes.byref(p), ctypes.byref(s)) == -1
     assert L.fgfrft_plan_bytes(64, 10, 1, 0, ctypes.byref(p), ctypes.byref(s)) == 0
     N, Lt = 64, 10

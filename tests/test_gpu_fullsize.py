@@ -4,13 +4,15 @@ on sampled outputs the FP64 oracle computes row by row.
 * knn4096: N = 4096, L = 32, one update launch of 256 orders (34 GB of Q), then one apply
   launch to 64 real signals per order, as in the benchmark step; then the same orders and
   signals through the real-F route of the apply call (R = Re Q written, rank-r imaginary part).
-* grid8192 (precision form): N = 8192, L = 64, one update launch of a 32-order chunk for the
-  FP32 stack and for the BF16 hi/lo stack, the direct route on both (32 orders x 2 signals),
-  and the apply of the FP32 operators to one shared block of 1024 real signals; per-order errors against the oracle are printed (and written as
-  JSON to $FGFRFT_REPORT_DIR when that is set).
+* grid8192 (precision form): N = 8192, L = 64, all 1024 orders in update launches of 128, for four
+  stack storage forms: FP32, FP16X2 (bitwise the FP32 results), BF16 hi/lo pairs and the plain
+  complex64 stack of F handed over as complex; the direct route on FP32 and BF16X2 (32 orders x 2
+  signals), and the apply of 32 FP32 operators to one shared block of 1024 real signals.  Per-order
+  errors against the oracle are printed (and written as JSON to $FGFRFT_REPORT_DIR when set).
 
 The oracle's rows come from the row/column power recurrences of the stack (no N x N FP64
-stack is formed) and its projector from the symmetric-part route for real orthogonal F.
+stack is formed; the row-sampled terms once, then one product per launch of orders) and its
+projector from the symmetric-part route for real orthogonal F.
 """
 import json
 import os
@@ -112,7 +114,7 @@ def test_knn4096_bench_launch_sampled_rows():
     assert max(errs_yf) <= TOL_FP32, errs_yf
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1500)
 def test_grid8192_precision_forms_sampled_rows():
     torch = torch_cuda()
     from paper_2602_20870_amd import Plan, apply_operator
@@ -120,51 +122,65 @@ def test_grid8192_precision_forms_sampled_rows():
     announce("grid8192: building F (128x64 grid, lognormal weights, N=8192)")
     cfg = synth.make_config("grid8192", seed=0, with_signals=False)
     F, L, N = cfg["F"], cfg["L"], cfg["N"]
-    chunk = cfg["alphas"][:32].copy()                      # one 32-order launch of the 1024
-    chunk[:4] = [0.0, 1.0, -1.0, 0.5]
+    alphas = cfg["alphas"].copy()                          # all 1024 orders, in launches of CH
+    assert alphas.size == 1024
+    alphas[:4] = [0.0, 1.0, -1.0, 0.5]
+    CH = 128
     rows = _rows(N, 2)
-    Ft = torch.from_numpy(F).cuda()
+    announce(f"grid8192: oracle projector and row-sampled terms [{time.time() - t0:.0f}s]")
+    P, _, r, nxt = O.projectors_symmetric_route(F)
+    T = O.sampled_term_rows(F, P, L, rows)                 # [(2L+1), 64 N], from the row / column recurrences
+    Prow = P[rows, :]
     Xs = synth.real_signals((N, 1024), synth.streams(0, 3)[2]).astype(np.float32)   # one shared block
-    got = {}
-    for st in ("fp32", "bf16x2"):
-        announce(f"grid8192: GPU plan ({st}) + one 32-order update launch [{time.time() - t0:.0f}s]")
+    X64 = Xs.astype(np.float64)
+    report = dict(alphas=alphas.tolist(), rows=rows.tolist(), r_minus1=r, next_cos=nxt)
+    # storage forms: FP32 stack, FP16X2 (the FP32 stack's split operands, bitwise the same results),
+    # BF16 hi/lo pairs, and the plain complex64 stack (F handed over as complex128)
+    forms = (("fp32", False, TOL_FP32), ("fp16x2", False, TOL_FP32), ("bf16x2", False, TOL_BF16X2),
+             ("complex64", True, TOL_FP32))
+    fp32_rows = []
+    for name, cplx, tol in forms:
+        st = "fp32" if name == "complex64" else name
+        announce(f"grid8192: GPU plan ({name}) [{time.time() - t0:.0f}s]")
+        Ft = torch.from_numpy(F.astype(np.complex128) if cplx else F).cuda()
         plan = Plan(Ft, L, stacktype=st)
-        Q = plan.update(chunk)
-        torch.cuda.synchronize()
-        got[st] = (_sample_rows(torch, Q, range(32), rows), plan.r_minus1)
-        # the direct route on the same plan: the 32 orders with two of the shared signals each
-        Yd = plan.apply_direct(chunk, np.repeat(np.arange(32, dtype=np.int32), 2),
-                               torch.from_numpy(np.ascontiguousarray(Xs[:, :64])).cuda())
-        got[st + "_direct"] = Yd[torch.as_tensor(rows, device="cuda")].cpu().numpy()
-        del Yd
-        if st == "fp32":   # the apply of the 32 operators to 1024 shared signals (pre-split signals)
-            Y = apply_operator(Q, torch.from_numpy(Xs).cuda())
-            Yrows = _sample_rows(torch, Y, range(32), rows)
-            del Y
+        del Ft
+        assert plan.r_minus1 == r
+        Q = torch.empty((CH, N, N), dtype=torch.complex64, device="cuda")
+        errs = []
+        for c0 in range(0, 1024, CH):
+            al = alphas[c0: c0 + CH]
+            plan.update(al, out=Q)
+            torch.cuda.synchronize()
+            Qr = _sample_rows(torch, Q, range(CH), rows)
+            if name == "fp32":
+                fp32_rows.append(Qr)
+            elif name == "fp16x2":
+                assert np.array_equal(Qr.view(np.uint32), fp32_rows[c0 // CH].view(np.uint32)), c0
+            ref = O.fgfrft_combine_many(Prow, T, al)
+            errs += [rel_fro(Qr[i], ref[i]) for i in range(CH)]
+            if c0 == 0 and name in ("fp32", "bf16x2"):
+                # the direct route on the same plan: the first 32 orders with two of the shared signals each
+                Yd = plan.apply_direct(al[:32], np.repeat(np.arange(32, dtype=np.int32), 2),
+                                       torch.from_numpy(np.ascontiguousarray(Xs[:, :64])).cuda())
+                Ydr = Yd[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+                errs_d = [rel_fro(Ydr[:, 2 * i: 2 * i + 2], ref[i] @ X64[:, 2 * i: 2 * i + 2]) for i in range(32)]
+                report[name + "_direct"] = errs_d
+                announce(f"grid8192 {name} direct route: worst row error {max(errs_d):.2e}")
+                assert max(errs_d) <= tol, (name, errs_d)
+                del Yd
+                if name == "fp32":   # the apply of the first 32 operators to the 1024 shared signals
+                    Y = apply_operator(Q[:32], torch.from_numpy(Xs).cuda())
+                    Yrows = _sample_rows(torch, Y, range(32), rows)
+                    del Y
+                    errs_y = [rel_fro(Yrows[i], ref[i] @ X64) for i in range(32)]
+                    report["apply_1024_shared_fp32"] = errs_y
+                    announce(f"grid8192 apply to 1024 shared signals: worst row error {max(errs_y):.2e}")
+                    assert max(errs_y) <= TOL_FP32, errs_y
+        report[name] = errs
+        announce(f"grid8192 {name}: 1024 orders, worst row error {max(errs):.2e}, median {np.median(errs):.2e}, "
+                 f"99th percentile {np.percentile(errs, 99):.2e} [{time.time() - t0:.0f}s]")
+        assert max(errs) <= tol, (name, max(errs))
         del Q, plan
         torch.cuda.empty_cache()
-    del Ft
-
-    announce(f"grid8192: oracle projector and sampled rows [{time.time() - t0:.0f}s]")
-    P, _, r, nxt = O.projectors_symmetric_route(F)
-    ref = O.sampled_rows(F, P, chunk, L, rows)
-    report = dict(alphas=chunk.tolist(), rows=rows.tolist(), r_minus1=r, next_cos=nxt)
-    for st, tol in (("fp32", TOL_FP32), ("bf16x2", TOL_BF16X2)):
-        Qr, r_gpu = got[st]
-        assert r_gpu == r
-        errs = [rel_fro(Qr[i], ref[i]) for i in range(32)]
-        report[st] = errs
-        announce(f"grid8192 {st}: worst row error {max(errs):.2e}, median {np.median(errs):.2e}")
-        assert max(errs) <= tol, (st, errs)
-    X64 = Xs.astype(np.float64)
-    for st, tol in (("fp32", TOL_FP32), ("bf16x2", TOL_BF16X2)):
-        Yd = got[st + "_direct"]
-        errs_d = [rel_fro(Yd[:, 2 * i: 2 * i + 2], ref[i] @ X64[:, 2 * i: 2 * i + 2]) for i in range(32)]
-        report[st + "_direct"] = errs_d
-        announce(f"grid8192 {st} direct route: worst row error {max(errs_d):.2e}")
-        assert max(errs_d) <= tol, (st, errs_d)
-    errs_y = [rel_fro(Yrows[i], ref[i] @ X64) for i in range(32)]
-    report["apply_1024_shared_fp32"] = errs_y
-    announce(f"grid8192 apply to 1024 shared signals: worst row error {max(errs_y):.2e}")
-    assert max(errs_y) <= TOL_FP32, errs_y
     _report("grid8192_precision.json", report)

@@ -345,3 +345,33 @@ def test_grad_paths(N, L, n, cplxF):
     for a in range(n):   # each order against its own magnitude
         assert abs(dal[a] - dal_ref[a]) <= TOL_FP32 * max(abs(dal_ref[a]), 1e-3 * np.max(np.abs(GY[a]))), a
     assert rel_fro(dX.cpu().numpy(), dX_ref) <= TOL_FP32
+
+
+@pytest.mark.parametrize("L,stacktype", [(40, "fp32"), (64, "fp32"), (64, "fp16x2"), (48, "bf16x2")])
+def test_update_complex_F_beyond_L32(L, stacktype):
+    """Complex F with 32 < L <= 64 (one-row strips of the update kernel, 96 or 128 terms per k extent):
+    a Haar unitary with one eigenvalue moved to -1, against the oracle; the gradient and the direct route
+    (plain kernel for complex F) on the same plan."""
+    torch = torch_cuda()
+    announce(f"complex F N=96 L={L} stack {stacktype}")
+    rng = np.random.default_rng(L)
+    V = synth.haar_unitary(96, rng)
+    th = rng.uniform(-np.pi * 0.9, np.pi * 0.9, 96)
+    th[7] = np.pi
+    F = (V * np.exp(1j * th)[None, :]) @ V.conj().T
+    tol = TOL_BF16X2 if stacktype == "bf16x2" else TOL_FP32
+    alphas = np.concatenate([[0.0, 1.0, -1.0], rng.uniform(-2, 2, 40)])
+    worst, plan, ref, Q = _check_update(torch, F, L, alphas, tol=tol, stacktype=stacktype, r_expect=1)
+    X = synth.complex_signals((96, 5), rng).astype(np.complex64)
+    Y = plan.apply_direct(alphas[:5], np.arange(5, dtype=np.int32), torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(5):
+        assert rel_fro(Y[:, c], ref.combine(float(alphas[c])) @ X[:, c].astype(np.complex128)) <= tol
+    if stacktype != "bf16x2":
+        Xg = synth.complex_signals((4, 96, 8), rng)
+        GY = synth.complex_signals((4, 96, 8), rng)
+        da, dX = plan.grad(alphas[3:7], torch.from_numpy(Xg.astype(np.complex64)).cuda(),
+                           torch.from_numpy(GY.astype(np.complex64)).cuda())
+        dref, dxref = O.grad(ref.P, ref.M, alphas[3:7], Xg.astype(np.complex64).astype(np.complex128),
+                             GY.astype(np.complex64).astype(np.complex128))
+        assert np.max(np.abs(da - dref)) <= TOL_FP32 * np.max(np.abs(dref))
+        assert rel_fro(dX.cpu().numpy(), dxref) <= TOL_FP32

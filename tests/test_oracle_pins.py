@@ -504,6 +504,42 @@ def test_batched_combination_dft_closed_form():
         assert _rel(Qs[a], closed) < 1e-12, alpha
 
 
+def test_batched_sampled_rows_dft_closed_form():
+    """Rows R of Q for many orders from the row-sampled terms (one product C T_R plus e^{j pi alpha} P[R, :])
+    equal the rows of the DFT's closed form sum_m q_m P_m (complex F, 16 eigenvalues at -1)."""
+    N, L = 64, 10
+    F = synth.dft_matrix(N)
+    Ps, thetas = _dft_projectors(F)
+    plan = O.Plan(F, L)
+    rows = np.array([0, 5, 63, 31])
+    alphas = [0.55, -1.3, 1.99, 0.0]
+    Qr = O.fgfrft_combine_many(plan.P[rows, :], O.sampled_term_rows(F, plan.P, L, rows), alphas)
+    assert Qr.shape == (len(alphas), rows.size, N)
+    for a, alpha in enumerate(alphas):
+        qs = []
+        for t in thetas:
+            if t == np.pi:
+                qs.append(np.exp(1j * np.pi * alpha))
+            else:
+                qs.append(sum(_quad_coeff(alpha, n).real * np.exp(1j * n * t) for n in range(-L, L + 1)))
+        closed = sum(q * P for q, P in zip(qs, Ps))
+        assert _rel(Qr[a], closed[rows]) < 1e-12, alpha
+
+
+def test_batched_sampled_rows_integer_orders_are_power_rows():
+    """Real orthogonal F with two eigenvalues at -1: integer orders give the rows of F^m, negative
+    ones the rows of (F^|m|)^T."""
+    F = _real_orthogonal_with_minus1(30, 2, 23)
+    plan = O.Plan(F, 5)
+    rows = np.array([29, 0, 11])
+    ms = [-4, -1, 0, 3]
+    Qr = O.fgfrft_combine_many(plan.P[rows, :], O.sampled_term_rows(F, plan.P, 5, rows), [float(m) for m in ms])
+    for a, m in enumerate(ms):
+        ref = np.linalg.matrix_power(F, abs(m))
+        ref = ref if m >= 0 else ref.T
+        assert np.max(np.abs(Qr[a] - ref[rows])) < 1e-13, m
+
+
 def test_batched_combination_integer_orders_are_powers():
     """Real orthogonal F with three eigenvalues at -1: integer orders give F^m, negative ones (F^|m|)^T."""
     F = _real_orthogonal_with_minus1(14, 3, 21)

@@ -37,8 +37,8 @@ def test_footprint_of_a_complex_plan_and_bad_requests(built):
     # complex stack (8 bytes per entry) and no direct-route blocks for complex F
     assert pb.value >= 2 * L * N * N * 8 + N * N * 8
     assert srv.footprint(N, L, complex_F=True) == pb.value + 2 * (4 * N * N * 8 + 4 * N * 8 * 12)
-    with pytest.raises(ValueError):        # complex F takes L <= 32
-        srv.footprint(N, 40, complex_F=True)
+    with pytest.raises(ValueError):        # L <= 64
+        srv.footprint(N, 65, complex_F=True)
     srv.plans[0] = SimpleNamespace(N=8, L=4)
     with pytest.raises(TypeError):
         srv.submit(0, 0.5, np.zeros((8, 2), np.complex64))
