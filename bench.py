@@ -440,10 +440,11 @@ def direct_algorithmic_bytes(N, L, ncols):
     return (L + 1) * 4.0 * N * N + 12.0 * N * ncols
 
 
-def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16))):
-    """Direct route (no operator formed) vs update + apply for small signal batches of one plan.
+def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16), (32, 64))):
+    """Direct route (no operator formed) vs update + apply vs the apply call (fgfrft_apply: the real-F
+    route when the signal count is a multiple of 64) for signal batches of one plan.
 
-    Each case is (orders, signals per order); both routes produce the same Y (complex64 [N, B] per
+    Each case is (orders, signals per order); every route produces the same Y (complex64 [N, B] per
     order).  Times are per call, HIP events on the current stream, inputs resident."""
     import torch
     import synth
@@ -462,6 +463,11 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
         Yd = torch.empty((N, n * B), dtype=torch.complex64, device=dev)
         ws = torch.empty(max(256, plan.direct_workspace_bytes(n * B, n * B)), dtype=torch.uint8, device=dev)
         Q = torch.empty((n, N, N), dtype=torch.complex64, device=dev)
+        Ya = torch.empty((n, N, B), dtype=torch.complex64, device=dev)
+        wsa = torch.empty(plan.apply_workspace_bytes(n, B, chunk=n), dtype=torch.uint8, device=dev)
+
+        def apply_call():
+            plan.apply(al, X, chunk=n, out=Ya, ws=wsa)
 
         def direct():
             plan.apply_direct(al_dev, cols, Xd, out=Yd, ws=ws)
@@ -471,7 +477,7 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
             return apply_operator(Q, X)
 
         res = {}
-        for name, fn in (("direct", direct), ("update_apply", two_step)):
+        for name, fn in (("direct", direct), ("update_apply", two_step), ("apply_call", apply_call)):
             for _ in range(2):
                 fn()
             torch.cuda.synchronize()
@@ -487,11 +493,13 @@ def direct_bench(plan, alphas, dev, reps=10, sizes=((32, 2), (64, 1), (16, 16)))
         alg = direct_algorithmic_bytes(N, L, n * B)
         out.append({"orders": n, "signals_per_order": B, "ncols": n * B, "direct_ms": res["direct"],
                     "update_apply_ms": res["update_apply"], "speedup": res["update_apply"] / res["direct"],
+                    "apply_call_ms": res["apply_call"], "apply_call_real_F_route": B % 64 == 0,
                     "direct_algorithmic_GB": alg / 1e9,
                     "direct_GBps": alg / (res["direct"] * 1e-3) / 1e9, "rel_diff_between_routes": diff})
-        log(f"direct n={n} B={B}: {res['direct']:.3f} ms vs update+apply {res['update_apply']:.3f} ms "
+        log(f"direct n={n} B={B}: {res['direct']:.3f} ms vs update+apply {res['update_apply']:.3f} ms, apply call "
+            f"{res['apply_call']:.3f} ms "
             f"({alg / (res['direct'] * 1e-3) / 1e9:.0f} GB/s algorithmic, rel diff {diff:.1e})")
-        del X, Xd, Yd, ws, Q, Y2
+        del X, Xd, Yd, ws, Q, Y2, Ya, wsa
         torch.cuda.empty_cache()
     res = {"workload": f"knn4096 plan (N={N}, L={L}), real signals, orders from the main workload", "cases": out}
     # roofline of the direct route on the 64-column case: HIP events on this stream around the
