@@ -31,6 +31,17 @@ __device__ __forceinline__ floatx16 mfma_f32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// fp16 hi / lo split of an FP32 value (already scaled into the fp16 range) and the split-fp16 product
+__device__ __forceinline__ void split16h(float v, short& hi, short& lo) {
+  const _Float16 h = (_Float16)v;
+  const _Float16 l = (_Float16)(v - (float)h);
+  hi = __builtin_bit_cast(short, h);
+  lo = __builtin_bit_cast(short, l);
+}
+__device__ __forceinline__ floatx16 mma16(shortx8 a, shortx8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0, 0, 0);
+}
+
 // Split layout of G for the matrix-core inner products (PRE): per order, positions in blocks of 8
 // consecutive ones, 64 bytes per block: fp16 parts [Re hi x 8][Re lo x 8][Im hi x 8][Im lo x 8] of
 // G * s_a (s_a the order's power-of-two scale), the same 8 bytes per position as complex64.
@@ -197,8 +208,23 @@ __global__ __launch_bounds__(256) void k_rownorm2_max(const void* __restrict__ V
 // Order scale from an a-priori bound: |G_a[i][j]| <= ||GY_a[i,:]|| ||X_a[j,:]|| (Cauchy-Schwarz), so
 // with m = max_i ||GY_a[i,:]|| max_j ||X_a[j,:]|| (1 + 2^-10 for the rounding of the norms) the scale
 // 2^e puts m 2^e in [2^13, 2^14): every scaled entry of G is below 2^14, its fp16 parts stay finite.
+// Also the operand scales of the split-fp16 outer product: s_gy, s_x with (largest row norm) s in
+// [2^13, 2^14) (every entry is at most its row's norm), and s_a / (s_gy s_x), all powers of two.
+__device__ __forceinline__ int pow2_exp_for(float m) {
+  int e = 0;
+  if (m > 0.f && isfinite(m)) {
+    int E;
+    frexpf(m, &E);
+    e = 14 - E;
+    if (e > 100) e = 100;
+    if (e < -100) e = -100;
+  }
+  return e;
+}
+
 __global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ gy2, const float* __restrict__ x2,
-                                                      int nch, int x_shared, float2* __restrict__ gsc) {
+                                                      int nch, int x_shared, float2* __restrict__ gsc,
+                                                      float4* __restrict__ osc) {
   __shared__ float r1[256], r2[256];
   const int a = blockIdx.x;
   float m1 = 0.f, m2 = 0.f;
@@ -217,16 +243,105 @@ __global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const float m = sqrtf(r1[0]) * sqrtf(r2[0]) * (1.f + 1.f / 1024.f);
-    int e = 0;
-    if (m > 0.f && isfinite(m)) {
-      int E;
-      frexpf(m, &E);
-      e = 14 - E;
-      if (e > 100) e = 100;
-      if (e < -100) e = -100;
-    }
+    const float n1 = sqrtf(r1[0]) * (1.f + 1.f / 1024.f), n2 = sqrtf(r2[0]) * (1.f + 1.f / 1024.f);
+    const int e = pow2_exp_for(n1 * n2), e1 = pow2_exp_for(n1), e2 = pow2_exp_for(n2);
     gsc[a] = make_float2(ldexpf(1.f, e), ldexpf(1.f, -e));
+    osc[a] = make_float4(ldexpf(1.f, e1), ldexpf(1.f, e2), ldexpf(1.f, e - e1 - e2), 0.f);
+  }
+}
+
+// ---------------------------------------------------------------- G = GY X^H, split-fp16 products
+// The same 64 x 64 output tile per workgroup (one 32 x 32 block per wave) as k_outer, on
+// v_mfma_f32_32x32x16_f16 with operands split into fp16 hi/lo after the power-of-two scales osc[a]:
+// each lane loads its fragments straight from global memory (8 consecutive signals of one row of GY
+// and of X: 64 and 32 contiguous bytes), so nothing is staged in LDS before the products; per 16
+// signals 6 products (real X) or 12 (complex X) instead of 16 or 32 FP32 ones.  Output: G s_a in the
+// split layout (k_outer<..., PRE = true>).  B % 16 == 0; rows past N read row N - 1 and are not stored.
+template <bool XC>
+__global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ GY, const void* __restrict__ X,
+                                                     int x_shared, int N, int B, cplx64* __restrict__ G,
+                                                     const float4* __restrict__ osc) {
+  __shared__ __align__(16) uint16_t st[64 * 256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int a = blockIdx.z;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const float4 sc = osc[a];
+  const int gi = min(i0 + wi + l32, N - 1), gj = min(j0 + wj + l32, N - 1);
+  const cplx64* gyr = GY + ((size_t)a * N + gi) * B;
+  const size_t xrow = ((size_t)(x_shared ? 0 : a) * N + gj) * B;
+  floatx16 accr = {}, acci = {};
+#pragma unroll 4
+  for (int b0 = 0; b0 < B; b0 += 16) {
+    const int b = b0 + 8 * lh;
+    shortx8 arh, arl, aih, ail, xrh, xrl, xih = {}, xil = {};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = *(const float4*)(gyr + b + 2 * q);
+      short h, l;
+      split16h(v.x * sc.x, h, l); arh[2 * q] = h; arl[2 * q] = l;
+      split16h(v.y * sc.x, h, l); aih[2 * q] = h; ail[2 * q] = l;
+      split16h(v.z * sc.x, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
+      split16h(v.w * sc.x, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+    }
+    if (XC) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = *(const float4*)((const cplx64*)X + xrow + b + 2 * q);
+        short h, l;
+        split16h(v.x * sc.y, h, l); xrh[2 * q] = h; xrl[2 * q] = l;
+        split16h(v.y * sc.y, h, l); xih[2 * q] = h; xil[2 * q] = l;
+        split16h(v.z * sc.y, h, l); xrh[2 * q + 1] = h; xrl[2 * q + 1] = l;
+        split16h(v.w * sc.y, h, l); xih[2 * q + 1] = h; xil[2 * q + 1] = l;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const float4 v = *(const float4*)((const float*)X + xrow + b + 4 * q);
+        short h, l;
+        split16h(v.x * sc.y, h, l); xrh[4 * q] = h; xrl[4 * q] = l;
+        split16h(v.y * sc.y, h, l); xrh[4 * q + 1] = h; xrl[4 * q + 1] = l;
+        split16h(v.z * sc.y, h, l); xrh[4 * q + 2] = h; xrl[4 * q + 2] = l;
+        split16h(v.w * sc.y, h, l); xrh[4 * q + 3] = h; xrl[4 * q + 3] = l;
+      }
+    }
+    // G = GY conj(X)^T: Re = gr xr + gi xi, Im = gi xr - gr xi (real X: xi = 0)
+    accr = mma16(arh, xrh, accr); accr = mma16(arh, xrl, accr); accr = mma16(arl, xrh, accr);
+    acci = mma16(aih, xrh, acci); acci = mma16(aih, xrl, acci); acci = mma16(ail, xrh, acci);
+    if (XC) {
+      accr = mma16(aih, xih, accr); accr = mma16(aih, xil, accr); accr = mma16(ail, xih, accr);
+      const shortx8 narh = arh ^ (short)0x8000, narl = arl ^ (short)0x8000;
+      acci = mma16(narh, xih, acci); acci = mma16(narh, xil, acci); acci = mma16(narl, xih, acci);
+    }
+  }
+  // lane holds column wj + l32, rows wi + 8 (e / 4) + 4 lh + e % 4: split G s_a into LDS in the split
+  // layout, then 16-byte pieces out (each tile row is 512 contiguous bytes of G), nontemporal
+  typedef int i4v __attribute__((ext_vector_type(4)));
+  const int c = wj + l32;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int rr = wi + 8 * (e >> 2) + 4 * lh + (e & 3);
+    const float vr = accr[e] * sc.z, vi = acci[e] * sc.z;
+    const _Float16 rh = (_Float16)vr, ih = (_Float16)vi;
+    const _Float16 rl = (_Float16)(vr - (float)rh), il = (_Float16)(vi - (float)ih);
+    uint16_t* blk = st + rr * 256 + (c >> 3) * 32 + (c & 7);
+    blk[0] = __builtin_bit_cast(uint16_t, rh);
+    blk[8] = __builtin_bit_cast(uint16_t, rl);
+    blk[16] = __builtin_bit_cast(uint16_t, ih);
+    blk[24] = __builtin_bit_cast(uint16_t, il);
+  }
+  __syncthreads();
+  char* g = (char*)(G + (size_t)a * N * N);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int idx = k * 256 + tid;             // 16-byte piece: row idx / 32, piece idx % 32 of the row
+    const int rr = idx >> 5, pc = idx & 31;
+    const int grow = i0 + rr;
+    if (grow < N && j0 + (pc >> 2) * 8 < N) {
+      const i4v v = *(const i4v*)((const char*)st + rr * 512 + pc * 16);
+      __builtin_nontemporal_store(v, (i4v*)(g + ((size_t)grow * N + j0) * 8 + pc * 16));
+    }
   }
 }
 
@@ -354,15 +469,6 @@ __global__ __launch_bounds__(256) void k_inner(const void* __restrict__ stack, c
 // row so fragment reads of 32 rows spread over the banks.
 constexpr int IM_NA = 64, IM_NW = 8, IM_FLPOS = 256;   // FP32 -> FP64 flush every IM_FLPOS positions
 
-__device__ __forceinline__ void split16h(float v, short& hi, short& lo) {
-  const _Float16 h = (_Float16)v;
-  const _Float16 l = (_Float16)(v - (float)h);
-  hi = __builtin_bit_cast(short, h);
-  lo = __builtin_bit_cast(short, l);
-}
-__device__ __forceinline__ floatx16 mma16(shortx8 a, shortx8 b, floatx16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0, 0, 0);
-}
 
 template <bool CPLX, int PC>
 struct InnerLayout {
@@ -693,6 +799,7 @@ size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   s += apply_ws_bytes(N, ch, B, 0);
   s += align_up((size_t)n_alpha * 8, 256);
   s += align_up((size_t)2 * ch * ceil_div(N, 64) * 4, 256);         // row-norm maxima of GY and X
+  s += align_up((size_t)ch * 16, 256);                              // operand scales of the split outer product
   s += align_up((size_t)ch * 8, 256);                               // G scales
   (void)x_shared;
   return s;
@@ -780,6 +887,8 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   float* gy2 = (float*)base;
   float* x2 = gy2 + (size_t)ch * nrch;
   base += align_up((size_t)2 * ch * nrch * 4, 256);
+  float4* osc = (float4*)base;
+  base += align_up((size_t)ch * 16, 256);
   float2* gsc = (float2*)base;
   const bool use_mfma = inner_mfma_ok(p);
 
@@ -817,11 +926,15 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
         const int nx = x_shared ? 1 : nc;
         if (x_complex) k_rownorm2_max<true><<<dim3(nx, nrch), 256, 0, s>>>(xa, N, B, NB, x2);
         else k_rownorm2_max<false><<<dim3(nx, nrch), 256, 0, s>>>(xa, N, B, NB, x2);
-        k_gbound_scale<<<nc, 256, 0, s>>>(gy2, x2, nrch, x_shared, gsc);
+        k_gbound_scale<<<nc, 256, 0, s>>>(gy2, x2, nrch, x_shared, gsc, osc);
         FG_LAUNCHED("gradient scales");
       }
       const bool vec = B % 4 == 0 && (uintptr_t)gya % 16 == 0 && (uintptr_t)xa % 16 == 0;
       const int key = (x_complex ? 4 : 0) | (vec ? 2 : 0) | (use_mfma ? 1 : 0);
+      if (use_mfma && vec && B % 16 == 0) {   // split-fp16 products, fragments loaded straight from memory
+        if (x_complex) k_outer_split<true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, Gbuf, osc);
+        else k_outer_split<false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, Gbuf, osc);
+      } else
       switch (key) {
         case 0: k_outer<false, false, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
         case 1: k_outer<false, false, true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
