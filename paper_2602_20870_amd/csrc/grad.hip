@@ -252,72 +252,110 @@ __global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ 
 
 // ---------------------------------------------------------------- G = GY X^H, split-fp16 products
 // The same 64 x 64 output tile per workgroup (one 32 x 32 block per wave) as k_outer, on
-// v_mfma_f32_32x32x16_f16 with operands split into fp16 hi/lo after the power-of-two scales osc[a]:
-// each lane loads its fragments straight from global memory (8 consecutive signals of one row of GY
-// and of X: 64 and 32 contiguous bytes), so nothing is staged in LDS before the products; per 16
-// signals 6 products (real X) or 12 (complex X) instead of 16 or 32 FP32 ones.  Output: G s_a in the
-// split layout (k_outer<..., PRE = true>).  B % 16 == 0; rows past N read row N - 1 and are not stored.
+// v_mfma_f32_32x32x16_f16 with operands split into fp16 hi/lo after the power-of-two scales osc[a].
+// Per chunk of 64 signals the tile's 64 GY rows (32 KB) and 64 X rows (16 or 32 KB) move into LDS once
+// with direct loads (16-byte chunks swizzled by row so the fragment reads of 32 rows spread over the
+// banks), and the four waves read their fragments from there: per 16 signals 6 products (real X) or 12
+// (complex X) instead of 16 or 32 FP32 ones.  Output: G s_a in the split layout (as k_outer with PRE).
+// B % 64 == 0; rows past N read row N - 1 and are not stored.
+constexpr int OS_GROW = 64 * 8;                 // bytes of one GY row chunk (64 complex)
+
 template <bool XC>
 __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ GY, const void* __restrict__ X,
                                                      int x_shared, int N, int B, cplx64* __restrict__ G,
                                                      const float4* __restrict__ osc) {
-  __shared__ __align__(16) uint16_t st[64 * 256];
+  constexpr int XROW = 64 * (XC ? 8 : 4), XCPR = XROW / 16;
+  constexpr int GB = 64 * OS_GROW, XB = 64 * XROW;
+  static_assert(GB + XB >= 64 * 512, "the output staging reuses the input LDS");
+  extern __shared__ __align__(16) char osm[];
+  char* gs = osm;
+  char* xs = osm + GB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
   const int a = blockIdx.z;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   const float4 sc = osc[a];
-  const int gi = min(i0 + wi + l32, N - 1), gj = min(j0 + wj + l32, N - 1);
-  const cplx64* gyr = GY + ((size_t)a * N + gi) * B;
-  const size_t xrow = ((size_t)(x_shared ? 0 : a) * N + gj) * B;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  // GY: instruction k (wave + 4q) moves rows 2k, 2k + 1: lane -> row 2k + lane / 32, LDS chunk lane % 32
+  // holding source chunk (lane % 32) ^ (row % 32).  X: rows of XROW bytes, 1024 / XROW rows per instruction.
+  const int grr = lane >> 5, gsl = lane & 31;
+  constexpr int XRPI = 1024 / XROW;
+  const int xrr = lane / XCPR, xsl = lane % XCPR;
   floatx16 accr = {}, acci = {};
-#pragma unroll 4
-  for (int b0 = 0; b0 < B; b0 += 16) {
-    const int b = b0 + 8 * lh;
-    shortx8 arh, arl, aih, ail, xrh, xrl, xih = {}, xil = {};
+  for (int b0 = 0; b0 < B; b0 += 64) {
+    if (b0 > 0) __syncthreads();   // every wave has read the previous chunk
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 v = *(const float4*)(gyr + b + 2 * q);
-      short h, l;
-      split16h(v.x * sc.x, h, l); arh[2 * q] = h; arl[2 * q] = l;
-      split16h(v.y * sc.x, h, l); aih[2 * q] = h; ail[2 * q] = l;
-      split16h(v.z * sc.x, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
-      split16h(v.w * sc.x, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+    for (int q = 0; q < GB / 4096; ++q) {
+      const int k = wv + 4 * q, row = 2 * k + grr;
+      const int gi = min(i0 + row, N - 1);
+      const char* src = (const char*)(GY + ((size_t)a * N + gi) * B + b0) + 16 * (gsl ^ (row & 31));
+      lds_dma16(src, __builtin_amdgcn_readfirstlane(lds_addr(gs + k * 1024)));
     }
-    if (XC) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 v = *(const float4*)((const cplx64*)X + xrow + b + 2 * q);
-        short h, l;
-        split16h(v.x * sc.y, h, l); xrh[2 * q] = h; xrl[2 * q] = l;
-        split16h(v.y * sc.y, h, l); xih[2 * q] = h; xil[2 * q] = l;
-        split16h(v.z * sc.y, h, l); xrh[2 * q + 1] = h; xrl[2 * q + 1] = l;
-        split16h(v.w * sc.y, h, l); xih[2 * q + 1] = h; xil[2 * q + 1] = l;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float4 v = *(const float4*)((const float*)X + xrow + b + 4 * q);
-        short h, l;
-        split16h(v.x * sc.y, h, l); xrh[4 * q] = h; xrl[4 * q] = l;
-        split16h(v.y * sc.y, h, l); xrh[4 * q + 1] = h; xrl[4 * q + 1] = l;
-        split16h(v.z * sc.y, h, l); xrh[4 * q + 2] = h; xrl[4 * q + 2] = l;
-        split16h(v.w * sc.y, h, l); xrh[4 * q + 3] = h; xrl[4 * q + 3] = l;
-      }
+    for (int q = 0; q < XB / 4096; ++q) {
+      const int k = wv + 4 * q, row = XRPI * k + xrr;
+      const int gj = min(j0 + row, N - 1);
+      const size_t xr = ((size_t)(x_shared ? 0 : a) * N + gj) * B + b0;
+      const char* src = (XC ? (const char*)((const cplx64*)X + xr) : (const char*)((const float*)X + xr)) +
+                        16 * (xsl ^ (row % XCPR));
+      lds_dma16(src, __builtin_amdgcn_readfirstlane(lds_addr(xs + k * 1024)));
     }
-    // G = GY conj(X)^T: Re = gr xr + gi xi, Im = gi xr - gr xi (real X: xi = 0)
-    accr = mma16(arh, xrh, accr); accr = mma16(arh, xrl, accr); accr = mma16(arl, xrh, accr);
-    acci = mma16(aih, xrh, acci); acci = mma16(aih, xrl, acci); acci = mma16(ail, xrh, acci);
-    if (XC) {
-      accr = mma16(aih, xih, accr); accr = mma16(aih, xil, accr); accr = mma16(ail, xih, accr);
-      const shortx8 narh = arh ^ (short)0x8000, narl = arl ^ (short)0x8000;
-      acci = mma16(narh, xih, acci); acci = mma16(narh, xil, acci); acci = mma16(narl, xih, acci);
+    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    barrier_nofence();
+    const int ra = wi + l32, rb = wj + l32;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      shortx8 arh, arl, aih, ail, xrh, xrl, xih = {}, xil = {};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {   // GY[ra][16 ks + 8 lh .. + 7]: chunks of two complex
+        const int c = (8 * ks + 4 * lh + q) ^ (ra & 31);
+        const float4 v = *(const float4*)(gs + ra * OS_GROW + c * 16);
+        short h, l;
+        split16h(v.x * sc.x, h, l); arh[2 * q] = h; arl[2 * q] = l;
+        split16h(v.y * sc.x, h, l); aih[2 * q] = h; ail[2 * q] = l;
+        split16h(v.z * sc.x, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
+        split16h(v.w * sc.x, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+      }
+      if (XC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = (8 * ks + 4 * lh + q) ^ (rb % XCPR);
+          const float4 v = *(const float4*)(xs + rb * XROW + c * 16);
+          short h, l;
+          split16h(v.x * sc.y, h, l); xrh[2 * q] = h; xrl[2 * q] = l;
+          split16h(v.y * sc.y, h, l); xih[2 * q] = h; xil[2 * q] = l;
+          split16h(v.z * sc.y, h, l); xrh[2 * q + 1] = h; xrl[2 * q + 1] = l;
+          split16h(v.w * sc.y, h, l); xih[2 * q + 1] = h; xil[2 * q + 1] = l;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int c = (4 * ks + 2 * lh + q) ^ (rb % XCPR);
+          const float4 v = *(const float4*)(xs + rb * XROW + c * 16);
+          short h, l;
+          split16h(v.x * sc.y, h, l); xrh[4 * q] = h; xrl[4 * q] = l;
+          split16h(v.y * sc.y, h, l); xrh[4 * q + 1] = h; xrl[4 * q + 1] = l;
+          split16h(v.z * sc.y, h, l); xrh[4 * q + 2] = h; xrl[4 * q + 2] = l;
+          split16h(v.w * sc.y, h, l); xrh[4 * q + 3] = h; xrl[4 * q + 3] = l;
+        }
+      }
+      // G = GY conj(X)^T: Re = gr xr + gi xi, Im = gi xr - gr xi (real X: xi = 0)
+      accr = mma16(arh, xrh, accr); accr = mma16(arh, xrl, accr); accr = mma16(arl, xrh, accr);
+      acci = mma16(aih, xrh, acci); acci = mma16(aih, xrl, acci); acci = mma16(ail, xrh, acci);
+      if (XC) {
+        accr = mma16(aih, xih, accr); accr = mma16(aih, xil, accr); accr = mma16(ail, xih, accr);
+        const shortx8 narh = arh ^ (short)0x8000, narl = arl ^ (short)0x8000;
+        acci = mma16(narh, xih, acci); acci = mma16(narh, xil, acci); acci = mma16(narl, xih, acci);
+      }
     }
   }
   // lane holds column wj + l32, rows wi + 8 (e / 4) + 4 lh + e % 4: split G s_a into LDS in the split
-  // layout, then 16-byte pieces out (each tile row is 512 contiguous bytes of G), nontemporal
+  // layout (reusing the input LDS), then 16-byte pieces out (each tile row is 512 contiguous bytes of
+  // G), nontemporal
+  __syncthreads();
   typedef int i4v __attribute__((ext_vector_type(4)));
+  uint16_t* st = (uint16_t*)osm;
   const int c = wj + l32;
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -343,6 +381,15 @@ __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ 
       __builtin_nontemporal_store(v, (i4v*)(g + ((size_t)grow * N + j0) * 8 + pc * 16));
     }
   }
+}
+
+template <bool XC>
+static fgfrft_status outer_split_launch(dim3 g, hipStream_t s, const cplx64* GY, const void* X, int x_shared, int N,
+                                        int B, cplx64* G, const float4* osc) {
+  constexpr int lds = 64 * OS_GROW + 64 * 64 * (XC ? 8 : 4);
+  FG_HIP(raise_lds_limit((const void*)k_outer_split<XC>, lds));
+  k_outer_split<XC><<<g, 256, lds, s>>>(GY, X, x_shared, N, B, G, osc);
+  return FGFRFT_OK;
 }
 
 // ---------------------------------------------------------------- T partials per tile
@@ -931,9 +978,10 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
       }
       const bool vec = B % 4 == 0 && (uintptr_t)gya % 16 == 0 && (uintptr_t)xa % 16 == 0;
       const int key = (x_complex ? 4 : 0) | (vec ? 2 : 0) | (use_mfma ? 1 : 0);
-      if (use_mfma && vec && B % 16 == 0) {   // split-fp16 products, fragments loaded straight from memory
-        if (x_complex) k_outer_split<true><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, Gbuf, osc);
-        else k_outer_split<false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, Gbuf, osc);
+      if (use_mfma && vec && B % 64 == 0) {   // split-fp16 products on LDS-staged operands
+        fgfrft_status rc = x_complex ? outer_split_launch<true>(g, s, gya, xa, x_shared, N, B, Gbuf, osc)
+                                     : outer_split_launch<false>(g, s, gya, xa, x_shared, N, B, Gbuf, osc);
+        if (rc) return rc;
       } else
       switch (key) {
         case 0: k_outer<false, false, false><<<g, 256, 0, s>>>(gya, xa, x_shared, N, B, 0, Gbuf, gsc); break;
