@@ -8,12 +8,15 @@
 // {M_1..M_L, M_1^H..M_L^H, P, I}; the host combines them with c_n'(alpha) in FP64.
 //
 // Steps per chunk of orders:
-//   k_outer      G_a = GY[a] X[a]^H                     (FP32 on the matrix cores, LDS-tiled)
-//   k_inner      per 16x16 tile: the tile's 2L stack matrices staged in LDS once,
-//                partial sums of T over the tile's positions for every order of the chunk
-//   k_inner_sum  fixed-order sum of the partials over all tiles in FP64 (deterministic)
+//   k_rownorm2_max, k_gbound_scale   per-order power-of-two scales of G and of the outer product's operands
+//   k_outer_split  G_a = GY[a] X[a]^H on split-fp16 matrix cores, written split (and, for real F with
+//                  N % 32 == 0, in the paired layout); k_outer for the other shapes
+//   k_inner_pair   T partials, each stack matrix read on half of its positions (paired layout);
+//                  k_inner_mfma over all positions otherwise; k_inner per 16x16 tile for N % 8 != 0
+//   k_inner_sum_wg / k_inner_sum   fixed-order sum of the partials in FP64 (deterministic)
 #include "internal.h"
 #include <math.h>
+#include <type_traits>
 #include <vector>
 
 namespace fgfrft {
@@ -252,29 +255,58 @@ __global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ 
 
 // ---------------------------------------------------------------- G = GY X^H, split-fp16 products
 // The same 64 x 64 output tile per workgroup (one 32 x 32 block per wave) as k_outer, on
+// ---------------------------------------------------------------- paired layout of G (real F)
+// For real F the stack holds M_n^H = M_n^T, so the inner products with M_n and with M_n^H can share one
+// read of the stack: beside G on a position (i, j) the kernel needs G on the mirrored position (j, i).
+// Positions are grouped in 32-wide row segments (i, jb) = row i, columns 32 jb .. 32 jb + 31 with
+// jb >= i / 32 (on or above the diagonal 32 x 32 blocks), numbered band by band (band b: rows
+// 32 b .. 32 b + 31), row by row within a band, jb ascending within a row (N % 32 == 0).  Per order two
+// planes of 256 bytes per segment in the split layout (the plane Lt follows the plane U):
+//   U  [segment][t]:  G[i][32 jb + t], zero where 32 jb + t < i,
+//   Lt [segment][t]:  G[32 jb + t][i], zero where 32 jb + t <= i,
+// so every position of G appears exactly once, and for the segment's stack rows
+//   <G, M_n> = sum U . M_n + Lt . M_n^H,   <G, M_n^H> = sum U . M_n^H + Lt . M_n,
+//   <G, P> = sum (U + Lt) . P (P symmetric),   <G, I> = sum U . I (Lt is zero on the diagonal).
+__host__ __device__ inline int pair_nseg(int N) { const int nb = N >> 5; return 16 * nb * (nb + 1); }
+__host__ __device__ inline int pair_band_base(int b, int nb) { return 32 * (b * nb - b * (b - 1) / 2); }
+__host__ __device__ inline int pair_seg(int i, int jb, int nb) {
+  const int b = i >> 5;
+  return pair_band_base(b, nb) + (i & 31) * (nb - b) + (jb - b);
+}
+constexpr int PAIR_SEG_BYTES = 512;
+
 // v_mfma_f32_32x32x16_f16 with operands split into fp16 hi/lo after the power-of-two scales osc[a].
 // Per chunk of 64 signals the tile's 64 GY rows (32 KB) and 64 X rows (16 or 32 KB) move into LDS once
 // with direct loads (16-byte chunks swizzled by row so the fragment reads of 32 rows spread over the
 // banks), and the four waves read their fragments from there: per 16 signals 6 products (real X) or 12
 // (complex X) instead of 16 or 32 FP32 ones.  Output: G s_a in the split layout (as k_outer with PRE).
 // B % 64 == 0; rows past N read row N - 1 and are not stored.
+// PAIR: output in the paired layout (N % 32 == 0).  A tile below the diagonal (blockIdx.y > blockIdx.x)
+// goes only into Lt parts, i.e. transposed: there the MFMA operands trade places, so each lane holds a
+// GY row and the staging writes stay along the segments.
 constexpr int OS_GROW = 64 * 8;                 // bytes of one GY row chunk (64 complex)
 
-template <bool XC>
+template <bool XC, bool PAIR>
 __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ GY, const void* __restrict__ X,
                                                      int x_shared, int N, int B, cplx64* __restrict__ G,
                                                      const float4* __restrict__ osc) {
   constexpr int XROW = 64 * (XC ? 8 : 4), XCPR = XROW / 16;
   constexpr int GB = 64 * OS_GROW, XB = 64 * XROW;
   static_assert(GB + XB >= 64 * 512, "the output staging reuses the input LDS");
+  static_assert(!PAIR || GB + XB >= 192 * 256, "a diagonal tile stages 192 half segments");
   extern __shared__ __align__(16) char osm[];
   char* gs = osm;
   char* xs = osm + GB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
   const int a = blockIdx.z;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int by = blockIdx.y, bx = blockIdx.x;   // tile
+  const int i0 = by * 64, j0 = bx * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // PAIR: the operands trade places in a tile below the diagonal and, in a diagonal tile, in the wave of
+  // the 32 x 32 block below the diagonal
+  const bool lower = by > bx, diag = by == bx;
+  const bool swp = PAIR && (lower || (diag && wi > wj));
   const float4 sc = osc[a];
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   // GY: instruction k (wave + 4q) moves rows 2k, 2k + 1: lane -> row 2k + lane / 32, LDS chunk lane % 32
@@ -283,6 +315,9 @@ __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ 
   constexpr int XRPI = 1024 / XROW;
   const int xrr = lane / XCPR, xsl = lane % XCPR;
   floatx16 accr = {}, acci = {};
+  // the whole signal loop once per operand order (SW: operands traded), chosen per wave
+  auto signal_loop = [&](auto sw_tag) {
+  constexpr bool SW = decltype(sw_tag)::value;
   for (int b0 = 0; b0 < B; b0 += 64) {
     if (b0 > 0) __syncthreads();   // every wave has read the previous chunk
 #pragma unroll
@@ -340,21 +375,104 @@ __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ 
           split16h(v.w * sc.y, h, l); xrh[4 * q + 3] = h; xrl[4 * q + 3] = l;
         }
       }
-      // G = GY conj(X)^T: Re = gr xr + gi xi, Im = gi xr - gr xi (real X: xi = 0)
-      accr = mma16(arh, xrh, accr); accr = mma16(arh, xrl, accr); accr = mma16(arl, xrh, accr);
-      acci = mma16(aih, xrh, acci); acci = mma16(aih, xrl, acci); acci = mma16(ail, xrh, acci);
+      // G = GY conj(X)^T: Re = gr xr + gi xi, Im = gi xr - gr xi (real X: xi = 0); every product is
+      // symmetric in its operands, so trading them (SW) only transposes the wave's 32 x 32 block
+      auto mm = [](shortx8 u, shortx8 v, floatx16 c) { return SW ? mma16(v, u, c) : mma16(u, v, c); };
+      accr = mm(arh, xrh, accr); accr = mm(arh, xrl, accr); accr = mm(arl, xrh, accr);
+      acci = mm(aih, xrh, acci); acci = mm(aih, xrl, acci); acci = mm(ail, xrh, acci);
       if (XC) {
-        accr = mma16(aih, xih, accr); accr = mma16(aih, xil, accr); accr = mma16(ail, xih, accr);
+        accr = mm(aih, xih, accr); accr = mm(aih, xil, accr); accr = mm(ail, xih, accr);
         const shortx8 narh = arh ^ (short)0x8000, narl = arl ^ (short)0x8000;
-        acci = mma16(narh, xih, acci); acci = mma16(narh, xil, acci); acci = mma16(narl, xih, acci);
+        acci = mm(narh, xih, acci); acci = mm(narh, xil, acci); acci = mm(narl, xih, acci);
       }
     }
+  }
+  };
+  if (swp) signal_loop(std::true_type{});
+  else signal_loop(std::false_type{});
+  typedef int i4v __attribute__((ext_vector_type(4)));
+  if constexpr (PAIR) {
+    // stage the tile's 256-byte half segments (U or Lt of one segment) in LDS, then 16-byte pieces out.
+    // Upper tile: U of segments (i0 + r, 2 bx + s), half segment 2 r + s.  Lower tile: Lt of segments
+    // (j0 + c, 2 by + s), half segment 2 c + s.  Diagonal tile: whole segments g = 0 (rows i0 .., column
+    // block 2 by), 1 (rows i0 .., 2 by + 1), 2 (rows i0 + 32 .., 2 by + 1), half segment 2 (32 g + r) + part.
+    const int nb = N >> 5;
+    __syncthreads();   // every wave is done with the input LDS
+    // The lane's element u of the wave's block lands in half segment hb + 2 u at position l32.  In the
+    // two diagonal 32 x 32 blocks of a diagonal tile (row u, column l32 of the block) it goes to U of row u
+    // on and above the diagonal; below it U of row u gets zero and the value goes to Lt of row l32 (half
+    // segment hb + 2 l32 + 1, position u); Lt of row u gets zero on and left of the diagonal.
+    int hb;
+    if (!diag) hb = lower ? 2 * wj + (wi >> 5) : 2 * wi + (wj >> 5);
+    else hb = wi != wj ? 64 + (wi > wj ? 1 : 0) : 4 * wi;
+    const bool dblk = diag && wi == wj;
+    uint16_t* st = (uint16_t*)osm;
+    auto put = [&](int h, int t, _Float16 rh, _Float16 rl, _Float16 ih, _Float16 il) {
+      uint16_t* blk = st + h * 128 + (t >> 3) * 32 + (t & 7);
+      blk[0] = __builtin_bit_cast(uint16_t, rh);
+      blk[8] = __builtin_bit_cast(uint16_t, rl);
+      blk[16] = __builtin_bit_cast(uint16_t, ih);
+      blk[24] = __builtin_bit_cast(uint16_t, il);
+    };
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int u = 8 * (e >> 2) + 4 * lh + (e & 3);
+      const float vr = accr[e] * sc.z, vi = acci[e] * sc.z;
+      const _Float16 rh = (_Float16)vr, ih = (_Float16)vi;
+      const _Float16 rl = (_Float16)(vr - (float)rh), il = (_Float16)(vi - (float)ih);
+      if (!dblk) {
+        put(hb + 2 * u, l32, rh, rl, ih, il);
+      } else {
+        const _Float16 z = (_Float16)0.0f;
+        const bool below = l32 < u;
+        if (below) {
+          put(hb + 2 * u, l32, z, z, z, z);
+          put(hb + 2 * l32 + 1, u, rh, rl, ih, il);
+        } else {
+          put(hb + 2 * u, l32, rh, rl, ih, il);
+        }
+        if (l32 <= u) put(hb + 2 * u + 1, l32, z, z, z, z);
+      }
+    }
+    __syncthreads();
+    const size_t plane = (size_t)pair_nseg(N) * (PAIR_SEG_BYTES / 2);
+    char* g = (char*)G + (size_t)a * 2 * plane;
+    // piece k of this thread: half segment h = 16 k + tid / 16, 16-byte piece tid % 16 of it; all LDS
+    // reads first, then the stores
+    auto target = [&](int h, int& i, int& jb) -> int {   // segment row, column block; returns the part
+      if (!diag) {
+        i = (lower ? j0 : i0) + (h >> 1);
+        jb = 2 * (lower ? by : bx) + (h & 1);
+        return lower ? 1 : 0;
+      }
+      const int q = h >> 1, gg = q >> 5;
+      i = i0 + (gg == 2 ? 32 : 0) + (q & 31);
+      jb = 2 * by + (gg == 0 ? 0 : 1);
+      return h & 1;
+    };
+    const int pc = tid & 15;
+    auto copy_out = [&](auto npieces) {
+      constexpr int NP = decltype(npieces)::value;
+      i4v v[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) v[k] = *(const i4v*)((const char*)st + (16 * k + (tid >> 4)) * 256 + pc * 16);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        int i, jb;
+        const int part = target(16 * k + (tid >> 4), i, jb);
+        if (i < N && jb < nb)
+          __builtin_nontemporal_store(
+              v[k], (i4v*)(g + part * plane + (size_t)pair_seg(i, jb, nb) * (PAIR_SEG_BYTES / 2) + pc * 16));
+      }
+    };
+    if (diag) copy_out(std::integral_constant<int, 12>{});
+    else copy_out(std::integral_constant<int, 8>{});
+    return;
   }
   // lane holds column wj + l32, rows wi + 8 (e / 4) + 4 lh + e % 4: split G s_a into LDS in the split
   // layout (reusing the input LDS), then 16-byte pieces out (each tile row is 512 contiguous bytes of
   // G), nontemporal
   __syncthreads();
-  typedef int i4v __attribute__((ext_vector_type(4)));
   uint16_t* st = (uint16_t*)osm;
   const int c = wj + l32;
 #pragma unroll
@@ -383,12 +501,12 @@ __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ 
   }
 }
 
-template <bool XC>
+template <bool XC, bool PAIR>
 static fgfrft_status outer_split_launch(dim3 g, hipStream_t s, const cplx64* GY, const void* X, int x_shared, int N,
                                         int B, cplx64* G, const float4* osc) {
   constexpr int lds = 64 * OS_GROW + 64 * 64 * (XC ? 8 : 4);
-  FG_HIP(raise_lds_limit((const void*)k_outer_split<XC>, lds));
-  k_outer_split<XC><<<g, 256, lds, s>>>(GY, X, x_shared, N, B, G, osc);
+  FG_HIP(raise_lds_limit((const void*)k_outer_split<XC, PAIR>, lds));
+  k_outer_split<XC, PAIR><<<g, 256, lds, s>>>(GY, X, x_shared, N, B, G, osc);
   return FGFRFT_OK;
 }
 
@@ -728,6 +846,164 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
   }
 }
 
+// Real F, G in the paired layout: stage s is segment s (its U and Lt, 2 x 256 bytes per order) and the
+// segment's 32 positions of the 2L stack matrices, P and the identity, so each stack matrix is read on
+// the segments only (about half of its positions).  The contraction per stage runs over 64 positions:
+// U against the column's own row, then Lt against its partner row (M_n <-> M_n^H; P, the identity,
+// the copies and the zero rows pair with themselves).  Ring, waves, splitting and FP64 flushes (every
+// 256 contracted positions) as in k_inner_mfma; the workgroups take contiguous ranges of segments.
+constexpr int IP_GB = IM_NA * PAIR_SEG_BYTES;   // G bytes of one stage
+constexpr int IP_FL = IM_FLPOS / 64;            // stages per FP32 accumulation
+
+template <int NS, int SM>
+__global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_pair(const void* __restrict__ stack, const void* __restrict__ Pm,
+                                                             int N, int L, const char* __restrict__ G, int n_c,
+                                                             const float2* __restrict__ gsc, int spw, int kb0,
+                                                             double* __restrict__ partial) {
+  using LY = InnerLayout<false, 32>;
+  extern __shared__ __align__(16) char smc[];
+  char* sm = smc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int ab = wave & 1, kg = wave >> 1;
+  const int RD = LY::rd(L), KP2 = LY::kp2(L), KB = KP2 / 32;
+  const size_t SB = IP_GB + (size_t)KP2 * LY::SROW;
+  const size_t NN = (size_t)N * N;
+  const int nb = N >> 5, nseg = pair_nseg(N);
+  const size_t plane = (size_t)nseg * (PAIR_SEG_BYTES / 2), ostride = 2 * plane;
+  const int st0 = blockIdx.x * spw, st1 = st0 + spw < nseg ? st0 + spw : nseg;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+
+  const int nbi = RD / LY::SRPI;
+  const int lw = (IP_GB / 1024 - wv + IM_NW - 1) / IM_NW + (nbi - wv + IM_NW - 1) / IM_NW;
+  for (int s = 0; s < NS; ++s) {
+    uint32_t* z = (uint32_t*)(sm + s * SB + IP_GB + (size_t)(RD + 1) * LY::SROW);
+    for (int e = tid; e < (KP2 - RD - 1) * LY::SROW / 4; e += 64 * IM_NW) z[e] = 0u;
+  }
+  // segment of the next stage to issue: row ci, column block cjb
+  int ci = 0, cjb = 0;
+  if (st0 < st1) {
+    int b = 0;
+    while (b + 1 < nb && pair_band_base(b + 1, nb) <= st0) ++b;
+    const int rem = st0 - pair_band_base(b, nb), w = nb - b;
+    ci = 32 * b + rem / w;
+    cjb = b + rem % w;
+  }
+
+  auto issue = [&](int st) {
+    char* buf = sm + (st % NS) * SB;
+    const size_t p0 = (size_t)ci * N + 32 * cjb;
+    const char* gs = G + (size_t)st * (PAIR_SEG_BYTES / 2);
+    // G: instruction i moves orders 2 i, 2 i + 1 (orders past n_c read order 0); LDS row of an order:
+    // U chunks 0..15, Lt chunks 16..31
+    for (int i = wv; i < IP_GB / 1024; i += IM_NW) {
+      const int r = 2 * i + lh;
+      const int c = l32 ^ (r & 31);
+      const int a = r < n_c ? r : 0;
+      lds_dma16(gs + (size_t)a * ostride + (c >> 4) * plane + (c & 15) * 16,
+                __builtin_amdgcn_readfirstlane(lds_addr(buf + i * 1024)));
+    }
+    // B rows 0..RD-1: stack matrices, P, then copies of P
+    for (int i = wv; i < nbi; i += IM_NW) {
+      const int k = i * LY::SRPI + lane / LY::SCPR, sl = lane % LY::SCPR;
+      const int c = sl ^ (k % LY::SCPR);
+      const char* src = k < 2 * L ? (const char*)stack + (size_t)k * NN * 4 : (const char*)Pm;
+      lds_dma16(src + (p0 + (size_t)c * 4) * 4, __builtin_amdgcn_readfirstlane(lds_addr(buf + IP_GB + i * 1024)));
+    }
+    // identity row RD
+    for (int e = tid; e < 32; e += 64 * IM_NW) {
+      const size_t p = p0 + e;
+      const int c = (e >> 2) ^ (RD % LY::SCPR);
+      float* dst = (float*)(buf + IP_GB + (size_t)RD * LY::SROW + c * 16 + (e & 3) * 4);
+      dst[0] = (p % (size_t)(N + 1)) == 0 ? 1.f : 0.f;
+    }
+    if (++cjb == nb) { ++ci; cjb = ci >> 5; }
+  };
+
+  floatx16 fre = {}, fim = {};
+  double dre[16], dim[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) { dre[e] = 0.0; dim[e] = 0.0; }
+  const int r = 32 * ab + l32;
+  const int kb = kb0 + kg;
+  const bool kact = kb < KB;
+  const int k = 32 * kb + l32;
+  const int kpart = k < L ? k + L : (k < 2 * L ? k - L : k);
+  const bool pairs = SM == 2 && k < 2 * L;   // the partner row is a stack row too
+  for (int q = 0; q < NS - 1 && st0 + q < st1; ++q) issue(st0 + q);
+  int since = 0;
+  for (int st = st0; st < st1; ++st) {
+    if (st + NS - 1 <= st1) wait_vm_upto((NS - 2) * lw);
+    else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+    barrier_nofence();
+    if (st + NS - 1 < st1) issue(st + NS - 1);
+    const char* buf = sm + (st % NS) * SB;
+    if (kact) {
+#pragma unroll
+      for (int vk = 0; vk < 4; ++vk) {
+        const char* grow = buf + (size_t)r * PAIR_SEG_BYTES;
+        const int sw = r & 31;
+        const shortx8 arh = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 0) ^ sw) * 16);
+        const shortx8 arl = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 1) ^ sw) * 16);
+        const shortx8 aih = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 2) ^ sw) * 16);
+        const shortx8 ail = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 3) ^ sw) * 16);
+        const int row = vk < 2 ? k : kpart, kk = vk & 1;
+        const char* brow = buf + IP_GB + (size_t)row * LY::SROW;
+        shortx8 brh, brl;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {   // four reals per chunk
+          const int c = (4 * kk + 2 * lh + q) ^ (row % LY::SCPR);
+          const float4 v = *(const float4*)(brow + c * 16);
+          if (pairs) {
+            const uint4 u = __builtin_bit_cast(uint4, v);
+            brh[4 * q] = (short)(u.x & 0xffff); brl[4 * q] = (short)(u.x >> 16);
+            brh[4 * q + 1] = (short)(u.y & 0xffff); brl[4 * q + 1] = (short)(u.y >> 16);
+            brh[4 * q + 2] = (short)(u.z & 0xffff); brl[4 * q + 2] = (short)(u.z >> 16);
+            brh[4 * q + 3] = (short)(u.w & 0xffff); brl[4 * q + 3] = (short)(u.w >> 16);
+          } else {
+            short h, l;
+            split16h(v.x * kStackScale, h, l); brh[4 * q] = h; brl[4 * q] = l;
+            split16h(v.y * kStackScale, h, l); brh[4 * q + 1] = h; brl[4 * q + 1] = l;
+            split16h(v.z * kStackScale, h, l); brh[4 * q + 2] = h; brl[4 * q + 2] = l;
+            split16h(v.w * kStackScale, h, l); brh[4 * q + 3] = h; brl[4 * q + 3] = l;
+          }
+        }
+        // conj(g) b with real b: Re = gr b, Im = -gi b (the sign is applied at the end)
+        fre = mma16(arh, brh, fre);
+        fre = mma16(arh, brl, fre);
+        fre = mma16(arl, brh, fre);
+        fim = mma16(aih, brh, fim);
+        fim = mma16(aih, brl, fim);
+        fim = mma16(ail, brh, fim);
+      }
+    }
+    if (++since == IP_FL || st + 1 == st1) {
+      since = 0;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        dre[e] += (double)fre[e];
+        dim[e] += (double)fim[e];
+        fre[e] = 0.f;
+        fim[e] = 0.f;
+      }
+    }
+  }
+  if (!kact) return;
+  const int K = 2 * L + 2;
+  const int kk = k <= 2 * L ? k : (k == RD ? 2 * L + 1 : -1);
+  if (kk < 0) return;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int a = 32 * ab + 8 * (e >> 2) + 4 * lh + (e & 3);
+    if (a < n_c) {
+      const double unscale = (double)gsc[a].y / (double)kStackScale;
+      const size_t o = (((size_t)blockIdx.x * n_c + a) * K + kk) * 2;
+      partial[o] = dre[e] * unscale;
+      partial[o + 1] = -dim[e] * unscale;
+    }
+  }
+}
+
 // T[a][k] = sum over workgroups in a fixed order (FP64).
 __global__ __launch_bounds__(256) void k_inner_sum_wg(const double* __restrict__ partial, int nwg, int n_c, int K,
                                                       int a_first, double* __restrict__ T) {
@@ -830,15 +1106,59 @@ static bool inner_mfma_ok(const Plan* p) {
 }
 static int inner_mfma_wgs() { return 256; }
 
+// paired inner products (real F, N % 32 == 0): stage bytes 32 KB of G + the stack rows, ring of up to 3
+static int pair_stages_fit(const Plan* p) {
+  const size_t sb = IP_GB + (size_t)InnerLayout<false, 32>::kp2(p->L) * InnerLayout<false, 32>::SROW;
+  const int ns = (int)((160 * 1024) / sb);
+  return ns > 3 ? 3 : ns;
+}
+static bool inner_pair_ok(const Plan* p) {
+  return !p->cplx && p->N % 32 == 0 && inner_mfma_ok(p) && pair_stages_fit(p) >= 2 &&
+         (p->stacktype == FGFRFT_STACK_FP32 || p->stacktype == FGFRFT_STACK_FP16X2);
+}
+static int inner_pair_grid(const Plan* p) {
+  const int nseg = pair_nseg(p->N);
+  return nseg < inner_mfma_wgs() ? nseg : inner_mfma_wgs();
+}
+// bytes of one order's G: N x N complex64 or split, or the paired layout (1 + 32 / N times that)
+static size_t g_order_bytes(const Plan* p) {
+  const size_t plain = (size_t)p->N * p->N * 8;
+  if (!inner_pair_ok(p)) return plain;
+  const size_t pair = (size_t)pair_nseg(p->N) * PAIR_SEG_BYTES;
+  return pair > plain ? pair : plain;
+}
+
+template <int NS, int SM>
+static fgfrft_status inner_pair_launch_ns(const Plan* p, const char* G, int nc, const float2* gsc, double* partial,
+                                          hipStream_t s) {
+  using LY = InnerLayout<false, 32>;
+  const int nseg = pair_nseg(p->N);
+  const int nwg = inner_pair_grid(p), spw = ceil_div(nseg, nwg);
+  const int lds = (int)(NS * (IP_GB + (size_t)LY::kp2(p->L) * LY::SROW));
+  const int KB = LY::kp2(p->L) / 32;
+  auto kern = k_inner_pair<NS, SM>;
+  FG_HIP(raise_lds_limit((const void*)kern, lds));
+  for (int kb0 = 0; kb0 < KB; kb0 += 4)
+    kern<<<nwg, 64 * IM_NW, lds, s>>>(p->stack, p->P, p->N, p->L, G, nc, gsc, spw, kb0, partial);
+  FG_LAUNCHED("inner_pair");
+  return FGFRFT_OK;
+}
+static fgfrft_status inner_pair_launch(const Plan* p, const char* G, int nc, const float2* gsc, double* partial,
+                                       hipStream_t s) {
+  const bool f16 = p->stacktype == FGFRFT_STACK_FP16X2;
+  if (pair_stages_fit(p) >= 3)
+    return f16 ? inner_pair_launch_ns<3, 2>(p, G, nc, gsc, partial, s) : inner_pair_launch_ns<3, 0>(p, G, nc, gsc, partial, s);
+  return f16 ? inner_pair_launch_ns<2, 2>(p, G, nc, gsc, partial, s) : inner_pair_launch_ns<2, 0>(p, G, nc, gsc, partial, s);
+}
+
 size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   const int ch = grad_chunk(p, n_alpha);
   const int N = p->N, nb = ceil_div(N, GT), npairs = nb * nb, K = 2 * p->L + 2;
-  const size_t ntile = (size_t)ceil_div(N, 64) * ceil_div(N, 64);
   size_t part = (size_t)npairs * ch * 2 * K * 16;                   // partials (complex FP64)
   const size_t part2 = (size_t)inner_mfma_wgs() * ch * K * 16;
   if (part2 > part) part = part2;
   size_t s = 0;
-  s += align_up((size_t)ch * N * N * 8, 256);                       // G chunk / Q(-alpha) chunk
+  s += align_up((size_t)ch * g_order_bytes(p), 256);                // G chunk / Q(-alpha) chunk
   s += align_up(part, 256);
   s += align_up((size_t)n_alpha * K * 16, 256);                     // T
   s += align_up((size_t)ch * N * B * 8, 256);                       // dX chunk (shared X)
@@ -924,7 +1244,7 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   const size_t part2 = (size_t)inner_mfma_wgs() * ch * K * 16;
   if (part2 > part) part = part2;
   char* base = (char*)ws;
-  cplx64* Gbuf = (cplx64*)base; base += align_up((size_t)ch * N * N * 8, 256);
+  cplx64* Gbuf = (cplx64*)base; base += align_up((size_t)ch * g_order_bytes(p), 256);
   double* partial = (double*)base; base += align_up(part, 256);
   double* T = (double*)base; base += align_up((size_t)n_alpha * K * 16, 256);
   void* dXc = base; base += align_up((size_t)ch * N * B * 8, 256);
@@ -938,6 +1258,8 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   base += align_up((size_t)ch * 16, 256);
   float2* gsc = (float2*)base;
   const bool use_mfma = inner_mfma_ok(p);
+  const bool use_pair = inner_pair_ok(p);   // real F, N % 32 == 0: paired layout when G is split on MFMA
+  bool split_outer = false;
 
   const size_t lds = inner_lds(p);
   if (!use_mfma)
@@ -978,9 +1300,13 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
       }
       const bool vec = B % 4 == 0 && (uintptr_t)gya % 16 == 0 && (uintptr_t)xa % 16 == 0;
       const int key = (x_complex ? 4 : 0) | (vec ? 2 : 0) | (use_mfma ? 1 : 0);
-      if (use_mfma && vec && B % 64 == 0) {   // split-fp16 products on LDS-staged operands
-        fgfrft_status rc = x_complex ? outer_split_launch<true>(g, s, gya, xa, x_shared, N, B, Gbuf, osc)
-                                     : outer_split_launch<false>(g, s, gya, xa, x_shared, N, B, Gbuf, osc);
+      split_outer = use_mfma && vec && B % 64 == 0;
+      if (split_outer) {   // split-fp16 products on LDS-staged operands
+        fgfrft_status rc;
+        if (use_pair) rc = x_complex ? outer_split_launch<true, true>(g, s, gya, xa, x_shared, N, B, Gbuf, osc)
+                                     : outer_split_launch<false, true>(g, s, gya, xa, x_shared, N, B, Gbuf, osc);
+        else rc = x_complex ? outer_split_launch<true, false>(g, s, gya, xa, x_shared, N, B, Gbuf, osc)
+                            : outer_split_launch<false, false>(g, s, gya, xa, x_shared, N, B, Gbuf, osc);
         if (rc) return rc;
       } else
       switch (key) {
@@ -995,7 +1321,12 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
       }
       FG_LAUNCHED("outer");
     }
-    if (use_mfma) {
+    if (use_mfma && use_pair && split_outer) {   // G in the paired layout
+      fgfrft_status rc = inner_pair_launch(p, (const char*)Gbuf, nc, gsc, partial, s);
+      if (rc) return rc;
+      k_inner_sum_wg<<<dim3(K, nc), 256, 0, s>>>(partial, inner_pair_grid(p), nc, K, a0, T);
+      FG_LAUNCHED("inner_sum");
+    } else if (use_mfma) {
       fgfrft_status rc = p->cplx ? inner_mfma_launch<true, IM_PC_CPLX>(p, Gbuf, nc, gsc, partial, s)
                                  : inner_mfma_launch<false, IM_PC_REAL>(p, Gbuf, nc, gsc, partial, s);
       if (rc) return rc;

@@ -108,6 +108,7 @@ class Plan:
                              pb.value, _ptr(scratch), sb.value, _stream(stream), ctypes.byref(h)), "fgfrft_plan")
         del scratch
         self._h = h
+        self._destroy = L_.fgfrft_destroy   # held here: module globals may be gone when __del__ runs at exit
         self.N, self.L = N, L
         self.complex = intype == 0
         self.stacktype = stacktype
@@ -115,8 +116,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().fgfrft_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
     # ------------------------------------------------------------------ info

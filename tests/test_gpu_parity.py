@@ -319,6 +319,40 @@ def test_grad_outer_product_row_scales(xc, B):
     assert rel_fro(dX.cpu().numpy(), dX_ref) <= TOL_FP32
 
 
+@pytest.mark.parametrize("N,L,n,xc,shared,B,stacktype", [
+    (32, 4, 3, True, False, 64, "fp32"),       # one diagonal 32 x 32 block, complex signals
+    (96, 9, 5, False, False, 64, "fp16x2"),    # a 64-tile cut at N: partial diagonal and edge tiles
+    (160, 20, 4, False, True, 128, "fp32"),    # shared signals, two 64-signal chunks
+    (64, 64, 3, False, False, 64, "fp16x2"),   # five k-blocks: two passes over the segments
+    (256, 33, 70, True, False, 64, "fp16x2")])  # two chunks of orders
+def test_grad_paired_layout(N, L, n, xc, shared, B, stacktype):
+    """Real F with N % 32 == 0 and B % 64 == 0: G is written in the paired layout (a segment's values
+    beside their mirror images) and each stack matrix is read on half of its positions; Proposition 4
+    with M_n^H = M_n^T (Proposition 2) against the oracle."""
+    torch = torch_cuda()
+    announce(f"grad paired layout N={N} L={L} n={n} xc={xc} shared={shared} B={B} stack {stacktype}")
+    rng = np.random.default_rng(N + 7 * L + n)
+    F = _real_orthogonal_with_minus1(N, 3, N + L)
+    alphas = rng.uniform(-min(L - 0.5, 2.5), min(L - 0.5, 2.5), n)
+    alphas[0] = 1.0
+    shape = (N, B) if shared else (n, N, B)
+    X = synth.complex_signals(shape, rng) if xc else synth.real_signals(shape, rng)
+    X = X.astype(np.complex64 if xc else np.float32)
+    GY = ((rng.standard_normal((n, N, B)) + 1j * rng.standard_normal((n, N, B)))
+          * np.logspace(-2, 2, n)[:, None, None]).astype(np.complex64)
+    plan = _gpu_plan(torch, F, L, stacktype)
+    ref = O.Plan(F, L)
+    Xd = X.astype(np.complex128) if xc else X.astype(np.float64)
+    Xs = np.broadcast_to(Xd, (n, N, B)) if shared else Xd
+    dal_ref, dX_ref = O.grad(ref.P, ref.M, alphas, Xs, GY.astype(np.complex128), x_real=not xc)
+    dal, dX = plan.grad(alphas, torch.from_numpy(X).cuda(), torch.from_numpy(GY).cuda())
+    for a in range(n):   # each order against its own magnitude
+        assert abs(dal[a] - dal_ref[a]) <= TOL_FP32 * max(abs(dal_ref[a]), 1e-3 * np.max(np.abs(GY[a]))), a
+    dX = dX.cpu().numpy()
+    dX_ref = dX_ref.sum(axis=0) if shared else dX_ref
+    assert rel_fro(dX, dX_ref) <= TOL_FP32
+
+
 @pytest.mark.parametrize("N,L,n,cplxF", [(50, 9, 5, False),    # N % 8 != 0: per-tile inner products
                                          # the same kernel after it, needing more LDS than 64 KB (69 KB,
                                          # 90 KB): the limit set by the first call must be raised
