@@ -253,6 +253,30 @@ FGFRFT_API fgfrft_status fgfrft_apply_direct(fgfrft_plan_t plan, const double* a
                                              int ncols, int ldx, void* Y_dev, int ldy, void* ws_dev,
                                              size_t ws_bytes, void* stream);
 
+/* Workspace bytes for fgfrft_apply_batched (per group of up to 64 requests: the gathered signals,
+ * the results, the column map and the direct route's workspace; the largest group counts).
+ * Returns 0 for a NULL plan or table, n_req < 1, or a signal count outside [0, 4096]. */
+FGFRFT_API size_t fgfrft_apply_batched_workspace_bytes(fgfrft_plan_t plan, int n_req, const int* B_per_req,
+                                                       int x_complex);
+
+/* Grouped apply for serving (Definition 2, one order per request): request r gets
+ *   Y_dev[r] = Q_L^{alphas[r]} X_dev[r]
+ * for r = 0..n_req-1, each request with its own order and its own number of signals.
+ *   alphas: host float64 [n_req], each finite with |alpha| < L (else FGFRFT_EALPHA, nothing
+ *   enqueued); B_per_req: host int32 [n_req], each in [0, 4096] (0: the request is skipped);
+ *   X_dev, Y_dev: host arrays of n_req device pointers; X_dev[r]: [N][B_per_req[r]] row-major,
+ *   float32 (x_complex = 0) or complex64 (x_complex = 1), element-aligned; Y_dev[r]: complex64
+ *   [N][B_per_req[r]], 8-byte aligned, not overlapping any X_dev.
+ * The requests are taken in groups of 64: per group the signals are gathered into one column
+ * block of the workspace, the direct route of fgfrft_apply_direct runs once over it (each column
+ * with its request's order; the stack is streamed once per 64 columns), and the results are
+ * scattered to Y_dev.  The request tables travel as kernel arguments, so nothing is copied from
+ * the host: the call only enqueues work on `stream` and can be captured in a graph (the host
+ * arrays are read during the call only).  Accuracy as fgfrft_apply_direct. */
+FGFRFT_API fgfrft_status fgfrft_apply_batched(fgfrft_plan_t plan, const double* alphas, int n_req,
+                                              const int* B_per_req, const void* const* X_dev, int x_complex,
+                                              void* const* Y_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Gradients (Proposition 4)
  * ------------------------------------------------------------------------- */

@@ -33,6 +33,9 @@ SIGNATURES = {
     "fgfrft_apply_direct_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int]),
     "fgfrft_apply_direct": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p,
                                     c_int, c_void_p, c_size_t, c_void_p]),
+    "fgfrft_apply_batched_workspace_bytes": (c_size_t, [c_void_p, c_int, P_int, c_int]),
+    "fgfrft_apply_batched": (c_int, [c_void_p, P_double, c_int, P_int, ctypes.POINTER(c_void_p), c_int,
+                                     ctypes.POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),
     "fgfrft_grad_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "fgfrft_grad": (c_int, [c_void_p, P_double, c_int, c_void_p, c_int, c_int, c_int, c_void_p, P_double,
                             c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -1,5 +1,6 @@
 // C ABI of the FGFRFT library: argument validation, buffer carving and dispatch.
 #include "internal.h"
+#include "batch.h"
 #include <cmath>
 #include <math.h>
 #include <stdarg.h>
@@ -289,6 +290,40 @@ fgfrft_status fgfrft_apply_direct(fgfrft_plan_t plan, const double* alphas_dev, 
   if (ws_bytes < need) { set_error("direct workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
   return direct_launch(p, alphas_dev, n_alpha, col_order_dev, X_dev, x_complex ? 1 : 0, ncols, ldx, Y_dev, ldy, ws_dev,
                        (hipStream_t)stream);
+}
+
+size_t fgfrft_apply_batched_workspace_bytes(fgfrft_plan_t plan, int n_req, const int* B_per_req, int x_complex) {
+  if (!plan || n_req < 1 || !B_per_req) return 0;
+  for (int r = 0; r < n_req; ++r)
+    if (B_per_req[r] < 0 || B_per_req[r] > 4096) return 0;
+  return batched_ws_bytes((const Plan*)plan, n_req, B_per_req, x_complex ? 1 : 0);
+}
+
+fgfrft_status fgfrft_apply_batched(fgfrft_plan_t plan, const double* alphas, int n_req, const int* B_per_req,
+                                   const void* const* X_dev, int x_complex, void* const* Y_dev, void* ws_dev,
+                                   size_t ws_bytes, void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  fgfrft_status rc = check_alphas(p, alphas, n_req);
+  if (rc) return rc;
+  if (!B_per_req || !X_dev || !Y_dev || !ws_dev) { set_error("NULL pointer"); return FGFRFT_EINVAL; }
+  if (!aligned(ws_dev, 256)) { set_error("ws_dev must be 256-byte aligned"); return FGFRFT_EINVAL; }
+  const size_t xe = x_complex ? 8 : 4;
+  for (int r = 0; r < n_req; ++r) {
+    if (B_per_req[r] < 0 || B_per_req[r] > 4096) {
+      set_error("B_per_req[%d]=%d outside [0, 4096]", r, B_per_req[r]);
+      return FGFRFT_EINVAL;
+    }
+    if (B_per_req[r] == 0) continue;
+    if (!X_dev[r] || !Y_dev[r]) { set_error("request %d: NULL signal or output pointer", r); return FGFRFT_EINVAL; }
+    if (!aligned(X_dev[r], xe) || !aligned(Y_dev[r], 8)) {
+      set_error("request %d: signals must be element-aligned and outputs 8-byte aligned", r);
+      return FGFRFT_EINVAL;
+    }
+  }
+  const size_t need = batched_ws_bytes(p, n_req, B_per_req, x_complex ? 1 : 0);
+  if (ws_bytes < need) { set_error("batched workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  return batched_launch(p, alphas, n_req, B_per_req, X_dev, x_complex ? 1 : 0, Y_dev, ws_dev, (hipStream_t)stream);
 }
 
 size_t fgfrft_grad_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_shared) {

@@ -230,6 +230,47 @@ class Plan:
                               chunk: int = 0) -> int:
         return int(lib().fgfrft_apply_workspace_bytes(self._h, n_alpha, B, int(x_complex), int(x_shared), chunk))
 
+    def apply_batched(self, alphas, Xs, outs=None, ws: torch.Tensor | None = None, stream=None) -> list:
+        """Grouped apply: request r gets Q(alphas[r]) Xs[r], each with its own order and signal count.
+
+        alphas: host sequence of n orders; Xs: n contiguous cuda tensors [N, B_r] (all float32 or all
+        complex64); outs: n complex64 [N, B_r] tensors or None.  One gather, one direct-route pass and
+        one scatter per group of 64 requests, all on the device.
+        """
+        dev = self.device
+        al = _alphas(alphas)
+        n = al.size
+        if len(Xs) != n:
+            raise ValueError("one signal block per order")
+        dts = {X.dtype for X in Xs}
+        if dts == {torch.float32}:
+            xc = 0
+        elif dts == {torch.complex64}:
+            xc = 1
+        else:
+            raise TypeError("signals must be all float32 or all complex64")
+        for X in Xs:
+            _on_device(dev, X=X)
+            if X.dim() != 2 or X.shape[0] != self.N or not X.is_contiguous():
+                raise ValueError(f"each signal block must be a contiguous cuda tensor of shape [{self.N}, B]")
+        if outs is None:
+            outs = [torch.empty((self.N, X.shape[1]), dtype=torch.complex64, device=dev) for X in Xs]
+        if len(outs) != n:
+            raise ValueError("one output per order")
+        for X, Y in zip(Xs, outs):
+            _on_device(dev, out=Y)
+            if Y.shape != X.shape or Y.dtype != torch.complex64 or not Y.is_contiguous():
+                raise ValueError("each output must be a contiguous complex64 tensor shaped like its signals")
+        B = (ctypes.c_int * n)(*[int(X.shape[1]) for X in Xs])
+        xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        yp = (ctypes.c_void_p * n)(*[Y.data_ptr() for Y in outs])
+        L_ = lib()
+        ws, tmp = _caller_ws(ws, L_.fgfrft_apply_batched_workspace_bytes(self._h, n, B, xc), dev)
+        check(L_.fgfrft_apply_batched(self._h, al.ctypes.data_as(P_double), n, B, xp, xc, yp, _ptr(ws), ws.numel(),
+                                      _stream(stream)), "fgfrft_apply_batched")
+        _keep(stream, tmp)
+        return outs
+
     def apply_direct(self, alphas, col_order, X: torch.Tensor, ncols: int | None = None, out: torch.Tensor | None = None,
                      ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """Y[:, c] = Q(alphas[col_order[c]]) X[:, c] straight from the resident stack (no operator formed).

@@ -57,6 +57,16 @@ int main(void) {
   expect(fgfrft_apply_direct(NULL, al, 2, NULL, buf, 0, 4, 4, buf, 4, buf, 256, NULL), FGFRFT_EINVAL,
          "apply_direct NULL plan");
   expect(fgfrft_grad(NULL, al, 2, buf, 0, 0, 4, buf, dal, NULL, buf, 256, NULL), FGFRFT_EINVAL, "grad NULL plan");
+  {
+    int bq[2] = {4, 3};
+    const void* xs[2] = {buf, buf};
+    void* ys[2] = {buf, buf};
+    expect(fgfrft_apply_batched(NULL, al, 2, bq, xs, 0, ys, buf, 256, NULL), FGFRFT_EINVAL, "apply_batched NULL plan");
+    if (fgfrft_apply_batched_workspace_bytes(NULL, 2, bq, 0) != 0) {
+      fprintf(stderr, "FAIL apply_batched workspace query on a NULL plan\n");
+      ++failures;
+    }
+  }
   if (fgfrft_update_workspace_bytes(NULL, 4) != 0 || fgfrft_apply_workspace_bytes(NULL, 4, 4, 0, 0, 0) != 0 ||
       fgfrft_apply_direct_workspace_bytes(NULL, 4, 4) != 0 || fgfrft_grad_workspace_bytes(NULL, 4, 4, 0) != 0) {
     fprintf(stderr, "FAIL workspace queries on a NULL plan\n");

@@ -82,6 +82,12 @@ def test_null_and_small_arguments_are_rejected_on_host(L):
     assert L.fgfrft_apply_direct(None, None, 1, None, None, 0, 4, 4, None, 4, None, 0, None) == -1
     assert b"NULL plan" in L.fgfrft_last_error()
     assert L.fgfrft_apply_direct_workspace_bytes(None, 4, 4) == 0
+    # grouped apply: NULL plan, and no workspace size for a NULL plan or a NULL count table
+    bq = (ctypes.c_int * 2)(4, 3)
+    ptrs = (ctypes.c_void_p * 2)(0x100000, 0x200000)
+    assert L.fgfrft_apply_batched(None, a, 2, bq, ptrs, 0, ptrs, None, 0, None) == -1
+    assert b"NULL plan" in L.fgfrft_last_error()
+    assert L.fgfrft_apply_batched_workspace_bytes(None, 2, bq, 0) == 0
 
 
 

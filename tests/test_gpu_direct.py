@@ -210,3 +210,77 @@ def test_direct_knn4096_launch_config_sampled_rows():
     assert rel_fro(Y[:, 0:2], X[:, 0:2]) <= TOL_FP32
     assert rel_fro(Y[:, 2:4], F @ X[:, 2:4].astype(np.float64)) <= TOL_FP32
     assert rel_fro(Y[:, 4:6], F.T @ X[:, 4:6].astype(np.float64)) <= TOL_FP32
+
+
+@pytest.mark.parametrize("case", ["real_mfma", "complex_plain_two_groups", "fp16x2_cut_tile"])
+def test_apply_batched_requests(case):
+    """fgfrft_apply_batched: each request with its own order and signal count (zero, one, ragged,
+    more than 64) gets Q(alpha_r) X_r, against the oracle per request; 70 requests take two
+    groups of 64 and 6."""
+    torch = torch_cuda()
+    announce(f"apply_batched {case}")
+    rng = np.random.default_rng({"real_mfma": 41, "complex_plain_two_groups": 42, "fp16x2_cut_tile": 43}[case])
+    stacktype = "fp32"
+    if case == "real_mfma":                  # real F, real signals, N % 32 == 0: matrix-core kernel
+        F = synth.make_config("knn4096", seed=8, N=96, with_signals=False)["F"]
+        L, counts, xc = 12, [3, 0, 1, 64, 17, 100, 2], False
+    elif case == "complex_plain_two_groups":  # complex F, complex signals: plain kernel
+        F = synth.haar_unitary(40, rng)
+        L, xc = 9, True
+        counts = list(rng.integers(0, 6, 70))
+    else:                                    # FP16X2 stack, N = 160 (a 64-row block cut at N)
+        F = synth.make_config("knn4096", seed=9, N=160, with_signals=False)["F"]
+        L, counts, xc, stacktype = 20, [65, 1, 7, 0, 31], False, "fp16x2"
+    N, n = F.shape[0], len(counts)
+    alphas = rng.uniform(-min(L - 0.5, 2.5), min(L - 0.5, 2.5), n)
+    alphas[0] = 1.0
+    mk = synth.complex_signals if xc else synth.real_signals
+    Xs = [mk((N, int(b)), rng).astype(np.complex64 if xc else np.float32) for b in counts]
+    plan = _plan(torch, F, L, stacktype=stacktype)
+    ref = O.Plan(F, L)
+    outs = plan.apply_batched(alphas, [torch.from_numpy(X).cuda() for X in Xs])
+    worst = 0.0
+    for r, (X, Y) in enumerate(zip(Xs, outs)):
+        assert tuple(Y.shape) == X.shape
+        if X.shape[1] == 0:
+            continue
+        e = rel_fro(Y.cpu().numpy(), ref.combine(float(alphas[r])) @ X.astype(np.complex128))
+        worst = max(worst, e)
+        assert e <= TOL_FP32, (r, alphas[r], e)
+    print(case, "worst rel err", worst)
+
+
+def test_apply_batched_refusals():
+    """Host-side refusals of fgfrft_apply_batched on a real plan: counts out of range, a NULL or
+    misaligned request pointer, an order out of range and a short workspace; nothing is enqueued."""
+    import ctypes
+    torch = torch_cuda()
+    from paper_2602_20870_amd._lib import lib
+    announce("apply_batched refusals")
+    F = synth.make_config("knn4096", seed=8, N=64, with_signals=False)["F"]
+    plan = _plan(torch, F, 8)
+    L_ = lib()
+    X = torch.zeros((64, 8), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((64, 8), dtype=torch.complex64, device="cuda")
+    ws = torch.zeros(1 << 22, dtype=torch.uint8, device="cuda")
+
+    def call(al, counts, xs, ys, wsb=ws.numel(), wsp=None):
+        n = len(counts)
+        a = (ctypes.c_double * n)(*al)
+        b = (ctypes.c_int * n)(*counts)
+        xp = (ctypes.c_void_p * n)(*xs)
+        yp = (ctypes.c_void_p * n)(*ys)
+        return L_.fgfrft_apply_batched(plan._h, a, n, b, xp, 0, yp, wsp or ws.data_ptr(), wsb, None)
+
+    x, y = X.data_ptr(), Y.data_ptr()
+    assert call([0.5, 0.1], [4, -1], [x, x], [y, y]) == -1
+    assert call([0.5, 0.1], [4, 5000], [x, x], [y, y]) == -1
+    assert call([0.5, 0.1], [4, 2], [x, None], [y, y]) == -1
+    assert call([0.5, 0.1], [4, 2], [x, x + 2], [y, y]) == -1
+    assert call([0.5, 0.1], [4, 2], [x, x], [y, y + 4]) == -1
+    assert call([0.5, 9.0], [4, 2], [x, x], [y, y]) == -3
+    assert call([0.5, 0.1], [4, 2], [x, x], [y, y], wsb=256) == -4
+    assert call([0.5, 0.1], [4, 2], [x, x], [y, y], wsp=ws.data_ptr() + 128) == -1
+    # a request with no signals may pass NULL pointers
+    assert call([0.5, 0.1], [4, 0], [x, None], [y, None]) == 0
+    torch.cuda.synchronize()
