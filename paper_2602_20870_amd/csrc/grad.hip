@@ -253,8 +253,56 @@ __global__ __launch_bounds__(256) void k_gbound_scale(const float* __restrict__ 
   }
 }
 
-// ---------------------------------------------------------------- G = GY X^H, split-fp16 products
-// The same 64 x 64 output tile per workgroup (one 32 x 32 block per wave) as k_outer, on
+// ---------------------------------------------------------------- operands of the outer product, split once
+// GY (complex64) and X (float32 or complex64) [n][N][B] scaled by the order's power of two (osc[v].x for
+// GY, osc[v].y for X; one block shared by all orders takes osc[0], the same for every order since it
+// depends on X alone) and split into fp16 hi / lo per 8 consecutive signals: complex [Re hi x 8]
+// [Re lo x 8][Im hi x 8][Im lo x 8] (64 bytes), real [hi x 8][lo x 8] (32 bytes), so a block keeps the
+// bytes and offsets of its 8 source elements.  These are the values k_outer_split would otherwise
+// split per wave and per tile (each GY row is used by N / 64 tiles and two waves).
+template <bool CPX>
+__global__ __launch_bounds__(256) void k_presplit(const void* __restrict__ V, size_t nblk, int N, int B,
+                                                  const float4* __restrict__ osc, int comp, int shared,
+                                                  char* __restrict__ out) {
+  const int bpr = B >> 3;   // 8-signal blocks per row
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < nblk; t += (size_t)gridDim.x * 256) {
+    const size_t row = t / bpr;                           // v * N + i
+    const int v = shared ? 0 : (int)(row / (size_t)N);
+    const float4 o = osc[v];
+    const float s = comp ? o.y : o.x;
+    const size_t e0 = t * 8;                              // first element of the block
+    if (CPX) {
+      const float4* src = (const float4*)((const cplx64*)V + e0);
+      shortx8 rh, rl, ih, il;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 w = src[q];
+        short h, l;
+        split16h(w.x * s, h, l); rh[2 * q] = h; rl[2 * q] = l;
+        split16h(w.y * s, h, l); ih[2 * q] = h; il[2 * q] = l;
+        split16h(w.z * s, h, l); rh[2 * q + 1] = h; rl[2 * q + 1] = l;
+        split16h(w.w * s, h, l); ih[2 * q + 1] = h; il[2 * q + 1] = l;
+      }
+      shortx8* dst = (shortx8*)(out + e0 * 8);
+      dst[0] = rh; dst[1] = rl; dst[2] = ih; dst[3] = il;
+    } else {
+      const float4* src = (const float4*)((const float*)V + e0);
+      shortx8 hi, lo;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const float4 w = src[q];
+        short h, l;
+        split16h(w.x * s, h, l); hi[4 * q] = h; lo[4 * q] = l;
+        split16h(w.y * s, h, l); hi[4 * q + 1] = h; lo[4 * q + 1] = l;
+        split16h(w.z * s, h, l); hi[4 * q + 2] = h; lo[4 * q + 2] = l;
+        split16h(w.w * s, h, l); hi[4 * q + 3] = h; lo[4 * q + 3] = l;
+      }
+      shortx8* dst = (shortx8*)(out + e0 * 4);
+      dst[0] = hi; dst[1] = lo;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- paired layout of G (real F)
 // For real F the stack holds M_n^H = M_n^T, so the inner products with M_n and with M_n^H can share one
 // read of the stack: beside G on a position (i, j) the kernel needs G on the mirrored position (j, i).
@@ -275,11 +323,13 @@ __host__ __device__ inline int pair_seg(int i, int jb, int nb) {
 }
 constexpr int PAIR_SEG_BYTES = 512;
 
-// v_mfma_f32_32x32x16_f16 with operands split into fp16 hi/lo after the power-of-two scales osc[a].
-// Per chunk of 64 signals the tile's 64 GY rows (32 KB) and 64 X rows (16 or 32 KB) move into LDS once
-// with direct loads (16-byte chunks swizzled by row so the fragment reads of 32 rows spread over the
-// banks), and the four waves read their fragments from there: per 16 signals 6 products (real X) or 12
-// (complex X) instead of 16 or 32 FP32 ones.  Output: G s_a in the split layout (as k_outer with PRE).
+// ---------------------------------------------------------------- G = GY X^H, split-fp16 products
+// The same 64 x 64 output tile per workgroup (one 32 x 32 block per wave) as k_outer, on
+// v_mfma_f32_32x32x16_f16 with the operands split by k_presplit.  Per chunk of 64 signals the tile's
+// 64 GY rows (32 KB) and 64 X rows (16 or 32 KB) move into LDS once with direct loads (16-byte chunks
+// swizzled by row so the fragment reads of 32 rows spread over the banks), and the four waves read
+// their fragments from there as stored: per 16 signals 6 products (real X) or 12 (complex X) instead
+// of 16 or 32 FP32 ones.  Output: G s_a in the split layout (as k_outer with PRE).
 // B % 64 == 0; rows past N read row N - 1 and are not stored.
 // PAIR: output in the paired layout (N % 32 == 0).  A tile below the diagonal (blockIdx.y > blockIdx.x)
 // goes only into Lt parts, i.e. transposed: there the MFMA operands trade places, so each lane holds a
@@ -341,39 +391,22 @@ __global__ __launch_bounds__(256) void k_outer_split(const cplx64* __restrict__ 
     const int ra = wi + l32, rb = wj + l32;
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      shortx8 arh, arl, aih, ail, xrh, xrl, xih = {}, xil = {};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {   // GY[ra][16 ks + 8 lh .. + 7]: chunks of two complex
-        const int c = (8 * ks + 4 * lh + q) ^ (ra & 31);
-        const float4 v = *(const float4*)(gs + ra * OS_GROW + c * 16);
-        short h, l;
-        split16h(v.x * sc.x, h, l); arh[2 * q] = h; arl[2 * q] = l;
-        split16h(v.y * sc.x, h, l); aih[2 * q] = h; ail[2 * q] = l;
-        split16h(v.z * sc.x, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
-        split16h(v.w * sc.x, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
-      }
+      // fragments read as split (k_presplit): block 2 ks + lh of the row, chunks [Re hi][Re lo][Im hi][Im lo]
+      // (complex) or [hi][lo] (real X)
+      auto frag = [](const char* row, int c) { return *(const shortx8*)(row + c * 16); };
+      const char* ga = gs + ra * OS_GROW;
+      const shortx8 arh = frag(ga, (8 * ks + 4 * lh + 0) ^ (ra & 31)), arl = frag(ga, (8 * ks + 4 * lh + 1) ^ (ra & 31));
+      const shortx8 aih = frag(ga, (8 * ks + 4 * lh + 2) ^ (ra & 31)), ail = frag(ga, (8 * ks + 4 * lh + 3) ^ (ra & 31));
+      const char* xa = xs + rb * XROW;
+      shortx8 xrh, xrl, xih = {}, xil = {};
       if (XC) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = (8 * ks + 4 * lh + q) ^ (rb % XCPR);
-          const float4 v = *(const float4*)(xs + rb * XROW + c * 16);
-          short h, l;
-          split16h(v.x * sc.y, h, l); xrh[2 * q] = h; xrl[2 * q] = l;
-          split16h(v.y * sc.y, h, l); xih[2 * q] = h; xil[2 * q] = l;
-          split16h(v.z * sc.y, h, l); xrh[2 * q + 1] = h; xrl[2 * q + 1] = l;
-          split16h(v.w * sc.y, h, l); xih[2 * q + 1] = h; xil[2 * q + 1] = l;
-        }
+        xrh = frag(xa, (8 * ks + 4 * lh + 0) ^ (rb % XCPR));
+        xrl = frag(xa, (8 * ks + 4 * lh + 1) ^ (rb % XCPR));
+        xih = frag(xa, (8 * ks + 4 * lh + 2) ^ (rb % XCPR));
+        xil = frag(xa, (8 * ks + 4 * lh + 3) ^ (rb % XCPR));
       } else {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int c = (4 * ks + 2 * lh + q) ^ (rb % XCPR);
-          const float4 v = *(const float4*)(xs + rb * XROW + c * 16);
-          short h, l;
-          split16h(v.x * sc.y, h, l); xrh[4 * q] = h; xrl[4 * q] = l;
-          split16h(v.y * sc.y, h, l); xrh[4 * q + 1] = h; xrl[4 * q + 1] = l;
-          split16h(v.z * sc.y, h, l); xrh[4 * q + 2] = h; xrl[4 * q + 2] = l;
-          split16h(v.w * sc.y, h, l); xrh[4 * q + 3] = h; xrl[4 * q + 3] = l;
-        }
+        xrh = frag(xa, (4 * ks + 2 * lh + 0) ^ (rb % XCPR));
+        xrl = frag(xa, (4 * ks + 2 * lh + 1) ^ (rb % XCPR));
       }
       // G = GY conj(X)^T: Re = gr xr + gi xi, Im = gi xr - gr xi (real X: xi = 0); every product is
       // symmetric in its operands, so trading them (SW) only transposes the wave's 32 x 32 block
@@ -1168,7 +1201,8 @@ size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   s += align_up((size_t)2 * ch * ceil_div(N, 64) * 4, 256);         // row-norm maxima of GY and X
   s += align_up((size_t)ch * 16, 256);                              // operand scales of the split outer product
   s += align_up((size_t)ch * 8, 256);                               // G scales
-  (void)x_shared;
+  s += align_up((size_t)ch * N * B * 8, 256);                       // GY split (k_presplit)
+  s += align_up((size_t)(x_shared ? 1 : ch) * N * B * 8, 256);      // X split
   return s;
 }
 
@@ -1257,6 +1291,10 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   float4* osc = (float4*)base;
   base += align_up((size_t)ch * 16, 256);
   float2* gsc = (float2*)base;
+  base += align_up((size_t)ch * 8, 256);
+  char* gys = base;                                   // GY split for the outer product
+  base += align_up((size_t)ch * N * B * 8, 256);
+  char* xsp = base;                                   // X split
   const bool use_mfma = inner_mfma_ok(p);
   const bool use_pair = inner_pair_ok(p);   // real F, N % 32 == 0: paired layout when G is split on MFMA
   bool split_outer = false;
@@ -1301,12 +1339,21 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
       const bool vec = B % 4 == 0 && (uintptr_t)gya % 16 == 0 && (uintptr_t)xa % 16 == 0;
       const int key = (x_complex ? 4 : 0) | (vec ? 2 : 0) | (use_mfma ? 1 : 0);
       split_outer = use_mfma && vec && B % 64 == 0;
-      if (split_outer) {   // split-fp16 products on LDS-staged operands
+      if (split_outer) {   // split-fp16 products on LDS-staged operands, split once beforehand
+        const int nx = x_shared ? 1 : nc;
+        const size_t gblk = (size_t)nc * N * (B / 8), xblk = (size_t)nx * N * (B / 8);
+        const unsigned gg = (unsigned)((gblk + 255) / 256 < 8192 ? (gblk + 255) / 256 : 8192);
+        const unsigned gx = (unsigned)((xblk + 255) / 256 < 8192 ? (xblk + 255) / 256 : 8192);
+        k_presplit<true><<<gg, 256, 0, s>>>(gya, gblk, N, B, osc, 0, 0, gys);
+        if (x_complex) k_presplit<true><<<gx, 256, 0, s>>>(xa, xblk, N, B, osc, 1, x_shared, xsp);
+        else k_presplit<false><<<gx, 256, 0, s>>>(xa, xblk, N, B, osc, 1, x_shared, xsp);
+        FG_LAUNCHED("presplit");
+        const cplx64* gyv = (const cplx64*)gys;
         fgfrft_status rc;
-        if (use_pair) rc = x_complex ? outer_split_launch<true, true>(g, s, gya, xa, x_shared, N, B, Gbuf, osc)
-                                     : outer_split_launch<false, true>(g, s, gya, xa, x_shared, N, B, Gbuf, osc);
-        else rc = x_complex ? outer_split_launch<true, false>(g, s, gya, xa, x_shared, N, B, Gbuf, osc)
-                            : outer_split_launch<false, false>(g, s, gya, xa, x_shared, N, B, Gbuf, osc);
+        if (use_pair) rc = x_complex ? outer_split_launch<true, true>(g, s, gyv, xsp, x_shared, N, B, Gbuf, osc)
+                                     : outer_split_launch<false, true>(g, s, gyv, xsp, x_shared, N, B, Gbuf, osc);
+        else rc = x_complex ? outer_split_launch<true, false>(g, s, gyv, xsp, x_shared, N, B, Gbuf, osc)
+                            : outer_split_launch<false, false>(g, s, gyv, xsp, x_shared, N, B, Gbuf, osc);
         if (rc) return rc;
       } else
       switch (key) {

@@ -324,7 +324,8 @@ def test_grad_outer_product_row_scales(xc, B):
     (96, 9, 5, False, False, 64, "fp16x2"),    # a 64-tile cut at N: partial diagonal and edge tiles
     (160, 20, 4, False, True, 128, "fp32"),    # shared signals, two 64-signal chunks
     (64, 64, 3, False, False, 64, "fp16x2"),   # five k-blocks: two passes over the segments
-    (256, 33, 70, True, False, 64, "fp16x2")])  # two chunks of orders
+    (256, 33, 70, True, False, 64, "fp16x2"),   # two chunks of orders
+    (64, 6, 3, True, True, 64, "fp32")])       # complex signals shared by the orders
 def test_grad_paired_layout(N, L, n, xc, shared, B, stacktype):
     """Real F with N % 32 == 0 and B % 64 == 0: G is written in the paired layout (a segment's values
     beside their mirror images) and each stack matrix is read on half of its positions; Proposition 4
