@@ -184,3 +184,56 @@ def test_grid8192_precision_forms_sampled_rows():
         del Q, plan
         torch.cuda.empty_cache()
     _report("grid8192_precision.json", report)
+
+
+@pytest.mark.timeout(900)
+def test_serving_config3_scale_sampled_rows():
+    """The serving workload at its own scale: kNN plans of N = 4096, 2048, 1024 and 256 on GMM points
+    (L = 32, the FP16X2 stack the server plans with), up to K = 32 requests per batch and 1-64 real
+    signals per request, Poisson arrivals at 5k requests/s replayed in real time with graph replay and
+    the per-batch route choice.  Every request's result on sampled rows against the FP64 oracle's rows
+    of Q^alpha, and four requests served alone equal to the same requests in the mix within the parity
+    bar (alone, a request may take the other route than its batch in the mix; within one route the
+    results are bitwise equal, as the small-scale serving tests check)."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import serve
+    t0 = time.time()
+    plans = {6: 4096, 4: 2048, 2: 1024, 0: 256}          # the benchmark's plan ids and sizes
+    announce("serving at scale: building the kNN graphs (N = 4096, 2048, 1024, 256)")
+    Fs = {g: synth.make_config("knn4096", seed=100 + g, N=N, with_signals=False)["F"] for g, N in plans.items()}
+    rng = np.random.default_rng(31)
+    sig = {g: rng.standard_normal((F.shape[0], 64)).astype(np.float32) for g, F in Fs.items()}
+    srv = serve.Server(hbm_budget=64 << 30, K=32, bmax=64, slot_sets=1, use_graphs=True, route="auto")
+    for g, F in Fs.items():
+        srv.add_plan(g, F, 32)
+    trace = serve.poisson_trace(600, 5000.0, list(Fs), 64, seed=21)
+    announce(f"serving at scale: replaying 600 requests [{time.time() - t0:.0f}s]")
+    stats = serve.run_trace(srv, trace, sig, keep_every=1)
+    kept = dict(stats.pop("kept"))
+    announce(f"serving at scale: p50 {stats['p50_ms']:.2f} ms, p99 {stats['p99_ms']:.2f} ms, mean batch "
+             f"{stats['mean_batch']:.2f}, direct share {stats['direct_share']:.2f}")
+    t_arr, gids, alphas, Bs = trace
+    results = {i: f.result() for i, f in kept.items()}
+    assert len(results) == 600
+    # alone: the first request of each plan once more, one at a time
+    firsts = [next(i for i in range(600) if gids[i] == g) for g in plans]
+    for i in firsts:
+        f = srv.submit(gids[i], alphas[i], sig[gids[i]][:, : Bs[i]])
+        srv.drain()
+        assert rel_fro(f.result(), results[i]) <= TOL_FP32, i
+    worst = {}
+    for g, F in Fs.items():
+        N = F.shape[0]
+        idx = [i for i in range(600) if gids[i] == g]
+        P, _, r, _ = O.projectors_symmetric_route(F)
+        assert srv.plans[g].r_minus1 == r
+        rows = _rows(N, 40 + g)[:16]
+        ref = O.sampled_rows(F, P, np.array([alphas[i] for i in idx]), 32, rows)
+        errs = []
+        for k, i in enumerate(idx):
+            X = sig[g][:, : Bs[i]].astype(np.float64)
+            errs.append(rel_fro(results[i][rows], ref[k] @ X))
+        worst[N] = max(errs)
+        announce(f"serving at scale: N={N}, {len(idx)} requests, worst row error {worst[N]:.2e} "
+                 f"[{time.time() - t0:.0f}s]")
+        assert worst[N] <= TOL_FP32, (N, worst[N])
