@@ -581,12 +581,14 @@ struct ApplyRealLayout {
 
 // PRE: X is the pre-split signal block of xsplit_launch (fp16 hi / lo parts in fragment order), so the
 // waves read their signal fragments with plain 16-byte LDS loads instead of each splitting them.
-template <bool PRE>
+// DXO: float32 output Y[a] = R[a] X[a] - sin(pi alpha_a) W Z[a] (the real part of Q[a] (X + j X'[a])
+// when Z[a] = W^T X'[a]: the signal gradient for real signals, with the orders negated).
+template <bool PRE, bool DXO = false>
 __global__ __launch_bounds__(256, 2) void k_apply_real(const float* __restrict__ R, int N, int n_alpha,
                                                        const void* __restrict__ X, int x_shared, int B,
                                                        const float2* __restrict__ xscale,
                                                        const double* __restrict__ alphas, const float* __restrict__ W,
-                                                       int r, const float* __restrict__ Z, cplx64* __restrict__ Y,
+                                                       int r, const float* __restrict__ Z, void* __restrict__ Y,
                                                        int nrb, int ncb) {
   using LY = ApplyRealLayout;
   constexpr int CPR = LY::CPR, RPI = LY::RPI, NS = RS_NS, K2 = RS_K2;
@@ -700,7 +702,8 @@ __global__ __launch_bounds__(256, 2) void k_apply_real(const float* __restrict__
       if (gi < N) {
         float im = 0.f;
         for (int q = 0; q < r; ++q) im = fmaf(W[(size_t)gi * kWCols + q], Za[(size_t)q * B + gb], im);
-        Y[yoff + (size_t)gi * B + gb] = cplx64{acc[c][e] * u, sn * im};
+        if (DXO) ((float*)Y)[yoff + (size_t)gi * B + gb] = acc[c][e] * u - sn * im;
+        else ((cplx64*)Y)[yoff + (size_t)gi * B + gb] = cplx64{acc[c][e] * u, sn * im};
       }
     }
   }
@@ -748,6 +751,64 @@ fgfrft_status apply_real_launch(const Plan* p, const float* R, int n_alpha, cons
   k_apply_real<true><<<(unsigned)nblocks, 256, lds, s>>>(R, N, n_alpha, Xs, x_shared, B, sc, alphas_dev, p->W, r, Z, Y,
                                                          nrb, ncb);
   FG_LAUNCHED("apply (real operator)");
+  return FGFRFT_OK;
+}
+
+// GY [n][N][B] complex64 -> its real and imaginary planes, float32 [n][N][B] each.
+__global__ __launch_bounds__(256) void k_deinterleave(const float2* __restrict__ GY, size_t n, float* __restrict__ re,
+                                                      float* __restrict__ im) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float2 v = GY[i];
+    re[i] = v.x;
+    im[i] = v.y;
+  }
+}
+
+size_t apply_real_dx_ws_bytes(int N, int n_alpha, int B, int r) {
+  const size_t nch = ceil_div(N, CR), plane = (size_t)n_alpha * N * B * sizeof(float);
+  return 2 * align_up(plane, 256) + apply_real_ws_bytes(N, n_alpha, B, 0, r) + colscale_partial_bytes(N, n_alpha, B) +
+         align_up((size_t)n_alpha * nch * B * sizeof(float), 256);
+}
+
+fgfrft_status apply_real_dx_launch(const Plan* p, const float* R, int n_alpha, const double* alphas_dev,
+                                   const cplx64* GY, int B, float* dX, void* ws, hipStream_t s) {
+  const int N = p->N, r = p->form == FGFRFT_FORM_SPLIT ? p->r_minus1 : 0;
+  const int nch = ceil_div(N, CR);
+  const size_t n = (size_t)n_alpha * N * B, plane = align_up(n * sizeof(float), 256);
+  char* w = (char*)ws;
+  float* gr = (float*)w;
+  float* gi = (float*)(w + plane);
+  char* aw = w + 2 * plane;                                  // the real-F apply's own workspace layout
+  float2* sc = (float2*)aw;
+  float* partial = (float*)(aw + align_up((size_t)n_alpha * B * sizeof(float2), 256));
+  float* Z = (float*)((char*)partial + colscale_partial_bytes(N, n_alpha, B));
+  float* pz = (float*)((char*)Z + align_up((size_t)n_alpha * kWCols * B * sizeof(float), 256));
+  short* Xs = (short*)((char*)pz + align_up((size_t)n_alpha * nch * r * B * sizeof(float), 256));
+  char* extra = aw + apply_real_ws_bytes(N, n_alpha, B, 0, r);
+  float* partial_im = (float*)extra;                         // column maxima of the imaginary plane (unused)
+  const unsigned g = (unsigned)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+  k_deinterleave<<<g, 256, 0, s>>>((const float2*)GY, n, gr, gi);
+  // scales of the real plane (the apply's signals), then W^T of the imaginary plane
+  k_colmax_wtx<<<dim3(ceil_div(B, 64) * n_alpha, nch), 256, 0, s>>>(gr, N, B, p->W, 0, partial, pz);
+  k_colscale<<<ceil_div(n_alpha * B, 256), 256, 0, s>>>(partial, nch, B, n_alpha, sc);
+  if (r > 0) {
+    k_colmax_wtx<<<dim3(ceil_div(B, 64) * n_alpha, nch), 256, 0, s>>>(gi, N, B, p->W, r, partial_im, pz);
+    k_zsum<<<(unsigned)(((size_t)n_alpha * r * B + 255) / 256), 256, 0, s>>>(pz, nch, r, B, n_alpha, Z);
+  }
+  FG_LAUNCHED("gradient planes, scales and W^T");
+  fgfrft_status rc = xsplit_launch(gr, B, B, N, n_alpha, (size_t)N * B, sc, B, Xs, s);
+  if (rc) return rc;
+  const int nrb = ceil_div(N, M2), ncb = B / 64;
+  const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
+  if (nblocks > 0x7fffffff) {
+    set_error("apply grid too large");
+    return FGFRFT_EUNSUPPORTED;
+  }
+  constexpr int lds = RS_NS * ApplyRealLayout::SB;
+  FG_HIP(raise_lds_limit((const void*)k_apply_real<true, true>, lds));
+  k_apply_real<true, true><<<(unsigned)nblocks, 256, lds, s>>>(R, N, n_alpha, Xs, 0, B, sc, alphas_dev, p->W, r, Z, dX,
+                                                               nrb, ncb);
+  FG_LAUNCHED("signal gradient (real operator)");
   return FGFRFT_OK;
 }
 

@@ -1203,6 +1203,7 @@ size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
   s += align_up((size_t)ch * 8, 256);                               // G scales
   s += align_up((size_t)ch * N * B * 8, 256);                       // GY split (k_presplit)
   s += align_up((size_t)(x_shared ? 1 : ch) * N * B * 8, 256);      // X split
+  if (apply_real_supported(p, 0, B)) s += apply_real_dx_ws_bytes(N, ch, B, p->r_minus1);   // real-F dX
   return s;
 }
 
@@ -1295,6 +1296,9 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   char* gys = base;                                   // GY split for the outer product
   base += align_up((size_t)ch * N * B * 8, 256);
   char* xsp = base;                                   // X split
+  base += align_up((size_t)(x_shared ? 1 : ch) * N * B * 8, 256);
+  void* rdxws = base;                                 // real-F dX (apply_real_dx_launch)
+  const bool realdx = !x_complex && apply_real_supported(p, 0, B);
   const bool use_mfma = inner_mfma_ok(p);
   const bool use_pair = inner_pair_ok(p);   // real F, N % 32 == 0: paired layout when G is split on MFMA
   bool split_outer = false;
@@ -1311,10 +1315,18 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
     const int nc = n_alpha - a0 < ch ? n_alpha - a0 : ch;
     // ---- dX = Q(-alpha) GY
     if (dX) {
-      fgfrft_status rc = update_launch(p, neg_dev + a0, nc, Gbuf, uws, s);
-      if (rc) return rc;
       void* dst = x_shared ? dXc : (void*)((char*)dX + (size_t)a0 * NB * (x_complex ? 8 : 4));
-      rc = apply_launch(Gbuf, N, nc, 0, gy + (size_t)a0 * NB, 1, 0, B, dst, x_complex ? 0 : 1, aws, s);
+      fgfrft_status rc;
+      if (realdx) {   // real F, real X: R = Re Q(-alpha) only, the rank-r imaginary part from W
+        rc = update_launch(p, neg_dev + a0, nc, Gbuf, uws, s, true);
+        if (rc) return rc;
+        rc = apply_real_dx_launch(p, (const float*)Gbuf, nc, neg_dev + a0, gy + (size_t)a0 * NB, B, (float*)dst, rdxws,
+                                  s);
+      } else {
+        rc = update_launch(p, neg_dev + a0, nc, Gbuf, uws, s);
+        if (rc) return rc;
+        rc = apply_launch(Gbuf, N, nc, 0, gy + (size_t)a0 * NB, 1, 0, B, dst, x_complex ? 0 : 1, aws, s);
+      }
       if (rc) return rc;
       if (x_shared) {
         const int g = (int)((NB + 255) / 256 < 4096 ? (NB + 255) / 256 : 4096);

@@ -142,6 +142,12 @@ size_t apply_real_ws_bytes(int N, int n_alpha, int B, int x_shared, int r);
 bool apply_real_supported(const Plan* p, int x_complex, int B);
 fgfrft_status apply_real_launch(const Plan* p, const float* R, int n_alpha, const double* alphas_dev, const float* X,
                                 int x_shared, int B, cplx64* Y, void* ws, hipStream_t s);
+// Signal gradient through the real-F form (apply.hip): dX[a] = Re(Q(alphas[a]) GY[a]) = R[a] Re GY[a] -
+// sin(pi alphas[a]) W (W^T Im GY[a]) as float32 [n_alpha][N][B], with R = Re Q(alphas[a]) from
+// update_launch(..., real_plane = true); the same shape conditions as apply_real_supported.
+size_t apply_real_dx_ws_bytes(int N, int n_alpha, int B, int r);
+fgfrft_status apply_real_dx_launch(const Plan* p, const float* R, int n_alpha, const double* alphas_dev,
+                                   const cplx64* GY, int B, float* dX, void* ws, hipStream_t s);
 
 // Gradient (grad.hip)
 size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared);
