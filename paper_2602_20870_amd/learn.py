@@ -4,6 +4,8 @@
   layer (the cascaded-network experiment of Sec. IV, learning setup).
 * ``FractionalMaskDenoiser``: Q_L^{-alpha} diag(h) Q_L^{alpha} y with a learnable order and a
   learnable diagonal mask h in the fractional domain (the denoising model of Sec. IV).
+* ``PointCloudDenoiser``: the same mask pipeline with one learnable order and mask per channel
+  between a linear lift of the point coordinates to C channels and a projection back.
 
 Every forward and backward step runs through the library (update + apply on the GPU, gradient
 through ``fgfrft_grad``); torch only holds the parameters and the optimizer state.
@@ -47,6 +49,31 @@ class FractionalMaskDenoiser(torch.nn.Module):
         Z = fgfrft(y.contiguous(), self.alpha, self.plan)[0]
         W = (self.h * Z).contiguous()
         return fgfrft(W, -self.alpha, self.plan)[0]
+
+
+class PointCloudDenoiser(torch.nn.Module):
+    """Y_hat = proj(Re Q^{-alpha_c} diag(h_c) Q^{alpha_c} lift(Y)_c) for noisy point coordinates
+    Y [clouds, N, c_in] (float32, on the plan's device): a c_in -> C linear lift, per channel c a
+    learnable order alpha_c and mask h_c in the fractional domain, and a C -> c_in projection of the
+    real part.  Channel c takes the clouds as its signals, so each transform is one library call for
+    all C orders with `clouds` signals per order, forward and backward."""
+
+    def __init__(self, plan: Plan, channels: int = 64, c_in: int = 3, alpha_init: float = 0.5, seed: int = 0):
+        super().__init__()
+        g = torch.Generator().manual_seed(seed)
+        dev = plan.device
+        self.plan = plan
+        self.W_in = torch.nn.Parameter((torch.randn(c_in, channels, generator=g) / c_in ** 0.5).to(dev))
+        self.W_out = torch.nn.Parameter((torch.randn(channels, c_in, generator=g) / channels ** 0.5).to(dev))
+        spread = torch.linspace(0.5, 1.5, channels, dtype=torch.float64)
+        self.alpha = torch.nn.Parameter(float(alpha_init) * spread)
+        self.h = torch.nn.Parameter(torch.ones(channels, plan.N, 1, dtype=torch.float32, device=dev))
+
+    def forward(self, Y: torch.Tensor) -> torch.Tensor:
+        X = torch.matmul(Y, self.W_in).permute(2, 1, 0).contiguous()      # [C, N, clouds]
+        Z = fgfrft(X, self.alpha, self.plan)
+        Zi = fgfrft((self.h * Z).contiguous(), -self.alpha, self.plan)
+        return torch.matmul(Zi.real.permute(2, 1, 0), self.W_out)         # [clouds, N, c_in]
 
 
 def train(model: torch.nn.Module, loss_fn, steps: int, lr: float = 0.01, params=None) -> list[float]:

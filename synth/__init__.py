@@ -235,6 +235,18 @@ def _graph_F(name: str, rng: np.random.Generator, N: int | None = None) -> np.nd
     raise KeyError(name)
 
 
+def point_cloud_denoising(seed: int = 0, N: int = 2048, clouds: int = 64, noise: float = 0.05) -> dict:
+    """Data of the differentiable workload: N points uniform on the unit sphere plus N(0, 0.02^2)
+    jitter, the graph of ``sphere2048`` (kNN k = 10, combinatorial Laplacian, F = U^T, the same F as
+    ``make_config("sphere2048", seed)``), the clean coordinates as a 3-channel graph signal
+    [N, 3], and `clouds` noisy copies [clouds, N, 3] with N(0, noise^2) added per coordinate."""
+    g_graph, _, g_sig = streams(seed, 3)
+    pts = sphere_points(N, g_graph)
+    F = gft_from_shift(laplacian(knn_adjacency(pts, 10)))
+    noisy = pts[None, :, :] + noise * g_sig.standard_normal((clouds, N, 3))
+    return dict(F=F, clean=pts, noisy=noisy, L=CONFIGS["sphere2048"]["L"], N=N)
+
+
 def make_config(name: str, seed: int = 0, n_alpha: int | None = None,
                 B: int | None = None, N: int | None = None,
                 with_signals: bool = True) -> dict:
