@@ -17,6 +17,7 @@
 // kernel with one thread per output and FP64 accumulation.
 #include "internal.h"
 #include <math.h>
+#include <type_traits>
 
 namespace fgfrft {
 
@@ -144,9 +145,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict_
 
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   const uint32_t aoff = (uint32_t)((((size_t)(lane >> 3)) * N + 4 * ((lane & 7) ^ (lane >> 3))) * 4);
-  auto issue = [&](int it) {
+  auto issue = [&](int it, int jc, int t) {   // stage it = (chunk jc, term t)
     char* st = sm + (it % NS) * DSB;
-    const int jc = cfirst + it / T1, t = it % T1;
     const float* A = t < L ? stack + (size_t)t * N * N : P;
 #pragma unroll
     for (int q = 0; q < DAB / 4096; ++q) {
@@ -165,16 +165,26 @@ __global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict_
 
   float sum_pos[2][16] = {}, sum_im[2][16] = {}, sum_neg[2][16] = {};
   const int r = 32 * wave + l32;
-  issue(0);
+  // stage counters advance incrementally: (jc, t) of the stage consumed, (jn, tn) of the one issued next
+  int jc = cfirst, t = 0, jn = cfirst, tn = 0;
+  auto advance = [&](int& j, int& k) { if (++k == T1) { k = 0; ++j; } };
+  issue(0, jn, tn);
+  advance(jn, tn);
   for (int it = 0; it < nst; ++it) {
     // this wave's loads of stage it have landed and its LDS reads of stage it - 1 are done; after the
     // barrier that holds for every wave, so stage it + 1 may refill the other slot
     __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
     barrier_nofence();
-    if (it + 1 < nst) issue(it + 1);
+    if (it + 1 < nst) {
+      issue(it + 1, jn, tn);
+      advance(jn, tn);
+    }
     const char* st = sm + (it % NS) * DSB;
-    const int jc = cfirst + it / T1, t = it % T1;
-    const bool isP = t == L;
+    // the stage's work; for the pair-stored stacks compiled separately for the projector stage and the
+    // stack terms (no per-chunk branches in the fragment assembly), for the FP32 stack one body with a
+    // run-time test (a second copy would not fit the register budget)
+    auto stage = [&](auto isp_tag, bool isp_rt) {
+    const bool isP = decltype(isp_tag)::value || isp_rt;
     // ---- positive: S_t[I, J] X[J]
     floatx16 acc[2] = {};
 #pragma unroll
@@ -291,6 +301,11 @@ __global__ __launch_bounds__(256, 2) void k_direct_pair(const float* __restrict_
 #pragma unroll
         for (int e = 0; e < 16; ++e) sum_neg[c][e] = 0.f;
     }
+    };
+    if (SM == 0) stage(std::false_type{}, t == L);
+    else if (t == L) stage(std::true_type{}, true);
+    else stage(std::false_type{}, false);
+    advance(jc, t);
   }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
