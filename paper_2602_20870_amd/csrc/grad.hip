@@ -879,21 +879,24 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_mfma(const void* __rest
   }
 }
 
-// Real F, G in the paired layout: stage s is segment s (its U and Lt, 2 x 256 bytes per order) and the
+// G in the paired layout: stage s is segment s (its U and Lt, 2 x 256 bytes per order) and the
 // segment's 32 positions of the 2L stack matrices, P and the identity, so each stack matrix is read on
 // the segments only (about half of its positions).  The contraction per stage runs over 64 positions:
 // U against the column's own row, then Lt against its partner row (M_n <-> M_n^H; P, the identity,
-// the copies and the zero rows pair with themselves).  Ring, waves, splitting and FP64 flushes (every
-// 256 contracted positions) as in k_inner_mfma; the workgroups take contiguous ranges of segments.
+// the copies and the zero rows pair with themselves).  For complex F the partner entries enter
+// conjugated (M_n(j, i) = conj(M_n^H(i, j)), P Hermitian), so the Lt half accumulates conj(g) conj(b):
+// its products with the imaginary parts of b change sign.  Ring, waves, splitting and FP64 flushes
+// (every 256 contracted positions) as in k_inner_mfma; the workgroups take contiguous ranges of segments.
 constexpr int IP_GB = IM_NA * PAIR_SEG_BYTES;   // G bytes of one stage
 constexpr int IP_FL = IM_FLPOS / 64;            // stages per FP32 accumulation
 
-template <int NS, int SM>
+template <bool CPLX, int NS, int SM>
 __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_pair(const void* __restrict__ stack, const void* __restrict__ Pm,
                                                              int N, int L, const char* __restrict__ G, int n_c,
                                                              const float2* __restrict__ gsc, int spw, int kb0,
                                                              double* __restrict__ partial) {
-  using LY = InnerLayout<false, 32>;
+  using LY = InnerLayout<CPLX, 32>;
+  constexpr int EB = LY::EB;
   extern __shared__ __align__(16) char smc[];
   char* sm = smc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -940,15 +943,17 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_pair(const void* __rest
     for (int i = wv; i < nbi; i += IM_NW) {
       const int k = i * LY::SRPI + lane / LY::SCPR, sl = lane % LY::SCPR;
       const int c = sl ^ (k % LY::SCPR);
-      const char* src = k < 2 * L ? (const char*)stack + (size_t)k * NN * 4 : (const char*)Pm;
-      lds_dma16(src + (p0 + (size_t)c * 4) * 4, __builtin_amdgcn_readfirstlane(lds_addr(buf + IP_GB + i * 1024)));
+      const char* src = k < 2 * L ? (const char*)stack + (size_t)k * NN * EB : (const char*)Pm;
+      lds_dma16(src + (p0 + (size_t)c * (16 / EB)) * EB,
+                __builtin_amdgcn_readfirstlane(lds_addr(buf + IP_GB + i * 1024)));
     }
     // identity row RD
     for (int e = tid; e < 32; e += 64 * IM_NW) {
       const size_t p = p0 + e;
-      const int c = (e >> 2) ^ (RD % LY::SCPR);
-      float* dst = (float*)(buf + IP_GB + (size_t)RD * LY::SROW + c * 16 + (e & 3) * 4);
+      const int c = (e * EB / 16) ^ (RD % LY::SCPR);
+      float* dst = (float*)(buf + IP_GB + (size_t)RD * LY::SROW + c * 16 + (e * EB) % 16);
       dst[0] = (p % (size_t)(N + 1)) == 0 ? 1.f : 0.f;
+      if (CPLX) dst[1] = 0.f;
     }
     if (++cjb == nb) { ++ci; cjb = ci >> 5; }
   };
@@ -974,40 +979,73 @@ __global__ __launch_bounds__(64 * IM_NW, 1) void k_inner_pair(const void* __rest
     if (kact) {
 #pragma unroll
       for (int vk = 0; vk < 4; ++vk) {
+        const bool lt = vk >= 2;   // the Lt half, against the partner rows
         const char* grow = buf + (size_t)r * PAIR_SEG_BYTES;
         const int sw = r & 31;
         const shortx8 arh = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 0) ^ sw) * 16);
         const shortx8 arl = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 1) ^ sw) * 16);
         const shortx8 aih = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 2) ^ sw) * 16);
         const shortx8 ail = *(const shortx8*)(grow + ((8 * vk + 4 * lh + 3) ^ sw) * 16);
-        const int row = vk < 2 ? k : kpart, kk = vk & 1;
+        const int row = lt ? kpart : k, kk = vk & 1;
         const char* brow = buf + IP_GB + (size_t)row * LY::SROW;
-        shortx8 brh, brl;
+        shortx8 brh, brl, bih = {}, bil = {};
+        if (CPLX) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {   // four reals per chunk
-          const int c = (4 * kk + 2 * lh + q) ^ (row % LY::SCPR);
-          const float4 v = *(const float4*)(brow + c * 16);
-          if (pairs) {
-            const uint4 u = __builtin_bit_cast(uint4, v);
-            brh[4 * q] = (short)(u.x & 0xffff); brl[4 * q] = (short)(u.x >> 16);
-            brh[4 * q + 1] = (short)(u.y & 0xffff); brl[4 * q + 1] = (short)(u.y >> 16);
-            brh[4 * q + 2] = (short)(u.z & 0xffff); brl[4 * q + 2] = (short)(u.z >> 16);
-            brh[4 * q + 3] = (short)(u.w & 0xffff); brl[4 * q + 3] = (short)(u.w >> 16);
-          } else {
-            short h, l;
-            split16h(v.x * kStackScale, h, l); brh[4 * q] = h; brl[4 * q] = l;
-            split16h(v.y * kStackScale, h, l); brh[4 * q + 1] = h; brl[4 * q + 1] = l;
-            split16h(v.z * kStackScale, h, l); brh[4 * q + 2] = h; brl[4 * q + 2] = l;
-            split16h(v.w * kStackScale, h, l); brh[4 * q + 3] = h; brl[4 * q + 3] = l;
+          for (int q = 0; q < 4; ++q) {   // two complex per chunk
+            const int c = (8 * kk + 4 * lh + q) ^ (row % LY::SCPR);
+            const float4 v = *(const float4*)(brow + c * 16);
+            if (pairs) {
+              const uint4 u = __builtin_bit_cast(uint4, v);
+              brh[2 * q] = (short)(u.x & 0xffff); brl[2 * q] = (short)(u.x >> 16);
+              bih[2 * q] = (short)(u.y & 0xffff); bil[2 * q] = (short)(u.y >> 16);
+              brh[2 * q + 1] = (short)(u.z & 0xffff); brl[2 * q + 1] = (short)(u.z >> 16);
+              bih[2 * q + 1] = (short)(u.w & 0xffff); bil[2 * q + 1] = (short)(u.w >> 16);
+            } else {
+              short h, l;
+              split16h(v.x * kStackScale, h, l); brh[2 * q] = h; brl[2 * q] = l;
+              split16h(v.y * kStackScale, h, l); bih[2 * q] = h; bil[2 * q] = l;
+              split16h(v.z * kStackScale, h, l); brh[2 * q + 1] = h; brl[2 * q + 1] = l;
+              split16h(v.w * kStackScale, h, l); bih[2 * q + 1] = h; bil[2 * q + 1] = l;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {   // four reals per chunk
+            const int c = (4 * kk + 2 * lh + q) ^ (row % LY::SCPR);
+            const float4 v = *(const float4*)(brow + c * 16);
+            if (pairs) {
+              const uint4 u = __builtin_bit_cast(uint4, v);
+              brh[4 * q] = (short)(u.x & 0xffff); brl[4 * q] = (short)(u.x >> 16);
+              brh[4 * q + 1] = (short)(u.y & 0xffff); brl[4 * q + 1] = (short)(u.y >> 16);
+              brh[4 * q + 2] = (short)(u.z & 0xffff); brl[4 * q + 2] = (short)(u.z >> 16);
+              brh[4 * q + 3] = (short)(u.w & 0xffff); brl[4 * q + 3] = (short)(u.w >> 16);
+            } else {
+              short h, l;
+              split16h(v.x * kStackScale, h, l); brh[4 * q] = h; brl[4 * q] = l;
+              split16h(v.y * kStackScale, h, l); brh[4 * q + 1] = h; brl[4 * q + 1] = l;
+              split16h(v.z * kStackScale, h, l); brh[4 * q + 2] = h; brl[4 * q + 2] = l;
+              split16h(v.w * kStackScale, h, l); brh[4 * q + 3] = h; brl[4 * q + 3] = l;
+            }
           }
         }
-        // conj(g) b with real b: Re = gr b, Im = -gi b (the sign is applied at the end)
+        // conj(g) b: Re = gr br + gi bi, Im = gr bi - gi br; conj(g) conj(b) (Lt half, complex F):
+        // Re = gr br - gi bi, Im = -(gr bi + gi br).  fim accumulates the negated imaginary part.
         fre = mma16(arh, brh, fre);
         fre = mma16(arh, brl, fre);
         fre = mma16(arl, brh, fre);
         fim = mma16(aih, brh, fim);
         fim = mma16(aih, brl, fim);
         fim = mma16(ail, brh, fim);
+        if (CPLX) {
+          const shortx8 sih = lt ? aih ^ (short)0x8000 : aih, sil = lt ? ail ^ (short)0x8000 : ail;
+          const shortx8 srh = lt ? arh : arh ^ (short)0x8000, srl = lt ? arl : arl ^ (short)0x8000;
+          fre = mma16(sih, bih, fre);
+          fre = mma16(sih, bil, fre);
+          fre = mma16(sil, bih, fre);
+          fim = mma16(srh, bih, fim);
+          fim = mma16(srh, bil, fim);
+          fim = mma16(srl, bih, fim);
+        }
       }
     }
     if (++since == IP_FL || st + 1 == st1) {
@@ -1139,14 +1177,17 @@ static bool inner_mfma_ok(const Plan* p) {
 }
 static int inner_mfma_wgs() { return 256; }
 
-// paired inner products (real F, N % 32 == 0): stage bytes 32 KB of G + the stack rows, ring of up to 3
+// paired inner products (N % 32 == 0): stage bytes 32 KB of G + the stack rows, ring of up to 3
+static size_t pair_stage_bytes(const Plan* p) {
+  return p->cplx ? IP_GB + (size_t)InnerLayout<true, 32>::kp2(p->L) * InnerLayout<true, 32>::SROW
+                 : IP_GB + (size_t)InnerLayout<false, 32>::kp2(p->L) * InnerLayout<false, 32>::SROW;
+}
 static int pair_stages_fit(const Plan* p) {
-  const size_t sb = IP_GB + (size_t)InnerLayout<false, 32>::kp2(p->L) * InnerLayout<false, 32>::SROW;
-  const int ns = (int)((160 * 1024) / sb);
+  const int ns = (int)((160 * 1024) / pair_stage_bytes(p));
   return ns > 3 ? 3 : ns;
 }
 static bool inner_pair_ok(const Plan* p) {
-  return !p->cplx && p->N % 32 == 0 && inner_mfma_ok(p) && pair_stages_fit(p) >= 2 &&
+  return p->N % 32 == 0 && inner_mfma_ok(p) && pair_stages_fit(p) >= 2 &&
          (p->stacktype == FGFRFT_STACK_FP32 || p->stacktype == FGFRFT_STACK_FP16X2);
 }
 static int inner_pair_grid(const Plan* p) {
@@ -1161,27 +1202,35 @@ static size_t g_order_bytes(const Plan* p) {
   return pair > plain ? pair : plain;
 }
 
-template <int NS, int SM>
+template <bool CPLX, int NS, int SM>
 static fgfrft_status inner_pair_launch_ns(const Plan* p, const char* G, int nc, const float2* gsc, double* partial,
                                           hipStream_t s) {
-  using LY = InnerLayout<false, 32>;
+  using LY = InnerLayout<CPLX, 32>;
   const int nseg = pair_nseg(p->N);
   const int nwg = inner_pair_grid(p), spw = ceil_div(nseg, nwg);
-  const int lds = (int)(NS * (IP_GB + (size_t)LY::kp2(p->L) * LY::SROW));
+  const int lds = (int)(NS * pair_stage_bytes(p));
   const int KB = LY::kp2(p->L) / 32;
-  auto kern = k_inner_pair<NS, SM>;
+  auto kern = k_inner_pair<CPLX, NS, SM>;
   FG_HIP(raise_lds_limit((const void*)kern, lds));
   for (int kb0 = 0; kb0 < KB; kb0 += 4)
     kern<<<nwg, 64 * IM_NW, lds, s>>>(p->stack, p->P, p->N, p->L, G, nc, gsc, spw, kb0, partial);
   FG_LAUNCHED("inner_pair");
   return FGFRFT_OK;
 }
-static fgfrft_status inner_pair_launch(const Plan* p, const char* G, int nc, const float2* gsc, double* partial,
-                                       hipStream_t s) {
+template <bool CPLX>
+static fgfrft_status inner_pair_launch_c(const Plan* p, const char* G, int nc, const float2* gsc, double* partial,
+                                         hipStream_t s) {
   const bool f16 = p->stacktype == FGFRFT_STACK_FP16X2;
   if (pair_stages_fit(p) >= 3)
-    return f16 ? inner_pair_launch_ns<3, 2>(p, G, nc, gsc, partial, s) : inner_pair_launch_ns<3, 0>(p, G, nc, gsc, partial, s);
-  return f16 ? inner_pair_launch_ns<2, 2>(p, G, nc, gsc, partial, s) : inner_pair_launch_ns<2, 0>(p, G, nc, gsc, partial, s);
+    return f16 ? inner_pair_launch_ns<CPLX, 3, 2>(p, G, nc, gsc, partial, s)
+               : inner_pair_launch_ns<CPLX, 3, 0>(p, G, nc, gsc, partial, s);
+  return f16 ? inner_pair_launch_ns<CPLX, 2, 2>(p, G, nc, gsc, partial, s)
+             : inner_pair_launch_ns<CPLX, 2, 0>(p, G, nc, gsc, partial, s);
+}
+static fgfrft_status inner_pair_launch(const Plan* p, const char* G, int nc, const float2* gsc, double* partial,
+                                       hipStream_t s) {
+  return p->cplx ? inner_pair_launch_c<true>(p, G, nc, gsc, partial, s)
+                 : inner_pair_launch_c<false>(p, G, nc, gsc, partial, s);
 }
 
 size_t grad_ws_bytes(const Plan* p, int n_alpha, int B, int x_shared) {
@@ -1300,7 +1349,7 @@ fgfrft_status grad_run(const Plan* p, const double* alphas, int n_alpha, const v
   void* rdxws = base;                                 // real-F dX (apply_real_dx_launch)
   const bool realdx = !x_complex && apply_real_supported(p, 0, B);
   const bool use_mfma = inner_mfma_ok(p);
-  const bool use_pair = inner_pair_ok(p);   // real F, N % 32 == 0: paired layout when G is split on MFMA
+  const bool use_pair = inner_pair_ok(p);   // N % 32 == 0: paired layout when G is split on MFMA
   bool split_outer = false;
 
   const size_t lds = inner_lds(p);

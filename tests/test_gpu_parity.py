@@ -354,6 +354,41 @@ def test_grad_paired_layout(N, L, n, xc, shared, B, stacktype):
     assert rel_fro(dX, dX_ref) <= TOL_FP32
 
 
+@pytest.mark.parametrize("N,L,n,xc,shared,B,stacktype", [
+    (96, 12, 5, False, False, 64, "fp32"),     # Haar with one eigenvalue at -1, real signals
+    (64, 40, 3, True, False, 64, "fp16x2"),    # two passes over the segments (four k-blocks of 32 + ...)
+    (128, 20, 4, True, True, 128, "fp32")])    # the unitary DFT (r_-1 = 32), shared complex signals
+def test_grad_paired_layout_complex_F(N, L, n, xc, shared, B, stacktype):
+    """Complex F in the paired layout: the partner rows enter conjugated (M_n(j, i) = conj(M_n^H(i, j)),
+    P Hermitian), Proposition 4 against the oracle."""
+    torch = torch_cuda()
+    announce(f"grad paired layout complex F N={N} L={L} n={n} xc={xc} shared={shared} B={B} stack {stacktype}")
+    rng = np.random.default_rng(3 * N + L)
+    if N == 128:
+        F = synth.dft_matrix(N)
+    else:
+        V = synth.haar_unitary(N, rng)
+        th = rng.uniform(-np.pi * 0.9, np.pi * 0.9, N)
+        th[5] = np.pi
+        F = (V * np.exp(1j * th)[None, :]) @ V.conj().T
+    alphas = rng.uniform(-2.0, 2.0, n)
+    alphas[0] = 1.0
+    shape = (N, B) if shared else (n, N, B)
+    X = synth.complex_signals(shape, rng) if xc else synth.real_signals(shape, rng)
+    X = X.astype(np.complex64 if xc else np.float32)
+    GY = synth.complex_signals((n, N, B), rng).astype(np.complex64)
+    plan = _gpu_plan(torch, F, L, stacktype)
+    ref = O.Plan(F, L)
+    Xd = X.astype(np.complex128) if xc else X.astype(np.float64)
+    Xs = np.broadcast_to(Xd, (n, N, B)) if shared else Xd
+    dal_ref, dX_ref = O.grad(ref.P, ref.M, alphas, Xs, GY.astype(np.complex128), x_real=not xc)
+    dal, dX = plan.grad(alphas, torch.from_numpy(X).cuda(), torch.from_numpy(GY).cuda())
+    assert np.max(np.abs(dal - dal_ref)) <= TOL_FP32 * np.max(np.abs(dal_ref)), (dal, dal_ref)
+    dX = dX.cpu().numpy()
+    dX_ref = dX_ref.sum(axis=0) if shared else dX_ref
+    assert rel_fro(dX, dX_ref) <= TOL_FP32
+
+
 @pytest.mark.parametrize("N,L,n,cplxF", [(50, 9, 5, False),    # N % 8 != 0: per-tile inner products
                                          # the same kernel after it, needing more LDS than 64 KB (69 KB,
                                          # 90 KB): the limit set by the first call must be raised
