@@ -200,7 +200,9 @@ FGFRFT_API fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_a
                                                void* stream);
 
 /* Workspace bytes for fgfrft_apply: operators for `chunk` orders at a time
- * plus the update and apply workspaces.  chunk <= 0 selects min(n_alpha, 16).
+ * plus the update and apply workspaces.  chunk <= 0 selects min(n_alpha, c) with c the number of
+ * orders whose operators fit about 4 GiB (N^2 * 8 bytes each, N^2 * 4 on the real-F route),
+ * clamped to [16, 256]: every update launch reads the whole stack, so fewer, larger launches.
  * Depends on x_complex: the real-F route below keeps 4 bytes per operator
  * entry instead of 8. */
 FGFRFT_API size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_complex,

@@ -44,3 +44,59 @@ class FGFRFTFunction(torch.autograd.Function):
 def fgfrft(X: torch.Tensor, alpha: torch.Tensor, plan: Plan) -> torch.Tensor:
     """Differentiable Y[a] = Q_L^{alpha_a} X[a]."""
     return FGFRFTFunction.apply(X, alpha, plan)
+
+
+class FractionalFilterFunction(torch.autograd.Function):
+    """Y = FractionalFilterFunction.apply(X, alpha, h, plan): per order a,
+    Y[a] = Q^{-alpha_a} diag(h[a]) Q^{alpha_a} X[a], a filter h in the fractional domain.
+
+    The operators of both orders are formed once in the forward pass and kept for the backward one,
+    where every product is again a plain apply (Q^{-a} = (Q^{a})^H, Proposition 3):
+      GM = Q^{a} GY,  dh = Re sum_b conj(GM) Z,  GZ = h GM,  dX = Q^{-a} GZ,
+      dalpha = Re<GZ X^H, dQ/da (a)> - Re<GY M^H, dQ/da (-a)>   (Proposition 4, the library's
+    order gradient without its signal part), with Z = Q^{a} X and M = h Z.
+    X: float32 or complex64 [n, N, B] or shared [N, B]; h: float32, broadcastable to [n, N, B]
+    (e.g. [n, N, 1] or [N, 1]); returns complex64 [n, N, B].
+    """
+
+    @staticmethod
+    def forward(ctx, X: torch.Tensor, alpha: torch.Tensor, h: torch.Tensor, plan: Plan) -> torch.Tensor:
+        from .ops import apply_operator
+        a = alpha.detach().to("cpu", torch.float64).reshape(-1).numpy()
+        Xc = X.detach().contiguous()
+        Qp = plan.update(a)
+        Qm = plan.update(-a)
+        Z = apply_operator(Qp, Xc)
+        M = (h.detach() * Z).contiguous()
+        Y = apply_operator(Qm, M)
+        ctx.plan = plan
+        ctx.save_for_backward(Xc, alpha, h, Qp, Qm, Z, M)
+        return Y
+
+    @staticmethod
+    def backward(ctx, GY: torch.Tensor):
+        from .ops import apply_operator
+        X, alpha, h, Qp, Qm, Z, M = ctx.saved_tensors
+        plan: Plan = ctx.plan
+        a = alpha.detach().to("cpu", torch.float64).reshape(-1).numpy()
+        gy = GY.to(torch.complex64).contiguous()
+        GM = apply_operator(Qp, gy)
+        GZ = (h.detach() * GM).contiguous()
+        dX = dh = d_alpha = None
+        if ctx.needs_input_grad[0]:
+            gx = apply_operator(Qm, GZ)
+            if not X.is_complex():
+                gx = gx.real
+            dX = gx.sum(dim=0) if X.dim() == 2 else gx
+        if ctx.needs_input_grad[2]:
+            dh = (GM.conj() * Z).real.sum_to_size(h.shape)
+        if ctx.needs_input_grad[1]:
+            g1, _ = plan.grad(a, X, GZ, want_dX=False)
+            g2, _ = plan.grad(-a, M, gy, want_dX=False)
+            d_alpha = torch.from_numpy(g1 - g2).to(device=alpha.device, dtype=alpha.dtype).reshape(alpha.shape)
+        return dX, d_alpha, dh, None
+
+
+def fractional_filter(X: torch.Tensor, alpha: torch.Tensor, h: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable Y[a] = Q_L^{-alpha_a} diag(h[a]) Q_L^{alpha_a} X[a]."""
+    return FractionalFilterFunction.apply(X, alpha, h, plan)

@@ -209,15 +209,21 @@ fgfrft_status fgfrft_apply_operator(const void* Q_dev, int N, int n_alpha, int a
                       y_real ? 1 : 0, ws_dev, (hipStream_t)stream);
 }
 
-static int apply_chunk(int n_alpha, int chunk) {
-  if (chunk <= 0) chunk = 16;
+// Orders per update launch of fgfrft_apply.  Every launch reads the whole stack, so the default takes as
+// many orders as fit about 4 GiB of operators (at least 16, at most 256).
+static int apply_chunk(const Plan* p, bool realF, int n_alpha, int chunk) {
+  if (chunk <= 0) {
+    const size_t per = (size_t)p->N * p->N * (realF ? 4 : 8);
+    const size_t fit = ((size_t)4 << 30) / per;
+    chunk = fit < 16 ? 16 : (fit > 256 ? 256 : (int)fit);
+  }
   return chunk < n_alpha ? chunk : n_alpha;
 }
 
 size_t fgfrft_apply_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_complex, int x_shared, int chunk) {
   if (!plan || n_alpha < 1 || B < 1) return 0;
   const Plan* p = (const Plan*)plan;
-  const int ch = apply_chunk(n_alpha, chunk);
+  const int ch = apply_chunk(p, apply_real_supported(p, x_complex, B), n_alpha, chunk);
   if (apply_real_supported(p, x_complex, B))   // real F, real X: R = Re Q (4 bytes per entry)
     return align_up((size_t)n_alpha * 8, 256) + align_up((size_t)ch * p->N * p->N * 4, 256) + update_ws_bytes(p, ch) +
            apply_real_ws_bytes(p->N, ch, B, x_shared, p->r_minus1);
@@ -237,7 +243,7 @@ fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha
     set_error("X_dev, Y_dev must be 8-byte and ws_dev 256-byte aligned");
     return FGFRFT_EINVAL;
   }
-  const int ch = apply_chunk(n_alpha, chunk);
+  const int ch = apply_chunk(p, apply_real_supported(p, x_complex, B), n_alpha, chunk);
   const size_t need = fgfrft_apply_workspace_bytes(plan, n_alpha, B, x_complex, x_shared, chunk);
   if (ws_bytes < need) { set_error("apply workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
   // real F and real signals: the update writes R = Re Q only and the apply adds the imaginary part

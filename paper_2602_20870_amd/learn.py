@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import torch
 
-from .autograd import fgfrft
+from .autograd import fgfrft, fractional_filter
 from .ops import Plan
 
 
@@ -46,9 +46,7 @@ class FractionalMaskDenoiser(torch.nn.Module):
         self.h = torch.nn.Parameter(torch.ones(plan.N, 1, dtype=torch.float32, device=plan.device))
 
     def forward(self, y: torch.Tensor) -> torch.Tensor:
-        Z = fgfrft(y.contiguous(), self.alpha, self.plan)[0]
-        W = (self.h * Z).contiguous()
-        return fgfrft(W, -self.alpha, self.plan)[0]
+        return fractional_filter(y.contiguous(), self.alpha, self.h, self.plan)[0]
 
 
 class PointCloudDenoiser(torch.nn.Module):
@@ -71,8 +69,7 @@ class PointCloudDenoiser(torch.nn.Module):
 
     def forward(self, Y: torch.Tensor) -> torch.Tensor:
         X = torch.matmul(Y, self.W_in).permute(2, 1, 0).contiguous()      # [C, N, clouds]
-        Z = fgfrft(X, self.alpha, self.plan)
-        Zi = fgfrft((self.h * Z).contiguous(), -self.alpha, self.plan)
+        Zi = fractional_filter(X, self.alpha, self.h, self.plan)
         return torch.matmul(Zi.real.permute(2, 1, 0), self.W_out)         # [clouds, N, c_in]
 
 
