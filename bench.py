@@ -31,12 +31,12 @@ COPY_BYTES = 1 << 31          # plain device copy used as the counter and bandwi
 # then WRITE_SIZE, KiB per dispatch), each scaled by the same counter's reading for the plain
 # copy of COPY_BYTES that this script runs.  Valid only for the kernel sources with this digest:
 # once update.hip or internal.h change, the figure is reported as null until re-measured.
-UPDATE_TRAFFIC = {"fetch_bytes": 4362320681, "write_bytes": 34365182293,
-                  "source_sha256": "892ce28268e6f482229549e9e7da921c5f708bfdd3515659e133a6cca5f342b3"}
+UPDATE_TRAFFIC = {"fetch_bytes": 4362317681, "write_bytes": 34366226155,
+                  "source_sha256": "b7d961fcdb8523ae7153adbf20c6c889a172ae72f602b1ff7eb068585a51d5e3"}
 # The same for one k_direct_pair launch over 64 signal columns of the knn4096 plan (FP16X2 stack;
 # direct.hip + internal.h).
-DIRECT_TRAFFIC = {"fetch_bytes": 2224835119, "write_bytes": 67108864, "ncols": 64,
-                  "source_sha256": "ab867c484e68452b7af459cd2865fe7eff6b0db6fdab666550f6c440182e03f5"}
+DIRECT_TRAFFIC = {"fetch_bytes": 2224949173, "write_bytes": 67108864, "ncols": 64,
+                  "source_sha256": "051fcb4c5eb5047fbbd57eaba18338c09bc5258cfad7b169e05c02cd7b517d67"}
 
 
 def log(msg):
