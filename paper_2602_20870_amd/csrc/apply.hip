@@ -235,44 +235,53 @@ __global__ __launch_bounds__(256) void k_apply(const cplx64* __restrict__ Q, int
 }
 
 // ---------------------------------------------------------------- streaming apply
-// Y[a] = Q[a] X[a] for N % K2 == 0 and B % 64 == 0: 128 output rows x 64 signals per
-// workgroup (wave w: rows 32w..32w+31, both 32-signal blocks), k in stages of K2.  Each stage
-// (K2 KB of Q, K2/4 or K2/2 KB of X) moves from HBM/L2 straight into LDS with direct loads
-// into a ring of NS stages, so NS - 1 stages are in flight while the matrix cores work on the
-// current one; operands are split into fp16 hi/lo when a wave reads its fragments.  Q rows
-// sit in LDS with their 16-byte chunks swizzled by row (chunk c of row r at c ^ (r mod CPR),
-// CPR chunks per row) so the fragment reads of 32 rows spread over the banks.
+// Y[a] = Q[a] X[a] for N % K2 == 0 and B % 64 == 0: 32 RG output rows x 64 signals per
+// workgroup, k in stages of K2.  Each stage (32 RG rows x K2 of Q, K2 rows of X) moves from
+// HBM/L2 straight into LDS with direct loads into a ring of NS stages, so NS - 1 stages are in
+// flight while the matrix cores work on the current one; operands are split into fp16 hi/lo
+// when a wave reads its fragments.  RG x KSPL waves: wave (g, p) computes rows 32g .. 32g + 31
+// for both 32-signal blocks over part p of each stage's 16-wide k steps; with KSPL > 1 the
+// parts' sums are added once at the end through LDS, in the fixed order p = 0, 1, ...
+//   RG = 4, KSPL = 1, K2 = 32 or 16: two workgroups per CU, 256- or 128-byte Q row runs per stage;
+//   RG = 4, KSPL = 2, K2 = 64: one workgroup per CU, two stages of 80 KB; every Q row is read as a
+//   512-byte run per stage, which the memory system streams measurably faster than 256-byte runs.
+// Q rows sit in LDS with their 16-byte chunks swizzled by row (chunk c of row r at
+// c ^ (r mod SW)) so the fragment reads of 32 rows spread over the banks.
 constexpr int M2 = 128;
 
-template <bool XC, int K2>
+template <bool XC, int K2, int RG = 4>
 struct Apply2Layout {
-  static constexpr int QB = M2 * K2 * 8;              // Q stage bytes
+  static constexpr int QB = 32 * RG * K2 * 8;         // Q stage bytes
   static constexpr int XB = K2 * 64 * (XC ? 8 : 4);   // X stage bytes
   static constexpr int SB = QB + XB;
   static constexpr int QROW = K2 * 8, CPR = K2 / 2, RPI = 1024 / QROW;   // row bytes, chunks, rows per load
-  static constexpr int LW = QB / 4096 + XB / 4096;    // direct loads per wave per stage
-  static_assert((RPI * 4) % CPR == 0, "row swizzle constant per wave");
+  static constexpr int SW = CPR < 16 ? CPR : 16;      // swizzle period (rows)
 };
 
-// PRE (real signals, K2 = 32): X is the pre-split signal block of xsplit_launch, so a stage's
-// B fragments are plain 16-byte LDS reads (no per-wave split of the same signals).
-template <bool XC, bool YREAL, int NS, int K2, bool PRE = false>
-__global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q, int N, int n_alpha,
-                                                   const void* __restrict__ X, int x_shared, int B,
-                                                   const float2* __restrict__ xscale, void* __restrict__ Y, int nrb,
-                                                   int ncb) {
-  static_assert(!PRE || (!XC && K2 == 32), "pre-split signals: real, 32-wide k stages");
-  using LY = Apply2Layout<XC, K2>;
-  constexpr int XE = XC ? 8 : 4, CPR = LY::CPR, RPI = LY::RPI;
+// PRE (real signals, K2 = 32 or 64): X is the pre-split signal block of xsplit_launch, so a
+// stage's B fragments are plain 16-byte LDS reads (no per-wave split of the same signals).
+template <bool XC, bool YREAL, int NS, int K2, bool PRE = false, int RG = 4, int KSPL = 1>
+__global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_apply2(
+    const cplx64* __restrict__ Q, int N, int n_alpha, const void* __restrict__ X, int x_shared, int B,
+    const float2* __restrict__ xscale, void* __restrict__ Y, int nrb, int ncb) {
+  static_assert(!PRE || (!XC && K2 % 32 == 0), "pre-split signals: real, k stages of whole 32-row chunks");
+  static_assert((K2 / 16) % KSPL == 0, "whole 16-wide k steps per part");
+  using LY = Apply2Layout<XC, K2, RG>;
+  constexpr int XE = XC ? 8 : 4, CPR = LY::CPR, RPI = LY::RPI, SW = LY::SW, NW = RG * KSPL;
+  constexpr int QLW = LY::QB / (1024 * NW), XLW = LY::XB / (1024 * NW), LW = QLW + XLW;   // loads per wave
+  static_assert(QLW * 1024 * NW == LY::QB && XLW * 1024 * NW == LY::XB, "whole loads per wave");
+  static_assert((RPI * NW) % SW == 0, "row swizzle constant per wave");
+  constexpr int KSW = K2 / 16 / KSPL;                 // 16-wide k steps per wave and stage
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
+  const int rg = wave % RG, kp = wave / RG;           // row group, k part
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int per_a = nrb * ncb;
   const int a = xcd + 8 * (slot / per_a);
   if (a >= n_alpha) return;
   const int rem = slot % per_a, rb = rem / ncb, cb = rem % ncb;
-  const int i0 = rb * M2, b0 = cb * 64;
+  const int i0 = rb * 32 * RG, b0 = cb * 64;
   const size_t NN = (size_t)N * N;
   const char* Qa = (const char*)(Q + (size_t)a * NN);
   const char* Xa = (const char*)X + (x_shared ? 0 : (size_t)a * N * B * XE);
@@ -280,30 +289,30 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
   const int nch = N / K2;
 
   // Each direct load is a wave-uniform base plus a fixed per-lane 32-bit offset, so the offsets
-  // stay in the same registers for the whole loop.  Q instruction i (i = wave + 4q) moves rows
+  // stay in the same registers for the whole loop.  Q instruction i (i = wave + NW q) moves rows
   // i0 + RPI i .. + RPI - 1 (a row group past N: any valid rows, never written back; N % 8 == 0
   // so groups are whole); lane: row + lane / CPR, stored chunk lane % CPR holds chunk
-  // (lane % CPR) ^ (row mod CPR), which is the same for every q of a wave.  X instruction i moves
+  // (lane % CPR) ^ (row mod SW), which is the same for every q of a wave.  X instruction i moves
   // the next rows of k of the 64 signals.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   const int qrow = lane / CPR;
   const uint32_t qoff =
-      (uint32_t)(((size_t)qrow * N + 2 * ((lane % CPR) ^ ((RPI * wv + qrow) % CPR))) * 8);
+      (uint32_t)(((size_t)qrow * N + 2 * ((lane % CPR) ^ ((RPI * wv + qrow) % SW))) * 8);
   const uint32_t xoff_l = XC ? (uint32_t)(((size_t)(lane >> 5) * B + 2 * (lane & 31)) * 8)
                              : (uint32_t)(((size_t)(lane >> 4) * B + 4 * (lane & 15)) * 4);
   auto issue = [&](int it) {
     char* st = sm + (it % NS) * LY::SB;
     const int k0 = it * K2;
 #pragma unroll
-    for (int q = 0; q < LY::QB / 4096; ++q) {
-      const int i = wv + 4 * q;
+    for (int q = 0; q < QLW; ++q) {
+      const int i = wv + NW * q;
       const int row0 = i0 + RPI * i < N ? i0 + RPI * i : N - RPI;
       const char* gb = Qa + ((size_t)row0 * N + k0) * 8;
       lds_dma16(gb + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
     }
 #pragma unroll
-    for (int q = 0; q < LY::XB / 4096; ++q) {
-      const int i = wv + 4 * q;
+    for (int q = 0; q < XLW; ++q) {
+      const int i = wv + NW * q;
       if (PRE) {
         const char* gb = (const char*)X + (((size_t)(x_shared ? 0 : a) * ncb + cb) * nch + it) * LY::XB + i * 1024;
         lds_dma16(gb + 16 * lane, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
@@ -321,24 +330,25 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
   // for every direct load issued after them
   asm volatile("" ::"v"(xsc[0]), "v"(xsc[1]));
   floatx16 acc_re[2] = {}, acc_im[2] = {};
-  const int r = 32 * wave + l32;
+  const int r = 32 * rg + l32;
 
   for (int it = 0; it < NS - 1 && it < nch; ++it) issue(it);
   for (int it = 0; it < nch; ++it) {
     // this wave's loads of stage it have landed (only the NS - 2 younger stages may still be in
     // flight) and its reads of stage it - 1 are done; after the barrier that holds for every wave
-    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NS - 2) * LY::LW));
+    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NS - 2) * LW));
     else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
     barrier_nofence();
     if (it + NS - 1 < nch) issue(it + NS - 1);   // refills the slot of stage it - 1
     const char* st = sm + (it % NS) * LY::SB;
 #pragma unroll
-    for (int ks = 0; ks < K2 / 16; ++ks) {
+    for (int kk = 0; kk < KSW; ++kk) {
+    const int ks = kp * KSW + kk;
     // A: Q[r][16 ks + 8 lh .. + 7] (4 chunks of two complex values)
     shortx8 arh, arl, aih, ail;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int c = (8 * ks + 4 * lh + q) ^ (r % CPR);
+      const int c = (8 * ks + 4 * lh + q) ^ (r % SW);
       const float4 v = *(const float4*)(st + r * LY::QROW + c * 16);
       short h, l;
       split_h(v.x * kStackScale, h, l); arh[2 * q] = h; arl[2 * q] = l;
@@ -393,19 +403,51 @@ __global__ __launch_bounds__(256, 2) void k_apply2(const cplx64* __restrict__ Q,
     }
     }
   }
-  // write back: lane holds signal b0 + 32c + l32, rows 32 wave + 8(r/4) + 4 lh + r%4
+  // write back: lane holds signal b0 + 32c + l32, rows 32 rg + 8(e/4) + 4 lh + e%4.  With KSPL
+  // parts, every wave leaves its sums in LDS and wave (rg, p) adds up the elements e of its
+  // share, over the parts in order, for both signal blocks.
+  constexpr int NV = YREAL ? 32 : 64;                 // values per lane: 2 blocks x 16 (re [, im])
+  constexpr int EP = 16 / KSPL;                       // elements per wave in the share
   const size_t yoff = (size_t)a * N * B;
+  if (KSPL > 1) {
+    __syncthreads();   // every wave is done with the ring
+    float* mine = (float*)sm + (size_t)wave * NV * 64;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        mine[(c * 16 + e) * 64 + lane] = acc_re[c][e];
+        if (!YREAL) mine[(32 + c * 16 + e) * 64 + lane] = acc_im[c][e];
+      }
+    __syncthreads();
+  }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int gb = b0 + 32 * c + l32;
     const float u = xs[gb].y * (1.0f / kStackScale);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int gi = i0 + 32 * wave + 8 * (e >> 2) + 4 * lh + (e & 3);
+    for (int j = 0; j < EP; ++j) {
+      const int e = KSPL == 1 ? j : kp * EP + j;
+      float vr, vi = 0.f;
+      if (KSPL == 1) {
+        vr = acc_re[c][j];
+        if (!YREAL) vi = acc_im[c][j];
+      } else {
+        const float* part0 = (const float*)sm + (size_t)rg * NV * 64;
+        vr = part0[(c * 16 + e) * 64 + lane];
+        if (!YREAL) vi = part0[(32 + c * 16 + e) * 64 + lane];
+#pragma unroll
+        for (int p = 1; p < KSPL; ++p) {
+          const float* pp = (const float*)sm + (size_t)(p * RG + rg) * NV * 64;
+          vr = vr + pp[(c * 16 + e) * 64 + lane];
+          if (!YREAL) vi = vi + pp[(32 + c * 16 + e) * 64 + lane];
+        }
+      }
+      const int gi = i0 + 32 * rg + 8 * (e >> 2) + 4 * lh + (e & 3);
       if (gi < N) {
         const size_t off = yoff + (size_t)gi * B + gb;
-        if (YREAL) ((float*)Y)[off] = acc_re[c][e] * u;
-        else ((cplx64*)Y)[off] = cplx64{acc_re[c][e] * u, acc_im[c][e] * u};
+        if (YREAL) ((float*)Y)[off] = vr * u;
+        else ((cplx64*)Y)[off] = cplx64{vr * u, vi * u};
       }
     }
   }
@@ -478,8 +520,10 @@ fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx
 
 // Pre-split signals pay when the same signals are split by many workgroups: a block shared by
 // every order, or many signals per order (each Q row block re-splits them once per 64 columns).
+// Real signals are split into fp16 hi/lo once (k_xsplit) for the 64-wide streaming kernel and,
+// with 32-wide stages, when a block is shared or wide; otherwise each wave splits its fragments.
 static bool apply_presplit(int N, int B, int x_complex, int x_shared) {
-  return !x_complex && N % 32 == 0 && B % 64 == 0 && (x_shared || B >= 256);
+  return !x_complex && N % 32 == 0 && B % 64 == 0 && (N % 64 == 0 || x_shared || B >= 256);
 }
 
 size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared) {
@@ -495,15 +539,17 @@ static void launch_apply_t(dim3 g, hipStream_t s, const cplx64* Q, int N, int n_
   k_apply<ADJ, XC, YR><<<g, 256, 0, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
-template <bool XC, bool YR, int NS, int K2, bool PRE = false>
-static void launch_apply2_t(unsigned g, hipStream_t s, const cplx64* Q, int N, int n_alpha, const void* X, int x_shared,
-                            int B, const float2* sc, void* Y, int nrb, int ncb) {
-  constexpr int lds = NS * Apply2Layout<XC, K2>::SB;
-  static_assert(lds <= 80 * 1024, "two workgroups per CU");
-  (void)raise_lds_limit((const void*)k_apply2<XC, YR, NS, K2, PRE>, lds);   // a failure surfaces at the launch
-  k_apply2<XC, YR, NS, K2, PRE><<<g, 256, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
+template <bool XC, bool YR, int NS, int K2, bool PRE = false, int RG = 4, int KSPL = 1>
+static void launch_apply2_t(hipStream_t s, const cplx64* Q, int N, int n_alpha, const void* X, int x_shared, int B,
+                            const float2* sc, void* Y, int ncb) {
+  constexpr int lds = NS * Apply2Layout<XC, K2, RG>::SB;
+  static_assert(lds <= (RG * KSPL == 4 ? 80 : 160) * 1024, "two workgroups per CU (4 waves), else one");
+  static_assert(KSPL == 1 || RG * KSPL * (YR ? 32 : 64) * 64 * 4 <= lds, "the parts' sums fit the ring");
+  const int nrb = ceil_div(N, 32 * RG);
+  const unsigned g = (unsigned)(8 * ceil_div(n_alpha, 8) * nrb * ncb);   // bounded by the caller
+  (void)raise_lds_limit((const void*)k_apply2<XC, YR, NS, K2, PRE, RG, KSPL>, lds);   // a failure surfaces at the launch
+  k_apply2<XC, YR, NS, K2, PRE, RG, KSPL><<<g, 64 * RG * KSPL, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
-
 
 
 // ---------------------------------------------------------------- real-F apply
@@ -827,25 +873,27 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
   }
   // streaming kernel: k stages of 32 (real signals, 2-stage ring) or 16 (complex, 3-stage ring)
   if (!adjoint && N % (x_complex ? 16 : 32) == 0 && B % 64 == 0) {
-    const int nrb = ceil_div(N, M2), ncb = B / 64;
-    const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
+    const int ncb = B / 64;
+    const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * ceil_div(N, 64) * ncb;   // the largest grid below
     if (nblocks > 0x7fffffff) {
       set_error("apply grid too large");
       return FGFRFT_EUNSUPPORTED;
     }
     const cplx64* q = (const cplx64*)Q;
-    const int key = (x_complex ? 2 : 0) | (y_real ? 1 : 0);
+    const bool wide = N % 64 == 0;   // 64-wide k stages (512-byte Q row runs)
     if (pre) {
-      if (y_real) launch_apply2_t<false, true, 2, 32, true>((unsigned)nblocks, s, q, N, n_alpha, Xs, x_shared, B, sc, Y, nrb, ncb);
-      else launch_apply2_t<false, false, 2, 32, true>((unsigned)nblocks, s, q, N, n_alpha, Xs, x_shared, B, sc, Y, nrb, ncb);
+      if (wide && y_real) launch_apply2_t<false, true, 2, 64, true, 4, 2>(s, q, N, n_alpha, Xs, x_shared, B, sc, Y, ncb);
+      else if (wide) launch_apply2_t<false, false, 2, 64, true, 4, 2>(s, q, N, n_alpha, Xs, x_shared, B, sc, Y, ncb);
+      else if (y_real) launch_apply2_t<false, true, 2, 32, true>(s, q, N, n_alpha, Xs, x_shared, B, sc, Y, ncb);
+      else launch_apply2_t<false, false, 2, 32, true>(s, q, N, n_alpha, Xs, x_shared, B, sc, Y, ncb);
       FG_LAUNCHED("apply");
       return FGFRFT_OK;
     }
-    switch (key) {
-      case 0: launch_apply2_t<false, false, 2, 32>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
-      case 1: launch_apply2_t<false, true, 2, 32>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
-      case 2: launch_apply2_t<true, false, 3, 16>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
-      case 3: launch_apply2_t<true, true, 3, 16>((unsigned)nblocks, s, q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb); break;
+    switch ((x_complex ? 2 : 0) | (y_real ? 1 : 0)) {
+      case 0: launch_apply2_t<false, false, 2, 32>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+      case 1: launch_apply2_t<false, true, 2, 32>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+      case 2: launch_apply2_t<true, false, 3, 16>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+      case 3: launch_apply2_t<true, true, 3, 16>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
     }
     FG_LAUNCHED("apply");
     return FGFRFT_OK;

@@ -224,7 +224,12 @@ def test_update_rejects_out_of_range_orders():
 @pytest.mark.parametrize("xc,shared,N,B", [(False, False, 64, 32), (True, False, 80, 37), (False, True, 50, 5),
                                            (True, True, 130, 70),
                                            (False, True, 96, 128),      # pre-split signals: shared block
-                                           (False, False, 160, 256)])   # pre-split signals: wide blocks
+                                           (False, False, 160, 256),    # pre-split signals: wide blocks
+                                           # 64-wide k stages split over two wave halves (N % 64 == 0):
+                                           (False, False, 192, 64),     # ragged row block, 3 stages
+                                           (False, False, 64, 64),      # one stage, half a row block
+                                           (False, True, 320, 128),     # pre-split shared block, ragged
+                                           (False, False, 256, 320)])   # pre-split wide blocks, 5 column blocks
 def test_apply_against_oracle(xc, shared, N, B):
     torch = torch_cuda()
     announce(f"apply xc={xc} shared={shared} N={N} B={B}")
@@ -262,6 +267,30 @@ def test_apply_operator_adjoint_and_real_output():
     for a in range(n):
         assert rel_fro(Y[a], Q32[a].conj().T @ X32[a]) <= TOL_FP32
         assert rel_fro(Yr[a], (Q32[a] @ X32[a]).real) <= TOL_FP32
+
+
+@pytest.mark.parametrize("N,B", [(192, 64), (128, 128)])
+def test_apply_operator_real_signals_both_outputs(N, B):
+    """Real signals through the streaming apply with 64-wide k stages (the two wave halves'
+    sums added at the end) for a complex and a real-part output."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import apply_operator
+    announce(f"apply_operator real signals N={N} B={B}")
+    rng = np.random.default_rng(N + 7 * B)
+    n = 3
+    Q = (rng.standard_normal((n, N, N)) + 1j * rng.standard_normal((n, N, N))) / np.sqrt(N)
+    X = rng.standard_normal((n, N, B)) * np.exp(rng.uniform(-4, 4, (1, 1, B)))   # columns over decades
+    Qt = torch.from_numpy(Q.astype(np.complex64)).cuda()
+    Xt = torch.from_numpy(X.astype(np.float32)).cuda()
+    Q32 = Q.astype(np.complex64).astype(np.complex128)
+    X32 = X.astype(np.float32).astype(np.float64)
+    Y = apply_operator(Qt, Xt).cpu().numpy()
+    Yr = apply_operator(Qt, Xt, y_real=True).cpu().numpy()
+    for a in range(n):
+        ref = Q32[a] @ X32[a]
+        for b in range(B):   # per column: the columns' magnitudes span eight decades
+            assert rel_fro(Y[a][:, b], ref[:, b]) <= TOL_FP32, (a, b)
+            assert rel_fro(Yr[a][:, b], ref[:, b].real) <= TOL_FP32, (a, b)
 
 
 # ----------------------------------------------------------------------------
