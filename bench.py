@@ -113,6 +113,37 @@ def write_bandwidth(dev, nbytes=1 << 33, reps=5):
     return {"bytes_written": nbytes, "ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}
 
 
+def update_traffic_reference(dev, N, L, na, reps=5):
+    """The operator update's own HBM traffic with no arithmetic (fgfrft_probe_update_traffic): per
+    strip of 4 x 64 positions, its 2L + 1 stack-shaped tiles staged in LDS with direct loads, then
+    the strip's positions of every order written in the update's store pattern.  The attainable
+    time for the update's mix of reads and writes on this device."""
+    import torch
+    from paper_2602_20870_amd import lib
+    from paper_2602_20870_amd._lib import check
+    import ctypes
+    nt = min(2 * L + 1, 65)
+    src = torch.zeros(nt * N * N * 4, dtype=torch.uint8, device=dev)
+    dst = torch.empty(na * N * N * 8, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    s = ctypes.c_void_p(stream.cuda_stream)
+    call = lambda: check(lib().fgfrft_probe_update_traffic(ctypes.c_void_p(src.data_ptr()), N, nt, na,
+                                                           ctypes.c_void_p(dst.data_ptr()), s),
+                         "fgfrft_probe_update_traffic")
+    call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "k_update_traffic: the update's staging reads and store pattern, no arithmetic",
+            "tiles": nt, "orders": na, "bytes_read": nt * N * N * 4, "bytes_written": na * N * N * 8, "ms": ms}
+
+
 def throughput_configs(reps=5):
     """Plain-method throughput on the 32x32 grid (N = 1024, weights U[0.5, 1.5], real F) and the
     directed 256-cycle (unitary DFT, complex F with a -1 eigenspace): L = 32, 256 orders in
@@ -792,6 +823,12 @@ def main():
         out["roofline"]["attainable_write_GBps"] = w
         out["roofline"]["frac_of_attainable_write"] = achieved / w
         log(f"write-only stream {w:.0f} GB/s; update at {achieved / w:.2f} of it")
+    leg("update_traffic_reference", lambda: update_traffic_reference(dev, N, L, na))
+    if "ms" in out["update_traffic_reference"]:
+        t = out["update_traffic_reference"]["ms"]
+        out["roofline"]["attainable_GBps"] = upd_bytes / (t * 1e-3) / 1e9
+        out["roofline"]["frac_of_attainable"] = t / upd_ms
+        log(f"update traffic alone {t:.3f} ms; update at {t / upd_ms:.2f} of it")
     if not args.no_configs:
         leg("throughput_configs", throughput_configs)
     if not args.no_grad:

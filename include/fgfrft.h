@@ -330,6 +330,16 @@ FGFRFT_API fgfrft_status fgfrft_gfrft_exact(const void* V_dev, const void* Vh_de
  * bytes a nonzero multiple of 16, else FGFRFT_EINVAL.  Enqueues on `stream`. */
 FGFRFT_API fgfrft_status fgfrft_probe_write(void* dst_dev, size_t bytes, void* stream);
 
+/* The operator update's HBM traffic with no arithmetic, for N % 64 == 0: per strip of 4 rows x
+ * 64 positions (64 <= N <= 32704), stages the strip's tiles of n_tiles row-major N x N matrices of 4-byte values at
+ * src_dev (n_tiles N^2 4 bytes, device, 16-byte aligned; the update stages its 2L stack matrices
+ * and the projector) in LDS, then writes those positions of n_alpha complex64 N x N planes at
+ * dst_dev (n_alpha N^2 8 bytes, device) in the update's store pattern (512-byte row runs, orders
+ * in sequence).  The values written are meaningless.  1 <= n_tiles <= 65, n_alpha >= 1, else
+ * FGFRFT_EINVAL.  Enqueues on `stream`. */
+FGFRFT_API fgfrft_status fgfrft_probe_update_traffic(const void* src_dev, int N, int n_tiles, int n_alpha,
+                                                     void* dst_dev, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Errors
  * ------------------------------------------------------------------------- */

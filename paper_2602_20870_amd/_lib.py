@@ -43,6 +43,7 @@ SIGNATURES = {
     "fgfrft_gfrft_exact": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_size_t,
                                    c_void_p]),
     "fgfrft_probe_write": (c_int, [c_void_p, c_size_t, c_void_p]),
+    "fgfrft_probe_update_traffic": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
     "fgfrft_strerror": (ctypes.c_char_p, [c_int]),
     "fgfrft_last_error": (ctypes.c_char_p, []),
 }

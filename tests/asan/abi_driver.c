@@ -89,6 +89,9 @@ int main(void) {
          "exact workspace too small");
   expect(fgfrft_probe_write(NULL, 64, NULL), FGFRFT_EINVAL, "probe_write NULL");
   expect(fgfrft_probe_write(buf, 17, NULL), FGFRFT_EINVAL, "probe_write size");
+  expect(fgfrft_probe_update_traffic(NULL, 64, 4, 1, buf, NULL), FGFRFT_EINVAL, "probe_update_traffic NULL");
+  expect(fgfrft_probe_update_traffic(buf, 96, 4, 1, buf, NULL), FGFRFT_EINVAL, "probe_update_traffic N");
+  expect(fgfrft_probe_update_traffic(buf, 64, 0, 1, buf, NULL), FGFRFT_EINVAL, "probe_update_traffic tiles");
   /* error strings */
   for (int c = 1; c >= -9; --c) {
     const char* t = fgfrft_strerror(c);
