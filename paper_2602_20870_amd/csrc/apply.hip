@@ -613,96 +613,90 @@ __global__ __launch_bounds__(256) void k_zsum(const float* __restrict__ pz, int 
   Z[((size_t)a * kWCols + q) * B + b] = s;
 }
 
-// Y[a] = R[a] X[a] + j sin(pi alpha_a) W Z[a] for N % 32 == 0 and B % 64 == 0: the streaming
-// kernel's structure (128 output rows x 64 signals per workgroup, direct-load LDS ring of NS
-// stages of 32 k) with a real operator: each 32-wide k stage holds 16 KB of R (128-byte row
-// segments, 16-byte chunks swizzled by row) and 8 KB of signals; per 16-wide k step a wave splits
-// its R fragment once (2 parts) and issues 3 products per 32-signal block.
-constexpr int RS_NS = 3, RS_K2 = 32;
+// Y[a] = R[a] X[a] + j sin(pi alpha_a) W Z[a] for N % K2 == 0 and B % 64 == 0: the streaming
+// kernel's structure (32 RG output rows x 64 signals per workgroup, RG x KSPL waves, direct-load
+// LDS ring of NS stages of K2 k) with a real operator: a stage holds 32 RG rows x K2 of R (4 K2-byte
+// row runs, 16-byte chunks swizzled by row) and the K2 rows of pre-split signals; per 16-wide k step
+// a wave splits its R fragment once (2 parts) and issues 3 products per 32-signal block; with
+// KSPL > 1 the k parts' sums are added once at the end through LDS in a fixed order.
+template <int K2, int RG>
 struct ApplyRealLayout {
-  static constexpr int QB = M2 * RS_K2 * 4, XB = RS_K2 * 64 * 4, SB = QB + XB;
-  static constexpr int QROW = RS_K2 * 4, CPR = QROW / 16, RPI = 1024 / QROW;
-  static constexpr int LW = QB / 4096 + XB / 4096;
+  static constexpr int QB = 32 * RG * K2 * 4, XB = K2 * 64 * 4, SB = QB + XB;
+  static constexpr int QROW = K2 * 4, CPR = QROW / 16, RPI = 1024 / QROW;
+  static constexpr int SW = CPR < 16 ? CPR : 16;      // swizzle period (rows)
 };
 
-// PRE: X is the pre-split signal block of xsplit_launch (fp16 hi / lo parts in fragment order), so the
-// waves read their signal fragments with plain 16-byte LDS loads instead of each splitting them.
+// X is the pre-split signal block of xsplit_launch (fp16 hi / lo parts in fragment order), so the
+// waves read their signal fragments with plain 16-byte LDS loads.
 // DXO: float32 output Y[a] = R[a] X[a] - sin(pi alpha_a) W Z[a] (the real part of Q[a] (X + j X'[a])
 // when Z[a] = W^T X'[a]: the signal gradient for real signals, with the orders negated).
-template <bool PRE, bool DXO = false>
-__global__ __launch_bounds__(256, 2) void k_apply_real(const float* __restrict__ R, int N, int n_alpha,
-                                                       const void* __restrict__ X, int x_shared, int B,
-                                                       const float2* __restrict__ xscale,
-                                                       const double* __restrict__ alphas, const float* __restrict__ W,
-                                                       int r, const float* __restrict__ Z, void* __restrict__ Y,
-                                                       int nrb, int ncb) {
-  using LY = ApplyRealLayout;
-  constexpr int CPR = LY::CPR, RPI = LY::RPI, NS = RS_NS, K2 = RS_K2;
-  static_assert(RPI % CPR == 0, "row swizzle constant per lane");
+template <bool DXO, int K2, int NS, int RG, int KSPL>
+__global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_apply_real(
+    const float* __restrict__ R, int N, int n_alpha, const void* __restrict__ X, int x_shared, int B,
+    const float2* __restrict__ xscale, const double* __restrict__ alphas, const float* __restrict__ W, int r,
+    const float* __restrict__ Z, void* __restrict__ Y, int nrb, int ncb) {
+  using LY = ApplyRealLayout<K2, RG>;
+  constexpr int CPR = LY::CPR, RPI = LY::RPI, SW = LY::SW, NW = RG * KSPL;
+  constexpr int QLW = LY::QB / (1024 * NW), XLW = LY::XB / (1024 * NW), LW = QLW + XLW;   // loads per wave
+  static_assert(QLW * 1024 * NW == LY::QB && XLW * 1024 * NW == LY::XB, "whole loads per wave");
+  static_assert((RPI * NW) % SW == 0, "row swizzle constant per wave");
+  static_assert(K2 % 32 == 0 && (K2 / 16) % KSPL == 0, "whole pre-split chunks, whole k steps per part");
+  constexpr int KSW = K2 / 16 / KSPL;
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, lh = lane >> 5;
+  const int rg = wave % RG, kp = wave / RG;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int per_a = nrb * ncb;
   const int a = xcd + 8 * (slot / per_a);
   if (a >= n_alpha) return;
   const int rem = slot % per_a, rb = rem / ncb, cb = rem % ncb;
-  const int i0 = rb * M2, b0 = cb * 64;
+  const int i0 = rb * 32 * RG, b0 = cb * 64;
   const size_t NN = (size_t)N * N;
   const char* Ra = (const char*)(R + (size_t)a * NN);
-  const char* Xa = (const char*)X + (x_shared ? 0 : (size_t)a * N * B * 4);
   const float2* xs = xscale + (x_shared ? 0 : (size_t)a * B);
   const int nch = N / K2;
 
-  // R instruction i (i = wave + 4q) moves rows i0 + RPI i .. + RPI - 1 (a row group past N: rows
+  // R instruction i (i = wave + NW q) moves rows i0 + RPI i .. + RPI - 1 (a row group past N: rows
   // N - RPI.., never written back); lane: row + lane / CPR, LDS chunk lane % CPR holds source chunk
-  // (lane % CPR) ^ (row mod CPR) = (lane % CPR) ^ (lane / CPR) since RPI is a multiple of CPR.
+  // (lane % CPR) ^ (row mod SW), the same for every q of a wave.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   const int qrow = lane / CPR;
-  const uint32_t qoff = (uint32_t)(((size_t)qrow * N + 4 * ((lane % CPR) ^ (qrow % CPR))) * 4);
-  const uint32_t xoff_l = (uint32_t)(((size_t)(lane >> 4) * B + 4 * (lane & 15)) * 4);
+  const uint32_t qoff = (uint32_t)(((size_t)qrow * N + 4 * ((lane % CPR) ^ ((RPI * wv + qrow) % SW))) * 4);
   auto issue = [&](int it) {
     char* st = sm + (it % NS) * LY::SB;
     const int k0 = it * K2;
 #pragma unroll
-    for (int q = 0; q < LY::QB / 4096; ++q) {
-      const int i = wv + 4 * q;
+    for (int q = 0; q < QLW; ++q) {
+      const int i = wv + NW * q;
       const int row0 = i0 + RPI * i < N ? i0 + RPI * i : N - RPI;
       lds_dma16(Ra + ((size_t)row0 * N + k0) * 4 + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
     }
 #pragma unroll
-    for (int q = 0; q < LY::XB / 4096; ++q) {
-      const int i = wv + 4 * q;
-      if (PRE) {
-        const char* gb = (const char*)X + (((size_t)(x_shared ? 0 : a) * ncb + cb) * nch + it) * LY::XB + i * 1024;
-        lds_dma16(gb + 16 * lane, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
-      } else {
-        const char* gb = Xa + ((size_t)(k0 + 4 * i) * B + b0) * 4;
-        lds_dma16(gb + xoff_l, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
-      }
+    for (int q = 0; q < XLW; ++q) {
+      const int i = wv + NW * q;
+      const char* gb = (const char*)X + (((size_t)(x_shared ? 0 : a) * ncb + cb) * nch + it) * LY::XB + i * 1024;
+      lds_dma16(gb + 16 * lane, __builtin_amdgcn_readfirstlane(lds_addr(st + LY::QB + i * 1024)));
     }
   };
 
-  float xsc[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) xsc[c] = xs[b0 + 32 * c + l32].x;
-  asm volatile("" ::"v"(xsc[0]), "v"(xsc[1]));   // settled before the ring starts
   floatx16 acc[2] = {};
-  const int rr = 32 * wave + l32;
+  const int rr = 32 * rg + l32;
 
   for (int it = 0; it < NS - 1 && it < nch; ++it) issue(it);
   for (int it = 0; it < nch; ++it) {
-    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NS - 2) * LY::LW));
+    if (it + NS - 1 <= nch) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NS - 2) * LW));
     else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
     barrier_nofence();
     if (it + NS - 1 < nch) issue(it + NS - 1);
     const char* st = sm + (it % NS) * LY::SB;
 #pragma unroll
-    for (int ks = 0; ks < K2 / 16; ++ks) {
+    for (int kk = 0; kk < KSW; ++kk) {
+      const int ks = kp * KSW + kk;
       shortx8 arh, arl;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {   // R[rr][16 ks + 8 lh .. + 7]: two chunks of four reals
-        const int c = (4 * ks + 2 * lh + q) ^ (rr % CPR);
+        const int c = (4 * ks + 2 * lh + q) ^ (rr % SW);
         const float4 v = *(const float4*)(st + rr * LY::QROW + c * 16);
         short h, l;
         split_h(v.x * kStackScale, h, l); arh[4 * q] = h; arl[4 * q] = l;
@@ -712,29 +706,28 @@ __global__ __launch_bounds__(256, 2) void k_apply_real(const float* __restrict__
       }
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const int col = 32 * c + l32;
-        shortx8 xh, xl;
-        if (PRE) {
-          const char* xb = st + LY::QB + ((ks * 2 + c) * 2) * 1024 + 16 * lane;
-          xh = *(const shortx8*)xb;
-          xl = *(const shortx8*)(xb + 1024);
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int k = 16 * ks + 8 * lh + j;
-            const float v = *(const float*)(st + LY::QB + (k * 64 + col) * 4);
-            short h, l;
-            split_h(v * xsc[c], h, l); xh[j] = h; xl[j] = l;
-          }
-        }
+        const char* xb = st + LY::QB + ((ks * 2 + c) * 2) * 1024 + 16 * lane;
+        const shortx8 xh = *(const shortx8*)xb;
+        const shortx8 xl = *(const shortx8*)(xb + 1024);
         acc[c] = mma(arh, xh, acc[c]);
         acc[c] = mma(arh, xl, acc[c]);
         acc[c] = mma(arl, xh, acc[c]);
       }
     }
   }
-  // write back: lane holds signal b0 + 32c + l32, rows 32 wave + 8(e/4) + 4 lh + e%4; the imaginary
-  // part is sin(pi alpha) (W Z[a]) with the rank-r factor (zero when r = 0)
+  // write back: lane holds signal b0 + 32c + l32, rows 32 rg + 8(e/4) + 4 lh + e%4; the imaginary
+  // part is sin(pi alpha) (W Z[a]) with the rank-r factor (zero when r = 0).  With KSPL parts every
+  // wave leaves its sums in LDS and wave (rg, p) adds up the elements of its share in part order.
+  constexpr int EP = 16 / KSPL;
+  if (KSPL > 1) {
+    __syncthreads();   // every wave is done with the ring
+    float* mine = (float*)sm + (size_t)wave * 32 * 64;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) mine[(c * 16 + e) * 64 + lane] = acc[c][e];
+    __syncthreads();
+  }
   const float sn = r > 0 ? (float)sinpi(alphas[a]) : 0.f;
   const float* Za = Z + (size_t)(x_shared ? 0 : a) * kWCols * B;
   const size_t yoff = (size_t)a * N * B;
@@ -743,16 +736,54 @@ __global__ __launch_bounds__(256, 2) void k_apply_real(const float* __restrict__
     const int gb = b0 + 32 * c + l32;
     const float u = xs[gb].y * (1.0f / kStackScale);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int gi = i0 + 32 * wave + 8 * (e >> 2) + 4 * lh + (e & 3);
+    for (int j = 0; j < EP; ++j) {
+      const int e = KSPL == 1 ? j : kp * EP + j;
+      float v;
+      if (KSPL == 1) {
+        v = acc[c][j];
+      } else {
+        v = ((const float*)sm)[((size_t)rg * 32 + c * 16 + e) * 64 + lane];
+#pragma unroll
+        for (int p = 1; p < KSPL; ++p) v = v + ((const float*)sm)[((size_t)(p * RG + rg) * 32 + c * 16 + e) * 64 + lane];
+      }
+      const int gi = i0 + 32 * rg + 8 * (e >> 2) + 4 * lh + (e & 3);
       if (gi < N) {
         float im = 0.f;
         for (int q = 0; q < r; ++q) im = fmaf(W[(size_t)gi * kWCols + q], Za[(size_t)q * B + gb], im);
-        if (DXO) ((float*)Y)[yoff + (size_t)gi * B + gb] = acc[c][e] * u - sn * im;
-        else ((cplx64*)Y)[yoff + (size_t)gi * B + gb] = cplx64{acc[c][e] * u, sn * im};
+        if (DXO) ((float*)Y)[yoff + (size_t)gi * B + gb] = v * u - sn * im;
+        else ((cplx64*)Y)[yoff + (size_t)gi * B + gb] = cplx64{v * u, sn * im};
       }
     }
   }
+}
+
+// Launch of the real-operator apply.  N % 64 == 0: 64-wide stages (256-byte R row runs), eight waves
+// over two k parts, three stages of 48 KB, one workgroup per CU; else 32-wide stages, four waves,
+// three stages of 24 KB, two workgroups per CU.  Measured on knn4096 (real-F call, 256 orders x 64
+// signals): 8.10 against 8.21 ms; 64 rows x 128-wide stages (512-byte runs, two stages of 64 KB)
+// 8.42 ms, 128 rows x 64-wide with two stages 8.42 ms.
+template <bool DXO>
+static fgfrft_status launch_apply_real(hipStream_t s, const float* R, int N, int n_alpha, const short* Xs,
+                                       int x_shared, int B, const float2* sc, const double* alphas_dev,
+                                       const float* W, int r, const float* Z, void* Y) {
+  const int ncb = B / 64;
+  auto go = [&](auto kern, int NS, int RG, int KSPL, int sb) -> fgfrft_status {
+    const int nrb = ceil_div(N, 32 * RG), lds = NS * sb;
+    const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
+    if (nblocks > 0x7fffffff) {
+      set_error("apply grid too large");
+      return FGFRFT_EUNSUPPORTED;
+    }
+    FG_HIP(raise_lds_limit((const void*)kern, lds));
+    kern<<<(unsigned)nblocks, 64 * RG * KSPL, lds, s>>>(R, N, n_alpha, Xs, x_shared, B, sc, alphas_dev, W, r, Z, Y,
+                                                        nrb, ncb);
+    return FGFRFT_OK;
+  };
+  static_assert(3 * ApplyRealLayout<64, 4>::SB <= 160 * 1024 && 3 * ApplyRealLayout<32, 4>::SB <= 80 * 1024,
+                "rings fit the LDS");
+  static_assert(8 * 32 * 64 * 4 <= 3 * ApplyRealLayout<64, 4>::SB, "the parts' sums fit the ring");
+  if (N % 64 == 0) return go(k_apply_real<DXO, 64, 3, 4, 2>, 3, 4, 2, ApplyRealLayout<64, 4>::SB);
+  return go(k_apply_real<DXO, 32, 3, 4, 1>, 3, 4, 1, ApplyRealLayout<32, 4>::SB);
 }
 
 size_t apply_real_ws_bytes(int N, int n_alpha, int B, int x_shared, int r) {
@@ -785,17 +816,8 @@ fgfrft_status apply_real_launch(const Plan* p, const float* R, int n_alpha, cons
   // four waves of every workgroup that reads them: 3.57 against 3.80 ms per knn4096 launch
   fgfrft_status rc = xsplit_launch(X, B, B, N, nx, x_shared ? 0 : (size_t)N * B, sc, B, Xs, s);
   if (rc) return rc;
-  const int nrb = ceil_div(N, M2), ncb = B / 64;
-  const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
-  if (nblocks > 0x7fffffff) {
-    set_error("apply grid too large");
-    return FGFRFT_EUNSUPPORTED;
-  }
-  constexpr int lds = RS_NS * ApplyRealLayout::SB;
-  static_assert(lds <= 80 * 1024, "two workgroups per CU");
-  FG_HIP(raise_lds_limit((const void*)k_apply_real<true>, lds));
-  k_apply_real<true><<<(unsigned)nblocks, 256, lds, s>>>(R, N, n_alpha, Xs, x_shared, B, sc, alphas_dev, p->W, r, Z, Y,
-                                                         nrb, ncb);
+  rc = launch_apply_real<false>(s, R, N, n_alpha, Xs, x_shared, B, sc, alphas_dev, p->W, r, Z, Y);
+  if (rc) return rc;
   FG_LAUNCHED("apply (real operator)");
   return FGFRFT_OK;
 }
@@ -844,16 +866,8 @@ fgfrft_status apply_real_dx_launch(const Plan* p, const float* R, int n_alpha, c
   FG_LAUNCHED("gradient planes, scales and W^T");
   fgfrft_status rc = xsplit_launch(gr, B, B, N, n_alpha, (size_t)N * B, sc, B, Xs, s);
   if (rc) return rc;
-  const int nrb = ceil_div(N, M2), ncb = B / 64;
-  const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * nrb * ncb;
-  if (nblocks > 0x7fffffff) {
-    set_error("apply grid too large");
-    return FGFRFT_EUNSUPPORTED;
-  }
-  constexpr int lds = RS_NS * ApplyRealLayout::SB;
-  FG_HIP(raise_lds_limit((const void*)k_apply_real<true, true>, lds));
-  k_apply_real<true, true><<<(unsigned)nblocks, 256, lds, s>>>(R, N, n_alpha, Xs, 0, B, sc, alphas_dev, p->W, r, Z, dX,
-                                                               nrb, ncb);
+  rc = launch_apply_real<true>(s, R, N, n_alpha, Xs, 0, B, sc, alphas_dev, p->W, r, Z, dX);
+  if (rc) return rc;
   FG_LAUNCHED("signal gradient (real operator)");
   return FGFRFT_OK;
 }

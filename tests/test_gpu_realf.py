@@ -55,6 +55,7 @@ def _check(F, L, alphas, X, Y, shared, form="split", tol=TOL_FP32):
                                             (128, 0, 128, False, 5),   # no -1 eigenvalue: Q real
                                             (64, 1, 64, True, 9),      # shared signal block
                                             (160, 32, 64, False, 4),   # largest basis the plan keeps
+                                            (192, 2, 128, False, 4),   # 64-wide stages, ragged row block
                                             (96, 40, 64, False, 3)])   # r_-1 > 32: complex route
 def test_real_route_against_oracle(N, r, B, shared, n):
     torch = torch_cuda()
