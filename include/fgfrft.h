@@ -224,6 +224,22 @@ FGFRFT_API fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, 
                                       void* Y_dev, int chunk, void* ws_dev, size_t ws_bytes,
                                       void* stream);
 
+/* Workspace bytes for fgfrft_apply_dev: the operators of all n_alpha orders (float32 R on the
+ * real-F route, complex64 Q otherwise) plus the update and apply workspaces.  0 for a NULL plan
+ * or n_alpha < 1 or B < 1. */
+FGFRFT_API size_t fgfrft_apply_dev_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_complex,
+                                                   int x_shared);
+
+/* fgfrft_apply with the orders already on the device (alphas_dev: float64 [n_alpha], 8-byte
+ * aligned) and all of them in one update launch: Y[a] = Q_L^{alphas_dev[a]} X[a] (Definition 2),
+ * by the real-F route under the same conditions as fgfrft_apply, else through the complex64
+ * operator.  Same layouts as fgfrft_apply.  The call only enqueues kernels on `stream` (no host
+ * copy or synchronisation; capturable).  Orders are device data and are not range-checked: an
+ * order with |alpha| >= L or a non-finite one gives NaN outputs for its signals. */
+FGFRFT_API fgfrft_status fgfrft_apply_dev(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha,
+                                          const void* X_dev, int x_complex, int x_shared, int B, void* Y_dev,
+                                          void* ws_dev, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Direct route: apply without forming any operator (Definition 2 with the
  * expansion of Definition 1 and Proposition 2)

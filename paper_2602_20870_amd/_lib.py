@@ -42,6 +42,9 @@ SIGNATURES = {
     "fgfrft_gfrft_exact_workspace_bytes": (c_size_t, [c_int]),
     "fgfrft_gfrft_exact": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_size_t,
                                    c_void_p]),
+    "fgfrft_apply_dev_workspace_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int]),
+    "fgfrft_apply_dev": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p,
+                                 c_size_t, c_void_p]),
     "fgfrft_probe_write": (c_int, [c_void_p, c_size_t, c_void_p]),
     "fgfrft_probe_update_traffic": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
     "fgfrft_strerror": (ctypes.c_char_p, [c_int]),

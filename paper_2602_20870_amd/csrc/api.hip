@@ -270,6 +270,42 @@ fgfrft_status fgfrft_apply(fgfrft_plan_t plan, const double* alphas, int n_alpha
   return FGFRFT_OK;
 }
 
+size_t fgfrft_apply_dev_workspace_bytes(fgfrft_plan_t plan, int n_alpha, int B, int x_complex, int x_shared) {
+  if (!plan || n_alpha < 1 || B < 1) return 0;
+  const Plan* p = (const Plan*)plan;
+  const bool realF = apply_real_supported(p, x_complex, B);
+  return align_up((size_t)n_alpha * p->N * p->N * (realF ? 4 : 8), 256) + update_ws_bytes(p, n_alpha) +
+         (realF ? apply_real_ws_bytes(p->N, n_alpha, B, x_shared, p->r_minus1) : apply_ws_bytes(p->N, n_alpha, B, x_shared));
+}
+
+fgfrft_status fgfrft_apply_dev(fgfrft_plan_t plan, const double* alphas_dev, int n_alpha, const void* X_dev,
+                               int x_complex, int x_shared, int B, void* Y_dev, void* ws_dev, size_t ws_bytes,
+                               void* stream) {
+  if (!plan) { set_error("NULL plan"); return FGFRFT_EINVAL; }
+  const Plan* p = (const Plan*)plan;
+  if (!alphas_dev || n_alpha < 1) { set_error("alphas_dev is NULL or n_alpha=%d < 1", n_alpha); return FGFRFT_EINVAL; }
+  if (B < 1 || B > 4096) { set_error("B=%d outside [1, 4096]", B); return FGFRFT_EINVAL; }
+  if (!X_dev || !Y_dev || !ws_dev) { set_error("NULL device pointer"); return FGFRFT_EINVAL; }
+  if (!aligned(alphas_dev, 8) || !aligned(X_dev, 8) || !aligned(Y_dev, 8) || !aligned(ws_dev, 256)) {
+    set_error("alphas_dev, X_dev, Y_dev must be 8-byte and ws_dev 256-byte aligned");
+    return FGFRFT_EINVAL;
+  }
+  const size_t need = fgfrft_apply_dev_workspace_bytes(plan, n_alpha, B, x_complex, x_shared);
+  if (ws_bytes < need) { set_error("apply workspace %zu < %zu bytes", ws_bytes, need); return FGFRFT_ENOMEM; }
+  const bool realF = apply_real_supported(p, x_complex, B);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws_dev;
+  void* Qc = base; base += align_up((size_t)n_alpha * p->N * p->N * (realF ? 4 : 8), 256);
+  void* uws = base; base += update_ws_bytes(p, n_alpha);
+  void* aws = base;
+  fgfrft_status rc = update_launch(p, alphas_dev, n_alpha, Qc, uws, s, realF);
+  if (rc) return rc;
+  if (realF)
+    return apply_real_launch(p, (const float*)Qc, n_alpha, alphas_dev, (const float*)X_dev, x_shared ? 1 : 0, B,
+                             (cplx64*)Y_dev, aws, s);
+  return apply_launch(Qc, p->N, n_alpha, 0, X_dev, x_complex ? 1 : 0, x_shared ? 1 : 0, B, Y_dev, 0, aws, s);
+}
+
 size_t fgfrft_apply_direct_workspace_bytes(fgfrft_plan_t plan, int ncols, int ldx) {
   if (!plan || ncols < 0 || ldx < 1 || ldx > (1 << 20)) return 0;
   return direct_ws_bytes((const Plan*)plan, ncols, ldx);

@@ -230,6 +230,30 @@ class Plan:
                               chunk: int = 0) -> int:
         return int(lib().fgfrft_apply_workspace_bytes(self._h, n_alpha, B, int(x_complex), int(x_shared), chunk))
 
+    def apply_dev(self, alphas_dev: torch.Tensor, X: torch.Tensor, out: torch.Tensor,
+                  ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """apply with the orders already on the device (float64 cuda tensor), all in one update
+        launch; enqueues kernels only (capturable with a caller workspace).  Orders with
+        |alpha| >= L give NaN outputs (no host-side check is possible)."""
+        _on_device(self.device, alphas_dev=alphas_dev, out=out)
+        if alphas_dev.dtype != torch.float64 or not alphas_dev.is_contiguous():
+            raise ValueError("alphas_dev must be a contiguous float64 cuda tensor")
+        n = alphas_dev.numel()
+        x_shared = X.dim() == 2
+        B = X.shape[-1]
+        xc = _check_signal(X, n, self.N, x_shared, self.device)
+        if out.dtype != torch.complex64 or not out.is_contiguous() or out.numel() != n * self.N * B:
+            raise ValueError("out must be a contiguous complex64 tensor of n_alpha*N*B elements")
+        L_ = lib()
+        ws, tmp = _caller_ws(ws, L_.fgfrft_apply_dev_workspace_bytes(self._h, n, B, xc, int(x_shared)), self.device)
+        check(L_.fgfrft_apply_dev(self._h, _ptr(alphas_dev), n, _ptr(X), xc, int(x_shared), B, _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "fgfrft_apply_dev")
+        _keep(stream, tmp)
+        return out
+
+    def apply_dev_workspace_bytes(self, n_alpha: int, B: int, x_complex: bool = False, x_shared: bool = False) -> int:
+        return int(lib().fgfrft_apply_dev_workspace_bytes(self._h, n_alpha, B, int(x_complex), int(x_shared)))
+
     def apply_batched(self, alphas, Xs, outs=None, ws: torch.Tensor | None = None, stream=None) -> list:
         """Grouped apply: request r gets Q(alphas[r]) Xs[r], each with its own order and signal count.
 

@@ -41,13 +41,15 @@ DIRECT_BLOCKS = 4          # the direct route takes batches of up to 4 x 64 sign
 ROUTES = ("auto", "operator", "direct")
 
 
-def prefer_direct(n_orders: int, n_blocks: int, L: int) -> bool:
+def prefer_direct(n_orders: int, n_blocks: int, L: int, real_route: bool = False) -> bool:
     """Route choice for one batch, in units of the operator route's stack stream S (its update
     reads the 2L resident matrices): the operator route costs S plus 16 N^2 bytes (write and read
-    of one complex64 operator) per order, 4 / (2L+1) of S each; the direct route costs about 0.85 S
-    for the first 64-column block and about 0.6 S for each further one (measured at N = 4096,
-    L = 32).  Direct iff 0.6 (blocks - 1) < 4 n_orders / (2L+1), slightly conservative."""
-    return n_blocks <= DIRECT_BLOCKS and 0.15 * (n_blocks - 1) * (2 * L + 1) < n_orders
+    of one complex64 operator) per order, 4 / (2L+1) of S each, or 8 N^2 bytes (2 / (2L+1) of S) on
+    the real-F route, which writes and reads only R = Re Q; the direct route costs about 0.85 S for
+    the first 64-column block and about 0.6 S for each further one (measured at N = 4096, L = 32).
+    Direct iff 0.6 (blocks - 1) < c n_orders / (2L+1) with c = 4 or 2, slightly conservative."""
+    c = 2 if real_route else 4
+    return n_blocks <= DIRECT_BLOCKS and 0.6 * (n_blocks - 1) * (2 * L + 1) < c * n_orders
 
 
 def _distinct_queue_streams(n: int, device) -> list:
@@ -112,9 +114,8 @@ class _SlotSet:
         exactly this)."""
         from ._lib import lib
         N = plan.N
-        b = K * 8 + K * N * bmax * 4 + K * N * N * 8 + K * N * bmax * 8      # orders, X, Q, Y
-        b += plan.update_workspace_bytes(K)
-        b += max(256, int(lib().fgfrft_apply_operator_workspace_bytes(N, K, bmax, 0)))
+        b = K * 8 + K * N * bmax * 4 + K * N * bmax * 8      # orders, X, Y
+        b += max(256, plan.apply_dev_workspace_bytes(K, bmax))  # the operators and their workspaces
         nbs = _direct_blocks(plan, route)
         b += sum(N * 64 * nb * 4 + 64 * nb * 4 + N * 64 * nb * 8 for nb in nbs)   # dX, dcols, dY
         b += max([256] + [plan.direct_workspace_bytes(64 * nb, 64 * nb) for nb in nbs])
@@ -126,12 +127,11 @@ class _SlotSet:
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.alphas = torch.zeros(K, dtype=torch.float64, device=device)
         self.X = torch.zeros((K, N, bmax), dtype=torch.float32, device=device)
-        self.Q = torch.empty((K, N, N), dtype=torch.complex64, device=device)
         self.Y = torch.empty((K, N, bmax), dtype=torch.complex64, device=device)
-        self.uws = torch.empty(plan.update_workspace_bytes(K), dtype=torch.uint8, device=device)
-        from ._lib import lib
-        self.aws = torch.empty(max(256, int(lib().fgfrft_apply_operator_workspace_bytes(N, K, bmax, 0))),
-                               dtype=torch.uint8, device=device)
+        # operator route: fgfrft_apply_dev (the real-F route when the plan offers it: R = Re Q in the
+        # workspace, half the bytes of a complex64 operator), one workspace for every bucket
+        self.ows = torch.empty(max(256, plan.apply_dev_workspace_bytes(K, bmax)), dtype=torch.uint8, device=device)
+        self.real_route = (not plan.complex and plan.r_minus1 <= 32 and N % 32 == 0 and bmax % 64 == 0)
         self.h_alphas = torch.zeros(K, dtype=torch.float64).pin_memory()
         self.h_X = torch.zeros((K, N, bmax), dtype=torch.float32).pin_memory()
         self.h_Y = torch.empty((K, N, bmax), dtype=torch.complex64).pin_memory()
@@ -166,8 +166,7 @@ class _SlotSet:
         if route == "direct":
             self.plan.apply_direct(self.alphas, self.dcols[k], self.dX[k], out=self.dY[k], ws=self.dws)
         else:
-            self.plan.update_dev(self.alphas[:k], out=self.Q[:k], ws=self.uws)
-            apply_operator(self.Q[:k], self.X[:k], out=self.Y[:k], ws=self.aws)
+            self.plan.apply_dev(self.alphas[:k], self.X[:k], out=self.Y[:k], ws=self.ows)
 
     def _keys(self):
         return [("operator", k) for k in BUCKETS if k <= self.K] + [("direct", nb) for nb in self.dblocks]
@@ -185,7 +184,7 @@ class _SlotSet:
         self.stream.synchronize()
 
     def nbytes(self) -> int:
-        ts = [self.alphas, self.X, self.Q, self.Y, self.uws, self.aws, self.dws]
+        ts = [self.alphas, self.X, self.Y, self.ows, self.dws]
         ts += list(self.dX.values()) + list(self.dcols.values()) + list(self.dY.values())
         return sum(t.numel() * t.element_size() for t in ts)
 
@@ -193,7 +192,7 @@ class _SlotSet:
         ncols = sum(r.B for r in batch)
         nb = -(-ncols // 64)
         if self.dblocks and nb <= DIRECT_BLOCKS and (
-                self.route == "direct" or prefer_direct(len(batch), nb, self.plan.L)):
+                self.route == "direct" or prefer_direct(len(batch), nb, self.plan.L, self.real_route)):
             return ("direct", nb)
         k = next(b for b in BUCKETS if b >= len(batch)) if self.graphs else len(batch)
         return ("operator", k)

@@ -89,6 +89,9 @@ int main(void) {
          "exact workspace too small");
   expect(fgfrft_probe_write(NULL, 64, NULL), FGFRFT_EINVAL, "probe_write NULL");
   expect(fgfrft_probe_write(buf, 17, NULL), FGFRFT_EINVAL, "probe_write size");
+  expect(fgfrft_apply_dev(NULL, (const double*)buf, 1, buf, 0, 0, 64, buf, buf, 1 << 20, NULL), FGFRFT_EINVAL,
+         "apply_dev NULL plan");
+  if (fgfrft_apply_dev_workspace_bytes(NULL, 4, 64, 0, 0) != 0) { fprintf(stderr, "FAIL apply_dev ws\n"); ++failures; }
   expect(fgfrft_probe_update_traffic(NULL, 64, 4, 1, buf, NULL), FGFRFT_EINVAL, "probe_update_traffic NULL");
   expect(fgfrft_probe_update_traffic(buf, 96, 4, 1, buf, NULL), FGFRFT_EINVAL, "probe_update_traffic N");
   expect(fgfrft_probe_update_traffic(buf, 64, 0, 1, buf, NULL), FGFRFT_EINVAL, "probe_update_traffic tiles");

@@ -88,6 +88,10 @@ def test_null_and_small_arguments_are_rejected_on_host(L):
     assert L.fgfrft_apply_batched(None, a, 2, bq, ptrs, 0, ptrs, None, 0, None) == -1
     assert b"NULL plan" in L.fgfrft_last_error()
     assert L.fgfrft_apply_batched_workspace_bytes(None, 2, bq, 0) == 0
+    # apply with device orders: NULL plan, and no workspace size for a NULL plan
+    assert L.fgfrft_apply_dev(None, None, 1, None, 0, 0, 64, None, None, 0, None) == -1
+    assert b"NULL plan" in L.fgfrft_last_error()
+    assert L.fgfrft_apply_dev_workspace_bytes(None, 4, 64, 0, 0) == 0
     # traffic reference: NULL buffers, N not a multiple of 64, too many tiles (host-side refusals)
     assert L.fgfrft_probe_update_traffic(None, 64, 4, 1, None, None) == -1
     assert L.fgfrft_probe_update_traffic(0x100000, 96, 4, 1, 0x200000, None) == -1

@@ -120,3 +120,50 @@ def test_cases_around_the_real_route(case):
     for a, al in enumerate(alphas):
         Q = ref.combine(float(al)) if form == "split" else O.fgfrft_operator_standard(F, float(al), L)
         assert rel_fro(Y[a], Q @ X[a].astype(np.complex128)) <= tol, (case, a)
+
+
+@pytest.mark.parametrize("case", ["real_route", "complex_F", "complex_x"])
+def test_apply_dev_matches_apply_and_replays(case):
+    """fgfrft_apply_dev (orders on the device, one update launch) gives bitwise the result of
+    fgfrft_apply with all orders in one chunk, on the real-F route and on the complex-operator
+    route; captured in a graph it replays to the same result with eager work between replays."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import Plan
+    announce(f"apply_dev {case}")
+    N, L, n, B = 128, 12, 5, 64
+    rng = np.random.default_rng(21)
+    F = synth.haar_unitary(N, rng) if case == "complex_F" else _orth_with_minus1(N, 3, seed=7)
+    alphas = np.array([0.5, -1.3, 0.0, 1.75, -0.2])
+    X = synth.complex_signals((n, N, B), rng).astype(np.complex64) if case == "complex_x" else \
+        synth.real_signals((n, N, B), rng).astype(np.float32)
+    plan = Plan(torch.from_numpy(F).cuda(), L)
+    Xt = torch.from_numpy(X).cuda()
+    ref = plan.apply(alphas, Xt, chunk=n)
+    ad = torch.from_numpy(alphas).cuda()
+    xc = case == "complex_x"
+    ws = torch.empty(plan.apply_dev_workspace_bytes(n, B, x_complex=xc), dtype=torch.uint8, device="cuda")
+    Y = torch.empty_like(ref)
+    plan.apply_dev(ad, Xt, out=Y, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(Y, ref)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.apply_dev(ad, Xt, out=Y, ws=ws)      # warm-up on the capture stream
+    s.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        plan.apply_dev(ad, Xt, out=Y, ws=ws)
+    for _ in range(3):
+        Y.zero_()
+        junk = plan.apply(alphas[::-1].copy(), Xt, chunk=n)   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y, ref)
+    del junk
+    O_ref = O.Plan(F, L)
+    Xd = X.astype(np.complex128) if xc else X.astype(np.float64)
+    Yh = Y.cpu().numpy()
+    for a, al in enumerate(alphas):
+        assert rel_fro(Yh[a], O_ref.combine(float(al)) @ Xd[a]) <= TOL_FP32, a

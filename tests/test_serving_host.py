@@ -62,6 +62,10 @@ def test_route_choice_boundary():
     assert not prefer_direct(1000, 5, 32)
     # a shorter stack makes the operator route's per-order bytes relatively dearer
     assert prefer_direct(4, 2, 10) and not prefer_direct(3, 2, 10)
+    # the real-F operator route writes and reads half the bytes per order: twice the orders per block
+    assert not prefer_direct(19, 2, 32, True) and prefer_direct(20, 2, 32, True)
+    assert not prefer_direct(39, 3, 32, True) and prefer_direct(40, 3, 32, True)
+    assert all(prefer_direct(n, 1, 32, True) for n in (1, 2, 16))
 
 
 def test_poisson_trace_statistics():
