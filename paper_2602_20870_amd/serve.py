@@ -422,7 +422,8 @@ def run_trace(server: Server, trace, signals: dict, warmup: int = 0, keep_every:
     consumes its results would: holding every result of a long trace (gigabytes of host
     arrays) makes each new result array fresh, page-faulted memory.  The cyclic garbage
     collector is paused during the replay: its collections over the trace's many request
-    objects otherwise stall the scheduling loop for tens of milliseconds."""
+    objects otherwise stall the scheduling loop for tens of milliseconds.  While batches are in
+    flight the loop polls without sleeping (one host core busy)."""
     gc_was = gc.isenabled()
     gc.disable()
     try:
@@ -446,7 +447,9 @@ def _run_trace(server: Server, trace, signals: dict, warmup: int, keep_every: in
                 kept.append((i, fut))
             reqs.append(server.pending[gids[i]][-1])
             i += 1
-        if not server.step():
+        if not server.step() and server.inflight == 0:
+            # nothing running: sleep until the next arrival (at most 200 us); while batches run the
+            # loop polls their events again at once, so a completion is retired without a sleep's delay
             nxt = t_arr[i] - (time.perf_counter() - t0) if i < n else 20e-6
             time.sleep(max(0.0, min(nxt, 200e-6)))
     wall = time.perf_counter() - t0
