@@ -9,7 +9,7 @@ GPU, one launch) followed by the apply of each operator to its 64 signals.
 Inputs are resident in HBM before timing starts; the plan (offline stage) is
 built once, outside the timed region, as in the paper's own timings.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -699,7 +699,7 @@ def main():
                     help="only the Table IV workload (FGFRFT vs exact GFRFT online time, N = 1000..8000)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

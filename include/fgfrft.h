@@ -58,7 +58,7 @@ typedef enum {
   FGFRFT_ENOMEM = -4,        /* caller-provided buffer smaller than the stated size        */
   FGFRFT_EHIP = -5,          /* a HIP runtime call or kernel launch failed                 */
   FGFRFT_EDRIFT = -6,        /* FP64 power recurrence lost orthogonality (||M_n^H M_n - P_c||_F / sqrt(N) > 1e-9) */
-  FGFRFT_EUNSUPPORTED = -7   /* combination of sizes this build does not implement         */
+  FGFRFT_EUNSUPPORTED = -7   /* combination of sizes the library does not implement        */
 } fgfrft_status;
 
 /* Element type of F as handed to fgfrft_plan. */
