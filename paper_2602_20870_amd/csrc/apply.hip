@@ -509,6 +509,12 @@ fgfrft_status xsplit_launch(const float* X, int ldx, int ncols, int N, int nx, s
 
 size_t colscale_partial_bytes(int N, int nx, int B) { return align_up((size_t)nx * ceil_div(N, CR) * B * sizeof(float), 256); }
 
+fgfrft_status colmax_launch(const void* X, int x_complex, int N, int B, int nx, float* partial, hipStream_t s) {
+  k_colmax<<<dim3(ceil_div(B, 64) * nx, ceil_div(N, CR)), 256, 0, s>>>(X, x_complex, N, B, partial);
+  FG_LAUNCHED("column maxima");
+  return FGFRFT_OK;
+}
+
 fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx, float2* scale, float* partial,
                               hipStream_t s) {
   const int nch = ceil_div(N, CR);

@@ -66,6 +66,89 @@ __device__ __forceinline__ void dsplit(float v, short& hi, short& lo) {
   hi = __builtin_bit_cast(short, h);
   lo = __builtin_bit_cast(short, l);
 }
+// The matrix-core route's set-up in one launch, one workgroup per (64-column block, 32-row chunk):
+// the block's column scales from the column maxima of chunks of 64 rows (as k_colscale: 2^e with
+// max |x| 2^e in [2^13, 2^14)), the chunk's signals scaled and split into hi / lo parts in the
+// layout of xsplit_launch, and, in the chunk-0 workgroup, the block's coefficient rows (as k_dcoef).
+// The results are bitwise those of the three separate kernels; a call launches two kernels fewer.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_direct_prep(const float* __restrict__ X, int ldx, int ncols, int N,
+                                                     const float* __restrict__ colpart, int nchm,
+                                                     const double* __restrict__ alphas, int n_alpha,
+                                                     const int* __restrict__ col_order, int L, int ncp,
+                                                     float unscale, float* __restrict__ gam,
+                                                     short* __restrict__ Xs) {
+  __shared__ float s_sc[64];
+  const int nch = N / 32, bc = blockIdx.x, chunk = bc % nch, cb = bc / nch;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int col = cb * 64 + tid;
+    float sc = 0.f;
+    if (col < ncols) {
+      float m = 0.f;
+      for (int c = 0; c < nchm; ++c) m = fmaxf(m, colpart[(size_t)c * ldx + col]);
+      int e = 0;
+      if (m > 0.f && isfinite(m)) {
+        int E;
+        frexpf(m, &E);
+        e = 14 - E;
+        if (e > 100) e = 100;
+        if (e < -100) e = -100;
+      }
+      sc = ldexpf(1.f, e);
+    }
+    s_sc[tid] = sc;
+  }
+  __syncthreads();
+  // 8 values of column 64 cb + 32 c + l32 at k = 32 chunk + 16 ks + 8 lh .. + 7
+  const int lane = tid & 63, c = (tid >> 6) & 1, ks = (tid >> 7) & 1;
+  const int col = cb * 64 + 32 * c + (lane & 31);
+  const int k0 = chunk * 32 + 16 * ks + 8 * (lane >> 5);
+  const float sc = s_sc[32 * c + (lane & 31)];
+  shortx8 h, l;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float v = col < ncols ? X[(size_t)(k0 + j) * ldx + col] * sc : 0.f;
+    short hh, ll;
+    if (BF) {
+      const __bf16 bh = (__bf16)v;
+      const __bf16 bl = (__bf16)(v - (float)bh);
+      hh = __builtin_bit_cast(short, bh);
+      ll = __builtin_bit_cast(short, bl);
+    } else {
+      dsplit(v, hh, ll);
+    }
+    h[j] = hh;
+    l[j] = ll;
+  }
+  shortx8* dst = (shortx8*)(Xs + (((size_t)bc * 2 + ks) * 2 + c) * 2 * 64 * 8);
+  dst[lane] = h;
+  dst[64 + lane] = l;
+  if (chunk == 0) {
+    for (int idx = tid; idx < (2 * L + 4) * 64; idx += 256) {
+      const int t = idx >> 6, cc = cb * 64 + (idx & 63);
+      float v = 0.f;
+      if (cc < ncols) {
+        const int a = col_order[cc];
+        const double al = (a >= 0 && a < n_alpha) ? alphas[a] : __builtin_nan("");
+        if (!(fabs(al) < (double)L)) {
+          v = __builtin_nanf("");
+        } else {
+          double g;
+          if (t < L) g = sinc_pi(al - (double)(t + 1));
+          else if (t < 2 * L) g = sinc_pi(al + (double)(t - L + 1));
+          else if (t == 2 * L) g = cospi(al) - sinc_pi(al);
+          else if (t == 2 * L + 1) g = sinpi(al);
+          else if (t == 2 * L + 2) g = sinc_pi(al);
+          else g = 1.0 / ((double)unscale * (double)s_sc[idx & 63]);
+          v = (float)g;
+        }
+      }
+      gam[(size_t)t * ncp + cc] = v;
+    }
+  }
+}
+
 template <bool BF>
 __device__ __forceinline__ floatx16 dmma(shortx8 a, shortx8 b, floatx16 c) {
   if (BF)
@@ -513,13 +596,17 @@ fgfrft_status direct_launch(const Plan* p, const double* alphas_dev, int n_alpha
     FG_LAUNCHED("direct (plain)");
     return FGFRFT_OK;
   }
-  fgfrft_status rc = colscale_launch(X, 0, N, ldx, 1, w.xs, w.colpart, s);
+  fgfrft_status rc = colmax_launch(X, 0, N, ldx, 1, w.colpart, s);
   if (rc) return rc;
-  k_dcoef<<<ceil_div(nrow * d.ncp, 256), 256, 0, s>>>(alphas_dev, n_alpha, col_order_dev, ncols, d.ncp, L, w.xs,
-                                                        bf ? 1.0f : kStackScale, w.gam);
-  FG_LAUNCHED("direct coefficients");
-  rc = xsplit_launch((const float*)X, ldx, ncols, N, 1, 0, w.xs, 0, w.Xs, s, bf);
-  if (rc) return rc;
+  // scales, split signals and coefficient rows in one launch
+  const unsigned npre = (unsigned)(d.ncb * (N / 32));
+  if (bf)
+    k_direct_prep<true><<<npre, 256, 0, s>>>((const float*)X, ldx, ncols, N, w.colpart, ceil_div(N, 64), alphas_dev,
+                                             n_alpha, col_order_dev, L, d.ncp, 1.0f, w.gam, w.Xs);
+  else
+    k_direct_prep<false><<<npre, 256, 0, s>>>((const float*)X, ldx, ncols, N, w.colpart, ceil_div(N, 64), alphas_dev,
+                                              n_alpha, col_order_dev, L, d.ncp, kStackScale, w.gam, w.Xs);
+  FG_LAUNCHED("direct set-up");
   const size_t nb = (size_t)8 * ceil_div(d.nIB * d.G, 8) * d.ncb;
   if (nb > 0x7fffffff) {
     set_error("direct grid too large");

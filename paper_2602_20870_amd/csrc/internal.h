@@ -115,10 +115,12 @@ fgfrft_status coef_launch(const Plan* p, const double* alphas_dev, int n_alpha, 
 // Apply (apply.hip)
 size_t apply_ws_bytes(int N, int n_alpha, int B, int x_shared);
 // per-column power-of-two scales of X [nx][N][B] (max |x| s in [2^13, 2^14)), scale[(a, b)] = (s, 1/s);
-// partial: nx * ceil(N / 256) * B floats of scratch
+// partial: nx * ceil(N / 64) * B floats of scratch
 size_t colscale_partial_bytes(int N, int nx, int B);
 fgfrft_status colscale_launch(const void* X, int x_complex, int N, int B, int nx, float2* scale, float* partial,
                               hipStream_t s);
+// its first pass alone: partial[a][chunk][b] = max |X[a][i][b]| over the chunk's 64 rows
+fgfrft_status colmax_launch(const void* X, int x_complex, int N, int B, int nx, float* partial, hipStream_t s);
 
 // Signals split once for the matrix cores (apply.hip): real X [nx][N][ldx] (order stride xstride
 // floats, 0 = one block for all), columns scaled by xs[a * xs_stride + col].x, written as
