@@ -31,12 +31,12 @@ COPY_BYTES = 1 << 31          # plain device copy used as the counter and bandwi
 # then WRITE_SIZE, KiB per dispatch), each scaled by the same counter's reading for the plain
 # copy of COPY_BYTES that this script runs.  Valid only for the kernel sources with this digest:
 # once update.hip or internal.h change, the figure is reported as null until re-measured.
-UPDATE_TRAFFIC = {"fetch_bytes": 4362317681, "write_bytes": 34366226155,
-                  "source_sha256": "b7d961fcdb8523ae7153adbf20c6c889a172ae72f602b1ff7eb068585a51d5e3"}
+UPDATE_TRAFFIC = {"fetch_bytes": 4362316720, "write_bytes": 34365347584,
+                  "source_sha256": "80a71ad94fa4793f0a7b1bc340e59dc76448790d91f14ef1c112cc35e3974bb2"}
 # The same for one k_direct_pair launch over 64 signal columns of the knn4096 plan (FP16X2 stack;
 # direct.hip + internal.h).
-DIRECT_TRAFFIC = {"fetch_bytes": 2224949173, "write_bytes": 67108864, "ncols": 64,
-                  "source_sha256": "051fcb4c5eb5047fbbd57eaba18338c09bc5258cfad7b169e05c02cd7b517d67"}
+DIRECT_TRAFFIC = {"fetch_bytes": 2225043155, "write_bytes": 67108864, "ncols": 64,
+                  "source_sha256": "976f7fd6b914907f4d9b0d3af81919de5ac507984ebfc20bf7caa22637058140"}
 
 
 def log(msg):
