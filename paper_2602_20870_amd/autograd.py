@@ -50,9 +50,10 @@ class FractionalFilterFunction(torch.autograd.Function):
     """Y = FractionalFilterFunction.apply(X, alpha, h, plan): per order a,
     Y[a] = Q^{-alpha_a} diag(h[a]) Q^{alpha_a} X[a], a filter h in the fractional domain.
 
-    The operators of both orders are formed once in the forward pass and kept for the backward one,
-    where every product is again a plain apply (Q^{-a} = (Q^{a})^H, Proposition 3):
-      GM = Q^{a} GY,  dh = Re sum_b conj(GM) Z,  GZ = h GM,  dX = Q^{-a} GZ,
+    The operator Q^{a} is formed once in the forward pass and kept for the backward one; since
+    Q^{-a} = (Q^{a})^H (Proposition 3) every product with Q^{-a} is an adjoint apply of Q^{a}, so no
+    second operator is formed:
+      Y = (Q^{a})^H M,  GM = Q^{a} GY,  dh = Re sum_b conj(GM) Z,  GZ = h GM,  dX = (Q^{a})^H GZ,
       dalpha = Re<GZ X^H, dQ/da (a)> - Re<GY M^H, dQ/da (-a)>   (Proposition 4, the library's
     order gradient without its signal part), with Z = Q^{a} X and M = h Z.
     X: float32 or complex64 [n, N, B] or shared [N, B]; h: float32, broadcastable to [n, N, B]
@@ -65,18 +66,17 @@ class FractionalFilterFunction(torch.autograd.Function):
         a = alpha.detach().to("cpu", torch.float64).reshape(-1).numpy()
         Xc = X.detach().contiguous()
         Qp = plan.update(a)
-        Qm = plan.update(-a)
         Z = apply_operator(Qp, Xc)
         M = (h.detach() * Z).contiguous()
-        Y = apply_operator(Qm, M)
+        Y = apply_operator(Qp, M, adjoint=True)     # Q^{-a} M
         ctx.plan = plan
-        ctx.save_for_backward(Xc, alpha, h, Qp, Qm, Z, M)
+        ctx.save_for_backward(Xc, alpha, h, Qp, Z, M)
         return Y
 
     @staticmethod
     def backward(ctx, GY: torch.Tensor):
         from .ops import apply_operator
-        X, alpha, h, Qp, Qm, Z, M = ctx.saved_tensors
+        X, alpha, h, Qp, Z, M = ctx.saved_tensors
         plan: Plan = ctx.plan
         a = alpha.detach().to("cpu", torch.float64).reshape(-1).numpy()
         gy = GY.to(torch.complex64).contiguous()
@@ -84,7 +84,7 @@ class FractionalFilterFunction(torch.autograd.Function):
         GZ = (h.detach() * GM).contiguous()
         dX = dh = d_alpha = None
         if ctx.needs_input_grad[0]:
-            gx = apply_operator(Qm, GZ)
+            gx = apply_operator(Qp, GZ, adjoint=True)   # Q^{-a} GZ
             if not X.is_complex():
                 gx = gx.real
             dX = gx.sum(dim=0) if X.dim() == 2 else gx

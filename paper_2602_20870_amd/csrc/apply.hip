@@ -260,17 +260,22 @@ struct Apply2Layout {
 
 // PRE (real signals, K2 = 32 or 64): X is the pre-split signal block of xsplit_launch, so a
 // stage's B fragments are plain 16-byte LDS reads (no per-wave split of the same signals).
-template <bool XC, bool YREAL, int NS, int K2, bool PRE = false, int RG = 4, int KSPL = 1>
+// ADJ (RG = 4, KSPL = 1): Y[a] = Q[a]^H X[a].  The 128 output rows i0.. of Q^H are the columns i0.. of
+// Q, so a stage holds the k rows k0 .. k0 + K2 - 1 of Q restricted to those columns (one contiguous
+// 1 KB run per row, one load instruction each) and a wave reads its operand fragments down the
+// stage's columns, with the imaginary parts negated (Proposition 3: Q^{-alpha} = (Q^alpha)^H).
+template <bool XC, bool YREAL, int NS, int K2, bool PRE = false, int RG = 4, int KSPL = 1, bool ADJ = false>
 __global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_apply2(
     const cplx64* __restrict__ Q, int N, int n_alpha, const void* __restrict__ X, int x_shared, int B,
     const float2* __restrict__ xscale, void* __restrict__ Y, int nrb, int ncb) {
   static_assert(!PRE || (!XC && K2 % 32 == 0), "pre-split signals: real, k stages of whole 32-row chunks");
   static_assert((K2 / 16) % KSPL == 0, "whole 16-wide k steps per part");
+  static_assert(!ADJ || (RG == 4 && KSPL == 1 && !PRE), "adjoint: 128 rows, one k part, signals split per wave");
   using LY = Apply2Layout<XC, K2, RG>;
   constexpr int XE = XC ? 8 : 4, CPR = LY::CPR, RPI = LY::RPI, SW = LY::SW, NW = RG * KSPL;
   constexpr int QLW = LY::QB / (1024 * NW), XLW = LY::XB / (1024 * NW), LW = QLW + XLW;   // loads per wave
   static_assert(QLW * 1024 * NW == LY::QB && XLW * 1024 * NW == LY::XB, "whole loads per wave");
-  static_assert((RPI * NW) % SW == 0, "row swizzle constant per wave");
+  static_assert(ADJ || (RPI * NW) % SW == 0, "row swizzle constant per wave");
   constexpr int KSW = K2 / 16 / KSPL;                 // 16-wide k steps per wave and stage
   extern __shared__ __align__(16) char sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -296,8 +301,11 @@ __global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_appl
   // the next rows of k of the 64 signals.
   const int wv = __builtin_amdgcn_readfirstlane(wave);
   const int qrow = lane / CPR;
+  // ADJ: lane's 16 bytes are columns i0 + 2 lane, + 1 of a k row; past N (the last row block when
+  // N % 128 != 0; N % 16 == 0 keeps pairs whole) any valid pair, never written back
   const uint32_t qoff =
-      (uint32_t)(((size_t)qrow * N + 2 * ((lane % CPR) ^ ((RPI * wv + qrow) % SW))) * 8);
+      ADJ ? (uint32_t)((i0 + 2 * lane < N ? 2 * lane : N - 2 - i0) * 8)
+          : (uint32_t)(((size_t)qrow * N + 2 * ((lane % CPR) ^ ((RPI * wv + qrow) % SW))) * 8);
   const uint32_t xoff_l = XC ? (uint32_t)(((size_t)(lane >> 5) * B + 2 * (lane & 31)) * 8)
                              : (uint32_t)(((size_t)(lane >> 4) * B + 4 * (lane & 15)) * 4);
   auto issue = [&](int it) {
@@ -306,9 +314,13 @@ __global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_appl
 #pragma unroll
     for (int q = 0; q < QLW; ++q) {
       const int i = wv + NW * q;
-      const int row0 = i0 + RPI * i < N ? i0 + RPI * i : N - RPI;
-      const char* gb = Qa + ((size_t)row0 * N + k0) * 8;
-      lds_dma16(gb + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
+      if (ADJ) {   // k row k0 + i, columns i0 ..
+        lds_dma16(Qa + ((size_t)(k0 + i) * N + i0) * 8 + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
+      } else {
+        const int row0 = i0 + RPI * i < N ? i0 + RPI * i : N - RPI;
+        const char* gb = Qa + ((size_t)row0 * N + k0) * 8;
+        lds_dma16(gb + qoff, __builtin_amdgcn_readfirstlane(lds_addr(st + i * 1024)));
+      }
     }
 #pragma unroll
     for (int q = 0; q < XLW; ++q) {
@@ -346,15 +358,26 @@ __global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_appl
     const int ks = kp * KSW + kk;
     // A: Q[r][16 ks + 8 lh .. + 7] (4 chunks of two complex values)
     shortx8 arh, arl, aih, ail;
+    if (ADJ) {
+      // A[r][k] = conj(Q[k][i0 + r]): down column r of the stage, k = 16 ks + 8 lh + q
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = (8 * ks + 4 * lh + q) ^ (r % SW);
-      const float4 v = *(const float4*)(st + r * LY::QROW + c * 16);
-      short h, l;
-      split_h(v.x * kStackScale, h, l); arh[2 * q] = h; arl[2 * q] = l;
-      split_h(v.y * kStackScale, h, l); aih[2 * q] = h; ail[2 * q] = l;
-      split_h(v.z * kStackScale, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
-      split_h(v.w * kStackScale, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+      for (int q = 0; q < 8; ++q) {
+        const float2 v = *(const float2*)(st + (16 * ks + 8 * lh + q) * 1024 + r * 8);
+        short h, l;
+        split_h(v.x * kStackScale, h, l); arh[q] = h; arl[q] = l;
+        split_h(-v.y * kStackScale, h, l); aih[q] = h; ail[q] = l;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = (8 * ks + 4 * lh + q) ^ (r % SW);
+        const float4 v = *(const float4*)(st + r * LY::QROW + c * 16);
+        short h, l;
+        split_h(v.x * kStackScale, h, l); arh[2 * q] = h; arl[2 * q] = l;
+        split_h(v.y * kStackScale, h, l); aih[2 * q] = h; ail[2 * q] = l;
+        split_h(v.z * kStackScale, h, l); arh[2 * q + 1] = h; arl[2 * q + 1] = l;
+        split_h(v.w * kStackScale, h, l); aih[2 * q + 1] = h; ail[2 * q + 1] = l;
+      }
     }
     shortx8 bxrh[2], bxrl[2], bxih[2], bxil[2];
     if (PRE) {
@@ -545,7 +568,7 @@ static void launch_apply_t(dim3 g, hipStream_t s, const cplx64* Q, int N, int n_
   k_apply<ADJ, XC, YR><<<g, 256, 0, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
-template <bool XC, bool YR, int NS, int K2, bool PRE = false, int RG = 4, int KSPL = 1>
+template <bool XC, bool YR, int NS, int K2, bool PRE = false, int RG = 4, int KSPL = 1, bool ADJ = false>
 static void launch_apply2_t(hipStream_t s, const cplx64* Q, int N, int n_alpha, const void* X, int x_shared, int B,
                             const float2* sc, void* Y, int ncb) {
   constexpr int lds = NS * Apply2Layout<XC, K2, RG>::SB;
@@ -553,8 +576,8 @@ static void launch_apply2_t(hipStream_t s, const cplx64* Q, int N, int n_alpha, 
   static_assert(KSPL == 1 || RG * KSPL * (YR ? 32 : 64) * 64 * 4 <= lds, "the parts' sums fit the ring");
   const int nrb = ceil_div(N, 32 * RG);
   const unsigned g = (unsigned)(8 * ceil_div(n_alpha, 8) * nrb * ncb);   // bounded by the caller
-  (void)raise_lds_limit((const void*)k_apply2<XC, YR, NS, K2, PRE, RG, KSPL>, lds);   // a failure surfaces at the launch
-  k_apply2<XC, YR, NS, K2, PRE, RG, KSPL><<<g, 64 * RG * KSPL, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
+  (void)raise_lds_limit((const void*)k_apply2<XC, YR, NS, K2, PRE, RG, KSPL, ADJ>, lds);   // a failure surfaces at the launch
+  k_apply2<XC, YR, NS, K2, PRE, RG, KSPL, ADJ><<<g, 64 * RG * KSPL, lds, s>>>(Q, N, n_alpha, X, x_shared, B, sc, Y, nrb, ncb);
 }
 
 
@@ -892,6 +915,22 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
     if (rc) return rc;
   }
   // streaming kernel: k stages of 32 (real signals, 2-stage ring) or 16 (complex, 3-stage ring)
+  if (adjoint && N % (x_complex ? 16 : 32) == 0 && B % 64 == 0) {
+    const int ncb = B / 64;
+    if ((size_t)8 * ceil_div(n_alpha, 8) * ceil_div(N, 128) * ncb > 0x7fffffff) {
+      set_error("apply grid too large");
+      return FGFRFT_EUNSUPPORTED;
+    }
+    const cplx64* q = (const cplx64*)Q;
+    switch ((x_complex ? 2 : 0) | (y_real ? 1 : 0)) {
+      case 0: launch_apply2_t<false, false, 2, 32, false, 4, 1, true>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+      case 1: launch_apply2_t<false, true, 2, 32, false, 4, 1, true>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+      case 2: launch_apply2_t<true, false, 3, 16, false, 4, 1, true>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+      case 3: launch_apply2_t<true, true, 3, 16, false, 4, 1, true>(s, q, N, n_alpha, X, x_shared, B, sc, Y, ncb); break;
+    }
+    FG_LAUNCHED("apply (adjoint)");
+    return FGFRFT_OK;
+  }
   if (!adjoint && N % (x_complex ? 16 : 32) == 0 && B % 64 == 0) {
     const int ncb = B / 64;
     const size_t nblocks = (size_t)8 * ceil_div(n_alpha, 8) * ceil_div(N, 64) * ncb;   // the largest grid below

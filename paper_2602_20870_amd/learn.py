@@ -68,9 +68,19 @@ class PointCloudDenoiser(torch.nn.Module):
         self.h = torch.nn.Parameter(torch.ones(channels, plan.N, 1, dtype=torch.float32, device=dev))
 
     def forward(self, Y: torch.Tensor) -> torch.Tensor:
-        X = torch.matmul(Y, self.W_in).permute(2, 1, 0).contiguous()      # [C, N, clouds]
-        Zi = fractional_filter(X, self.alpha, self.h, self.plan)
-        return torch.matmul(Zi.real.permute(2, 1, 0), self.W_out)         # [clouds, N, c_in]
+        # The lift and the projection contract over 3 or C values per (point, cloud); written as
+        # broadcast multiply-adds in the filter's [C, N, clouds] layout their weight gradients are
+        # plain reductions, not GEMMs with a contraction over all N x clouds positions and a 3 x C
+        # result (which the BLAS library runs with little parallelism).
+        Yt = Y.permute(2, 1, 0)                                            # [c_in, N, clouds]
+        X = self.W_in[0][:, None, None] * Yt[0]
+        for d in range(1, Yt.shape[0]):
+            X = X + self.W_in[d][:, None, None] * Yt[d]
+        Zi = fractional_filter(X.contiguous(), self.alpha, self.h, self.plan)   # [C, N, clouds]
+        Zr = Zi.real
+        out = torch.stack([(Zr * self.W_out[:, e][:, None, None]).sum(0) for e in range(self.W_out.shape[1])],
+                          dim=-1)                                          # [N, clouds, c_in]
+        return out.permute(1, 0, 2)                                        # [clouds, N, c_in]
 
 
 def train(model: torch.nn.Module, loss_fn, steps: int, lr: float = 0.01, params=None) -> list[float]:

@@ -269,6 +269,33 @@ def test_apply_operator_adjoint_and_real_output():
         assert rel_fro(Yr[a], (Q32[a] @ X32[a]).real) <= TOL_FP32
 
 
+@pytest.mark.parametrize("xc,N,B", [(True, 144, 64),    # complex signals, ragged 128-column block
+                                     (True, 16, 64),     # one block narrower than a load row
+                                     (False, 192, 128)])  # real signals, two signal blocks
+def test_apply_operator_adjoint_streaming(xc, N, B):
+    """Y = Q^H X through the streaming kernel's adjoint form (Q's columns as operand rows, imaginary
+    parts negated), for complex and real-part outputs, against the FP64 product per order."""
+    torch = torch_cuda()
+    from paper_2602_20870_amd import apply_operator
+    announce(f"apply_operator adjoint xc={xc} N={N} B={B}")
+    rng = np.random.default_rng(N + B + (7 if xc else 0))
+    n = 3
+    Q = (rng.standard_normal((n, N, N)) + 1j * rng.standard_normal((n, N, N))) / np.sqrt(N)
+    X = (rng.standard_normal((n, N, B)) + 1j * rng.standard_normal((n, N, B))) if xc else rng.standard_normal((n, N, B))
+    X = X * np.exp(rng.uniform(-3, 3, (1, 1, B)))                       # columns over decades
+    Qt = torch.from_numpy(Q.astype(np.complex64)).cuda()
+    Xt = torch.from_numpy(X.astype(np.complex64 if xc else np.float32)).cuda()
+    Q32 = Q.astype(np.complex64).astype(np.complex128)
+    X32 = X.astype(np.complex64 if xc else np.float32).astype(np.complex128)
+    Y = apply_operator(Qt, Xt, adjoint=True).cpu().numpy()
+    Yr = apply_operator(Qt, Xt, adjoint=True, y_real=True).cpu().numpy()
+    for a in range(n):
+        ref = Q32[a].conj().T @ X32[a]
+        for b in range(B):
+            assert rel_fro(Y[a][:, b], ref[:, b]) <= TOL_FP32, (a, b)
+            assert rel_fro(Yr[a][:, b], ref[:, b].real) <= TOL_FP32, (a, b)
+
+
 @pytest.mark.parametrize("N,B", [(192, 64), (128, 128)])
 def test_apply_operator_real_signals_both_outputs(N, B):
     """Real signals through the streaming apply with 64-wide k stages (the two wave halves'
