@@ -54,8 +54,10 @@ class FractionalFilterFunction(torch.autograd.Function):
     Q^{-a} = (Q^{a})^H (Proposition 3) every product with Q^{-a} is an adjoint apply of Q^{a}, so no
     second operator is formed:
       Y = (Q^{a})^H M,  GM = Q^{a} GY,  dh = Re sum_b conj(GM) Z,  GZ = h GM,  dX = (Q^{a})^H GZ,
-      dalpha = Re<GZ X^H, dQ/da (a)> - Re<GY M^H, dQ/da (-a)>   (Proposition 4, the library's
-    order gradient without its signal part), with Z = Q^{a} X and M = h Z.
+      dalpha = Re<GZ X^H, dQ/da (a)> - Re<GY M^H, dQ/da (-a)>   (Proposition 4), with Z = Q^{a} X
+    and M = h Z.  Differentiating Q^{-a} = (Q^{a})^H gives dQ/da (-a) = -(dQ/da (a))^H, so the second
+    term is Re<M GY^H, dQ/da (a)> and dalpha is one order gradient at a (the library's, without its
+    signal part) of the outer product [GZ | M] [X | GY]^H over the two signal blocks side by side.
     X: float32 or complex64 [n, N, B] or shared [N, B]; h: float32, broadcastable to [n, N, B]
     (e.g. [n, N, 1] or [N, 1]); returns complex64 [n, N, B].
     """
@@ -91,9 +93,14 @@ class FractionalFilterFunction(torch.autograd.Function):
         if ctx.needs_input_grad[2]:
             dh = (GM.conj() * Z).real.sum_to_size(h.shape)
         if ctx.needs_input_grad[1]:
-            g1, _ = plan.grad(a, X, GZ, want_dX=False)
-            g2, _ = plan.grad(-a, M, gy, want_dX=False)
-            d_alpha = torch.from_numpy(g1 - g2).to(device=alpha.device, dtype=alpha.dtype).reshape(alpha.shape)
+            n = a.size
+            Xb = X.to(torch.complex64)
+            if Xb.dim() == 2:
+                Xb = Xb.expand(n, *Xb.shape)
+            Xcat = torch.cat([Xb, gy], dim=-1).contiguous()       # [X | GY]
+            Gcat = torch.cat([GZ, M], dim=-1).contiguous()        # [GZ | M]
+            g, _ = plan.grad(a, Xcat, Gcat, want_dX=False)
+            d_alpha = torch.from_numpy(g).to(device=alpha.device, dtype=alpha.dtype).reshape(alpha.shape)
         return dX, d_alpha, dh, None
 
 
