@@ -786,9 +786,9 @@ __global__ __launch_bounds__(64 * RG * KSPL, RG * KSPL == 4 ? 2 : 1) void k_appl
   }
 }
 
-// Launch of the real-operator apply.  N % 64 == 0: 64-wide stages (256-byte R row runs), eight waves
-// over two k parts, three stages of 48 KB, one workgroup per CU; else 32-wide stages, four waves,
-// three stages of 24 KB, two workgroups per CU.  Measured on knn4096 (real-F call, 256 orders x 64
+// Launch of the real-operator apply.  N % 64 == 0 and B <= 128: 64-wide stages (256-byte R row runs),
+// eight waves over two k parts, three stages of 48 KB, one workgroup per CU; else 32-wide stages,
+// four waves, three stages of 24 KB, two workgroups per CU.  Measured on knn4096 (real-F call, 256 orders x 64
 // signals): 8.10 against 8.21 ms; 64 rows x 128-wide stages (512-byte runs, two stages of 64 KB)
 // 8.42 ms, 128 rows x 64-wide with two stages 8.42 ms.
 template <bool DXO>
@@ -811,7 +811,8 @@ static fgfrft_status launch_apply_real(hipStream_t s, const float* R, int N, int
   static_assert(3 * ApplyRealLayout<64, 4>::SB <= 160 * 1024 && 3 * ApplyRealLayout<32, 4>::SB <= 80 * 1024,
                 "rings fit the LDS");
   static_assert(8 * 32 * 64 * 4 <= 3 * ApplyRealLayout<64, 4>::SB, "the parts' sums fit the ring");
-  if (N % 64 == 0) return go(k_apply_real<DXO, 64, 3, 4, 2>, 3, 4, 2, ApplyRealLayout<64, 4>::SB);
+  // as the complex-operator apply: the wide stages while the call is bound by the operators' bytes
+  if (N % 64 == 0 && B <= 128) return go(k_apply_real<DXO, 64, 3, 4, 2>, 3, 4, 2, ApplyRealLayout<64, 4>::SB);
   return go(k_apply_real<DXO, 32, 3, 4, 1>, 3, 4, 1, ApplyRealLayout<32, 4>::SB);
 }
 
@@ -939,7 +940,11 @@ fgfrft_status apply_launch(const void* Q, int N, int n_alpha, int adjoint, const
       return FGFRFT_EUNSUPPORTED;
     }
     const cplx64* q = (const cplx64*)Q;
-    const bool wide = N % 64 == 0;   // 64-wide k stages (512-byte Q row runs)
+    // 64-wide k stages (512-byte Q row runs, one workgroup per CU) while the call is bound by the
+    // operators' bytes (up to two 64-signal blocks); wider signal blocks re-read each operator from
+    // the caches and are bound by the matrix cores, where two workgroups per CU with 32-wide stages
+    // do better (32 operators x 1024 shared signals at N = 8192: 27.9 against 29.6 ms)
+    const bool wide = N % 64 == 0 && B <= 128;
     if (pre) {
       if (wide && y_real) launch_apply2_t<false, true, 2, 64, true, 4, 2>(s, q, N, n_alpha, Xs, x_shared, B, sc, Y, ncb);
       else if (wide) launch_apply2_t<false, false, 2, 64, true, 4, 2>(s, q, N, n_alpha, Xs, x_shared, B, sc, Y, ncb);
