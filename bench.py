@@ -36,7 +36,7 @@ UPDATE_TRAFFIC = {"fetch_bytes": 4362316720, "write_bytes": 34365347584,
 # The same for one k_direct_pair launch over 64 signal columns of the knn4096 plan (FP16X2 stack;
 # direct.hip + internal.h).
 DIRECT_TRAFFIC = {"fetch_bytes": 2225043155, "write_bytes": 67108864, "ncols": 64,
-                  "source_sha256": "976f7fd6b914907f4d9b0d3af81919de5ac507984ebfc20bf7caa22637058140"}
+                  "source_sha256": "fd3bc293a225be9b1a52c6790e40e76d8b0ebd80473cefe1c6f3de21a336cf3c"}
 
 
 def log(msg):

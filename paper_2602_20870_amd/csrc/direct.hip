@@ -7,7 +7,7 @@
 //
 // Matrix-core kernel (real F, real X, N % 32 == 0; `k_direct_pair` below): the signals are split
 // once into fp16 hi/lo (after a power-of-two scale per column) in the order the matrix cores read
-// them (xsplit_launch, shared with the apply); every resident tile M_n[I, J] feeds both M_n X
+// them (`k_direct_prep`, in the apply's split layout); every resident tile M_n[I, J] feeds both M_n X
 // (rows I) and M_n^T X (rows J), so the stored adjoints are not read; partial sums of row blocks,
 // runs and waves are added in a fixed order by a second kernel, with the identity term c_0 X.
 //
