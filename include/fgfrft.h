@@ -184,7 +184,9 @@ FGFRFT_API fgfrft_status fgfrft_update_dev_static(fgfrft_plan_t plan, const doub
  * Apply to graph signals (Definition 2)
  * ------------------------------------------------------------------------- */
 
-/* Workspace bytes for fgfrft_apply_operator (per-signal scale table). */
+/* Workspace bytes for fgfrft_apply_operator: the per-signal scale table and its partial maxima and,
+ * for real signals taken by the streaming kernel with pre-split signals, the signals split into
+ * fp16 hi / lo parts (4 bytes per signal value). */
 FGFRFT_API size_t fgfrft_apply_operator_workspace_bytes(int N, int n_alpha, int B, int x_shared);
 
 /* Y[a] = op(Q[a]) X[a] for a = 0..n_alpha-1 with op = identity (adjoint = 0)
