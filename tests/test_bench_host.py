@@ -23,3 +23,16 @@ def test_algorithmic_byte_counts():
     # per order 8 N^2 written plus (L+2) 4 N^2 of stack and projector read once per call
     assert bench.update_algorithmic_bytes(4096, 32, 256) == 256 * 8 * 4096 ** 2 + 34 * 4 * 4096 ** 2
     assert bench.apply_algorithmic_bytes(4096, 64, 256) == 256 * (8 * 4096 ** 2 + 12 * 4096 * 64)
+
+
+def test_stored_traffic_counters_belong_to_the_committed_kernels():
+    # the HBM byte counts the line reports were taken on these exact sources; a kernel edit without
+    # new counter runs must show up here (the bench would then report the traffic as null)
+    assert bench.UPDATE_TRAFFIC["source_sha256"] == bench.update_source_digest()
+    assert bench.DIRECT_TRAFFIC["source_sha256"] == bench.source_digest("direct.hip")
+    # and they sit just above the algorithmic bytes: no kernel re-reads its operands
+    alg = bench.update_algorithmic_bytes(4096, 32, 256)
+    assert 1.0 <= bench.update_traffic() / alg < 1.1
+    d = bench.DIRECT_TRAFFIC
+    d_alg = 33 * 4 * 4096 ** 2 + 12 * 4096 * d["ncols"]    # (L+1) 4N^2 of stack and P, 12 N per column
+    assert 0.99 <= (d["fetch_bytes"] + d["write_bytes"]) / d_alg < 1.1
