@@ -260,6 +260,84 @@ def _sampled_term_rows(variant):
     return f
 
 
+def _exact_grad_no_theta(F, alpha, decomposition=None):
+    from oracle import fgfrft as m
+    Z, theta, _ = decomposition if decomposition is not None else m.spectral_decomposition(F)
+    return (Z * (1j * np.exp(1j * alpha * theta))[None, :]) @ Z.conj().T   # slip: the factor theta dropped
+
+
+def _dQ_eigen_P_sign(F, alpha, L, tau=1e-6, decomposition=None):
+    from oracle import fgfrft as m
+    Z, theta, m1 = decomposition if decomposition is not None else m.spectral_decomposition(F, tau)
+    d = m.coefficient_derivatives(alpha, L)
+    n = np.arange(-L, L + 1)
+    g = np.exp(1j * np.outer(theta, n)) @ d
+    g[m1] = -1j * np.pi * np.exp(1j * np.pi * alpha)   # slip: sign of the -1 eigenspace term
+    return (Z * g[None, :]) @ Z.conj().T
+
+
+def _operator_eigen_conj_phase(F, alpha, L, tau=1e-6, decomposition=None):
+    from oracle import fgfrft as m
+    Z, theta, m1 = decomposition if decomposition is not None else m.spectral_decomposition(F, tau)
+    c = m.coefficients(alpha, L)
+    n = np.arange(-L, L + 1)
+    q = np.exp(-1j * np.outer(theta, n)) @ c           # slip: e^{-j n theta}
+    q[m1] = np.exp(1j * np.pi * alpha)
+    return (Z * q[None, :]) @ Z.conj().T
+
+
+def _parseval_tail_short(alpha, L):
+    from oracle import fgfrft as m
+    c = m.coefficients(alpha, L)[1:-1]                 # slip: the n = +-L terms left in the tail
+    return float(1.0 - np.sum(c * c))
+
+
+def _parseval_prediction_full_N(alpha, L, N, r_minus1=0):
+    from oracle import fgfrft as m
+    return m.parseval_tail(alpha, L)                   # slip: the (N - r_{-1}) / N factor dropped
+
+
+def _block_errors_c_whole(Q, Fa, P):
+    E = Q - Fa
+    return dict(E_total=float(np.linalg.norm(E)), E_m1=float(np.linalg.norm(P @ E @ P)),
+                E_c=float(np.linalg.norm(E)))          # slip: P_c dropped from the complementary block
+
+
+def _apply_transpose(Q, X):
+    return Q.T @ X                                     # slip: Q^T x
+
+
+def _unitarity_no_conj(F):
+    n = F.shape[0]
+    return float(np.max(np.abs(F.T @ F - np.eye(n))))  # slip: F^T F
+
+
+def _derivatives_taylor_sign(alpha, L):
+    n = np.arange(-L, L + 1, dtype=np.float64)
+    x = alpha - n
+    out = np.empty_like(x)
+    small = np.abs(x) < 1e-4
+    xs = x[small]
+    out[small] = (np.pi ** 2) * xs / 3.0               # slip: sign of the series near integers
+    xb = x[~small]
+    out[~small] = (np.cos(np.pi * xb) - np.sin(np.pi * xb) / (np.pi * xb)) / xb
+    return out
+
+
+def _residual_short_sum(theta, alpha, L):
+    from oracle import fgfrft as m
+    theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    c = m.coefficients(alpha, L)[:-1]                  # slip: the sum stops at n = L - 1
+    n = np.arange(-L, L)
+    return np.exp(1j * alpha * theta) - np.exp(1j * np.outer(theta, n)) @ c
+
+
+def _frobenius_exact_keeps_minus1(theta, in_minus1, alpha, L):
+    from oracle import fgfrft as m
+    th = np.asarray(theta)                             # slip: I_{-1} left in the sum
+    return float(np.sqrt(np.sum(np.abs(m.truncation_residual(th, alpha, L)) ** 2)))
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -293,6 +371,17 @@ MUTATIONS = {
     "combine_many_coefficients_unreversed": ("fgfrft_combine_many", _combine_many_coefficients_unreversed),
     "sampled_term_rows_no_conj": ("sampled_term_rows", _sampled_term_rows("no_conj")),
     "sampled_term_rows_inverse_rows": ("sampled_term_rows", _sampled_term_rows("inverse_rows")),
+    "exact_grad_no_theta": ("gfrft_exact_grad", _exact_grad_no_theta),
+    "dQ_eigen_P_sign": ("dQ_dalpha_eigen", _dQ_eigen_P_sign),
+    "operator_eigen_conj_phase": ("fgfrft_operator_eigen", _operator_eigen_conj_phase),
+    "parseval_tail_short": ("parseval_tail", _parseval_tail_short),
+    "parseval_prediction_full_N": ("parseval_nmse_prediction", _parseval_prediction_full_N),
+    "block_errors_c_whole": ("block_errors", _block_errors_c_whole),
+    "apply_transpose": ("apply", _apply_transpose),
+    "unitarity_no_conj": ("unitarity_defect", _unitarity_no_conj),
+    "derivatives_taylor_sign": ("coefficient_derivatives", _derivatives_taylor_sign),
+    "residual_short_sum": ("truncation_residual", _residual_short_sum),
+    "frobenius_exact_keeps_minus1": ("frobenius_error_exact", _frobenius_exact_keeps_minus1),
 }
 
 _ORIG: dict = {}
