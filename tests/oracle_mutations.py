@@ -338,6 +338,84 @@ def _frobenius_exact_keeps_minus1(theta, in_minus1, alpha, L):
     return float(np.sqrt(np.sum(np.abs(m.truncation_residual(th, alpha, L)) ** 2)))
 
 
+def _operator_integer_no_adjoint(F, alpha, L, tau=1e-6, decomposition=None, stack=None):
+    from oracle import fgfrft as m
+    F = np.asarray(F)
+    if float(alpha).is_integer():
+        Fm = np.linalg.matrix_power(F.astype(np.complex128), abs(int(alpha)))
+        return Fm                                      # slip: F^{-m} returned as F^m
+    return _ORIG["fgfrft_operator"](F, alpha, L, tau, decomposition, stack)
+
+
+def _grad_variant(variant):
+    def f(P, M, alphas, X, GY, x_real=None):
+        from oracle import fgfrft as m
+        X = np.asarray(X)
+        if x_real is None:
+            x_real = np.isrealobj(X)
+        dal = np.empty(len(alphas))
+        dX = np.empty(X.shape, dtype=np.float64 if x_real else np.complex128)
+        for a, al in enumerate(alphas):
+            Q = m.fgfrft_combine(P, M, al)
+            D = m.dQ_dalpha(P, M, al)
+            GQ = GY[a] @ X[a].conj().T
+            if variant == "inner_no_conj":
+                dal[a] = float(np.real(np.sum(GQ * D)))          # slip: <A, B> without conj(A)
+            else:
+                dal[a] = float(np.real(np.sum(GQ.conj() * D)))
+            g = Q @ GY[a] if variant == "dX_with_Q" else Q.conj().T @ GY[a]   # slip (dX_with_Q): Q, not Q^H
+            dX[a] = g.real if x_real else g
+        return dal, dX
+    return f
+
+
+def _pointwise_bound_no_abs(theta, alpha, L):
+    theta = np.asarray(theta, dtype=np.float64)
+    return (np.sin(np.pi * alpha) / (np.pi * np.cos(theta / 2.0))      # slip: |sin(pi alpha)| lost
+            * (1.0 / (L + 1 - alpha) + 1.0 / (L + 1 + alpha)))
+
+
+def _frobenius_simplified_ccmax(theta, in_minus1, alpha, L):
+    th = np.asarray(theta)[~np.asarray(in_minus1)]
+    cc = float(np.max(np.abs(np.cos(th / 2.0))))       # slip: the largest cos(theta/2), not the smallest
+    pre = 2 * (L + 1) * np.sqrt(th.size) * abs(np.sin(np.pi * alpha))
+    return float(pre / (np.pi * cc * ((L + 1) ** 2 - alpha ** 2)))
+
+
+def _coefficients_integer_zero(alpha, L):
+    n = np.arange(-L, L + 1, dtype=np.float64)
+    x = alpha - n
+    out = np.zeros_like(x)                              # slip: c_n(n) = 0 instead of 1
+    nz = x != 0.0
+    out[nz] = np.sin(np.pi * x[nz]) / (np.pi * x[nz])
+    return out
+
+
+def _power_stack_no_Pc(F, Pc, L):
+    M = [np.array(Pc, dtype=np.result_type(F, Pc))]
+    Fn = np.eye(F.shape[0], dtype=np.result_type(F, Pc))
+    for _ in range(L):
+        Fn = F @ Fn
+        M.append(Fn)                                    # slip: M_n = F^n, P_c dropped
+    return M
+
+
+def _spectral_theta_conj(F, tau=1e-6):
+    Z, theta, m1 = _ORIG["spectral_decomposition"](F, tau)
+    theta = -theta                                       # slip: phases of the conjugate eigenvalues
+    theta[m1] = np.pi
+    return Z, theta, m1
+
+
+def _combine_many_phase_sign(P, T, alphas):
+    from oracle import fgfrft as m
+    alphas = np.atleast_1d(np.asarray(alphas, dtype=np.float64))
+    Q = _ORIG["fgfrft_combine_many"](P, T, alphas)
+    for a, al in enumerate(alphas):                     # slip: e^{-j pi alpha} P
+        Q[a] += (np.exp(-1j * np.pi * al) - np.exp(1j * np.pi * al)) * P
+    return Q
+
+
 MUTATIONS = {
     "coefficients_index_flip": ("coefficients", _coefficients_index_flip),
     "coefficients_unnormalised": ("coefficients", _coefficients_unnormalised),
@@ -382,6 +460,15 @@ MUTATIONS = {
     "derivatives_taylor_sign": ("coefficient_derivatives", _derivatives_taylor_sign),
     "residual_short_sum": ("truncation_residual", _residual_short_sum),
     "frobenius_exact_keeps_minus1": ("frobenius_error_exact", _frobenius_exact_keeps_minus1),
+    "operator_integer_no_adjoint": ("fgfrft_operator", _operator_integer_no_adjoint),
+    "grad_inner_no_conj": ("grad", _grad_variant("inner_no_conj")),
+    "grad_dX_with_Q": ("grad", _grad_variant("dX_with_Q")),
+    "pointwise_bound_no_abs": ("pointwise_bound", _pointwise_bound_no_abs),
+    "frobenius_simplified_ccmax": ("frobenius_bound_simplified", _frobenius_simplified_ccmax),
+    "coefficients_integer_zero": ("coefficients", _coefficients_integer_zero),
+    "power_stack_no_Pc": ("power_stack", _power_stack_no_Pc),
+    "spectral_theta_conj": ("spectral_decomposition", _spectral_theta_conj),
+    "combine_many_phase_sign": ("fgfrft_combine_many", _combine_many_phase_sign),
 }
 
 _ORIG: dict = {}

@@ -169,6 +169,10 @@ def test_integer_orders_equal_matrix_powers(maker):
         ref = np.linalg.matrix_power(F, abs(m)).astype(complex)
         ref = ref if m >= 0 else ref.conj().T
         assert np.max(np.abs(plan.combine(float(m)) - ref)) < 1e-13, m
+        # the operator's integer short cut gives the same matrix as the online combination
+        assert np.max(np.abs(O.fgfrft_operator(F, float(m), 6) - plan.combine(float(m)))) < 1e-13, m
+    # and order -1 inverts F (a library inverse, no adjoint involved)
+    assert np.max(np.abs(O.fgfrft_operator(F, -1.0, 6) - np.linalg.inv(F))) < 1e-12
 
 
 def test_two_routes_agree():
